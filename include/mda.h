@@ -1,0 +1,201 @@
+/*
+ * mda.h -- C ABI of the MI355X multi-objective Digital Annealer (MDA) for the
+ * bi-objective quadratic assignment problem (bQAP).
+ *
+ * Method: Ayodele, Allmendinger, Lopez-Ibanez, Parizy, "Multi-objective QUBO
+ * Solver: Bi-objective Quadratic Assignment Problem", GECCO 2022
+ * (arXiv:2205.13399).  Section 2 defines the QUBO of the bQAP, Section 3.1 the
+ * parallel-trial annealing step (Algorithm 1, Eqs. cale and paccepts),
+ * Section 3.3 the multi-objective annealer (Algorithm 3, Eqs. wqubom,
+ * pacceptms, pacceptml) and its archive updates (Algorithms 4 and 5).
+ *
+ * Conventions shared by every call:
+ *  - Every function returns MDA_OK (0) or a negative MDA_E* code and never
+ *    aborts or throws across the ABI; mda_last_error() gives a thread-local
+ *    message for the last failure.
+ *  - Bit a = i*n + u of a solution means "facility i is at location u"
+ *    (row = facility, column = location, as in the worked example of Sec. 2.2).
+ *  - Host arrays passed in are owned by the caller and copied before return.
+ *    Handles are owned by the library and released with the matching *_free
+ *    (NULL is a no-op).  A run keeps its QUBO referenced: free runs first.
+ *  - Device memory is obtained through the allocator installed with
+ *    mda_set_allocator (default: hipMalloc / hipFree).  Work is enqueued on the
+ *    HIP stream given in the parameters; da_run returns before the device is
+ *    done, archive_get and da_state_get synchronise that stream.
+ *  - A handle is not thread-safe; distinct handles may be used from distinct
+ *    threads.  Runs sharing a stream execute in submission order.
+ */
+#ifndef MDA_H
+#define MDA_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    MDA_OK = 0,
+    MDA_EINVAL = -1,     /* bad argument (size, NULL pointer, unknown option) */
+    MDA_EOVERFLOW = -2,  /* a local field or threshold would not fit its integer type */
+    MDA_ENOMEM = -3,     /* host or device allocation failed */
+    MDA_EDEVICE = -4,    /* a HIP call failed */
+    MDA_ERANGE = -5,     /* output capacity too small (count holds the size needed) */
+    MDA_EBUSY = -6       /* the run is still referenced or in use */
+};
+
+/* Penalty weight alpha_k of the one-hot constraint QUBO G (Eq. wqubom). */
+enum { MDA_PEN_2MAX = 0,   /* alpha_k = 2 * max |C_k| (the benchmark setting) */
+       MDA_PEN_VL = 1 };   /* Eq. (vermap) on the symmetric form, alpha = ceil(w/2), Eq. (wvermaa) */
+
+/* How the local fields are updated after a flip. */
+enum { MDA_PATH_AUTO = 0,  /* dense when 8*m*m <= dense_budget, else Kronecker */
+       MDA_PATH_DENSE = 1, /* stream int32 rows of the symmetric P_1, P_2 from HBM */
+       MDA_PATH_KRON = 2 };/* regenerate the column from F_k, D and alpha_k */
+
+enum { MDA_STRICT = 0, MDA_LENIENT = 1 };        /* Eq. (pacceptms) / Eq. (pacceptml) */
+enum { MDA_EXPLORE = 0, MDA_EXPLOIT = 1 };       /* Algorithm 4 / Algorithm 5 */
+enum { MDA_ESC_OFFSET = 0,                       /* Algorithm 1: E_offset += beta when stuck */
+       MDA_ESC_ARCHIVE = 1 };                    /* Algorithm 3: restart from a random archive member */
+enum { MDA_VARIANT_AUTO = 0,                     /* persistent launch */
+       MDA_VARIANT_PERSISTENT = 1,               /* all steps in one launch, state on chip */
+       MDA_VARIANT_PLAIN = 2 };                  /* one launch per annealing step, state in HBM */
+
+typedef struct mda_qubo mda_qubo;  /* one bQAP instance: host copies + device operands */
+typedef struct mda_run mda_run;    /* one run: device replica state and archives */
+
+typedef struct {
+    int32_t penalty;       /* MDA_PEN_* */
+    int32_t path;          /* MDA_PATH_* */
+    int64_t dense_budget;  /* bytes for MDA_PATH_AUTO; <= 0 means 2 GiB */
+} mda_build_opts;
+
+typedef struct {
+    int32_t n, m;            /* facilities, bits (m = n*n) */
+    int32_t path;            /* MDA_PATH_DENSE or MDA_PATH_KRON as chosen */
+    int32_t symmetric;       /* 1 when D (or F1 and F2) is symmetric */
+    int64_t alpha1, alpha2;  /* penalty weights */
+    int64_t q1, q2;          /* constant terms alpha_k * 2n of Y and Z */
+    int64_t maxabs_c;        /* max(max|C_1|, max|C_2|) */
+    int64_t device_bytes;    /* device memory held by the handle */
+} mda_qubo_info;
+
+/*
+ * Builds the two penalised objective QUBOs of Eq. (wqubom) for one bQAP
+ * instance (Sec. 2.2-2.3): C_k from flows F_k and distances D (Eq. cqap), G
+ * from the two-way one-hot constraint (Eq. gqap), Y = C_1 + alpha_1 G,
+ * Z = C_2 + alpha_2 G, and uploads what the chosen update path needs.
+ *   n            2 <= n <= 100 (m = n*n <= 10000)
+ *   F1, F2, D    host, row-major n*n int32: F_k[i*n+j] flow from facility i to j
+ *                in objective k, D[u*n+v] distance from location u to v
+ *   opts         NULL for defaults (MDA_PEN_2MAX, MDA_PATH_AUTO, 2 GiB)
+ *   stream       hipStream_t for the uploads (NULL = default stream)
+ *   out          receives the handle
+ * Errors: MDA_EINVAL (bad n, NULL array), MDA_EOVERFLOW (some bit's
+ * |P_aa| + sum_b |P_ab| exceeds 2^31-1, so its local field would not fit
+ * int32), MDA_ENOMEM, MDA_EDEVICE.
+ */
+int qubo_build_bqap(int32_t n, const int32_t *F1, const int32_t *F2, const int32_t *D,
+                    const mda_build_opts *opts, void *stream, mda_qubo **out);
+int qubo_info(const mda_qubo *q, mda_qubo_info *info);
+void qubo_free(mda_qubo *q);
+
+typedef struct {
+    int32_t replicas;         /* independent annealing chains, >= 1 */
+    int32_t archive_size;     /* s; 0 = m (Table param) */
+    int64_t steps;            /* I_max, 1 <= steps < 2^32; 0 = 0.25 * m^2 (Table param) */
+    double delta0, deltaf, xi;/* geometric schedule; delta0 <= 0 selects 1e9*M/2^23, 1e4*M/2^23, 1e-3
+                                 where M = max|C| (the paper's values on coefficients scaled to 2^23) */
+    int64_t beta;             /* E_offset increment; < 0 selects max(1, floor(delta0/steps)) */
+    int32_t accept;           /* MDA_STRICT | MDA_LENIENT */
+    int32_t archive;          /* MDA_EXPLORE | MDA_EXPLOIT */
+    int32_t escape;           /* MDA_ESC_OFFSET | MDA_ESC_ARCHIVE */
+    int32_t variant;          /* MDA_VARIANT_* */
+    uint64_t seed;            /* Philox key of this run */
+    int32_t trace_replicas;   /* record the flipped bit of every step for replicas [0, k) */
+    int32_t waves_per_block;  /* launch shape hint; 0 = tuned default (results do not depend on it) */
+    void *stream;             /* hipStream_t; NULL = default stream */
+} mda_params;
+
+/* Fills p with the defaults of Table (param) and the benchmark settings. */
+void mda_params_default(mda_params *p);
+
+/*
+ * Runs Algorithm 3 (MDA) for p->replicas independent replicas of q: random
+ * start, per-step energy differences of both objectives for all m bits from
+ * maintained local fields, parallel acceptance with the dynamic offset,
+ * uniform choice of one accepted flip, field update, archive update.
+ * Asynchronous on p->stream.  Errors: MDA_EINVAL, MDA_EOVERFLOW (schedule
+ * threshold beyond 2^32-2), MDA_ENOMEM, MDA_EDEVICE.
+ */
+int da_run(const mda_qubo *q, const mda_params *p, mda_run **out);
+
+/*
+ * Runs several independent MDA runs (instances of any size, each with its own
+ * parameters and seed) in one persistent launch on ps[0].stream; each result is
+ * identical to the corresponding da_run.  outs receives one handle per run.
+ */
+int da_run_batch(const mda_qubo *const *qs, const mda_params *ps, int32_t count, mda_run **outs);
+
+/* Waits for the run's device work. */
+int da_sync(mda_run *r);
+
+/* Device time of the run's launch in milliseconds (HIP events; synchronises). */
+int da_elapsed_ms(mda_run *r, double *ms);
+
+typedef struct {
+    int64_t cap;          /* entries the arrays below can hold */
+    int64_t *e1, *e2;     /* energies E_1, E_2 (Eq. mqap) */
+    int32_t *replica;     /* replica the entry comes from */
+    int32_t *slot;        /* archive slot within that replica */
+    uint8_t *feasible;    /* 1 when x is a permutation matrix (g(x) = 0), may be NULL */
+    uint32_t *xbits;      /* cap * ceil(m/32) words, bit a of word a/32, may be NULL */
+    int32_t *perm;        /* cap * n, location of each facility (-1 if infeasible), may be NULL */
+} mda_archive_out;
+
+/*
+ * Copies archives to the host.  replica >= 0: that replica's archive; -1: the
+ * union over all replicas.  raw = 1: the ordered archive as stored (one replica
+ * only); raw = 0: its non-dominated entries (Sec. 3.3), equal-energy duplicates
+ * reduced to the lowest (replica, slot), sorted by (E1, E2, replica, slot).
+ * out == NULL is a size query.  *count receives the number of entries.
+ * Synchronises the run's stream.  Errors: MDA_EINVAL, MDA_ERANGE, MDA_EDEVICE.
+ */
+int archive_get(mda_run *r, int32_t replica, int32_t raw, mda_archive_out *out, int64_t *count);
+
+typedef struct {
+    uint8_t *x;             /* m bits, one byte each, may be NULL */
+    int32_t *h1, *h2;       /* local fields h_k[a] = sum_{b != a} P_k[a][b] x_b, may be NULL */
+    int64_t e1, e2;         /* energies of x */
+    int64_t e_offset;       /* current offset */
+    int64_t moves;          /* accepted flips */
+    int64_t scanned;        /* archive entries compared */
+    int64_t rng_blocks;     /* acceptance random blocks drawn */
+    int32_t *trace;         /* steps entries (bit index or -1), may be NULL; needs trace_replicas */
+} mda_state;
+
+/* Final state of one replica (synchronises). */
+int da_state_get(mda_run *r, int32_t replica, mda_state *st);
+
+/* Run statistics summed over replicas: moves, archive entries compared, random
+ * blocks drawn, total archive entries (synchronises). */
+int da_stats(mda_run *r, int64_t *moves, int64_t *scanned, int64_t *rng_blocks, int64_t *archived);
+
+void da_run_free(mda_run *r);
+
+/* Installs the device allocator (NULL alloc restores hipMalloc/hipFree). */
+typedef void *(*mda_alloc_fn)(size_t bytes, void *stream, void *ctx);
+typedef void (*mda_free_fn)(void *ptr, size_t bytes, void *stream, void *ctx);
+int mda_set_allocator(mda_alloc_fn alloc, mda_free_fn release, void *ctx);
+
+const char *mda_last_error(void);
+
+/* Debug/verification exports: the library's own host tables. */
+int mda_threshold_table(int32_t *lnt4096);
+int mda_temperature_table(double delta0, double deltaf, double xi, int64_t steps, int64_t *T);
+
+#ifdef __cplusplus
+}
+#endif
+#endif
