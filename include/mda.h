@@ -114,7 +114,7 @@ typedef struct {
     int32_t variant;          /* MDA_VARIANT_* */
     uint64_t seed;            /* Philox key of this run */
     int32_t trace_replicas;   /* record the flipped bit of every step for replicas [0, k) */
-    int32_t waves_per_block;  /* launch shape hint; 0 = tuned default (results do not depend on it) */
+    int32_t waves_per_block;  /* launch shape hint, 1..4 (larger is clamped); 0 = default; results do not depend on it */
     void *stream;             /* hipStream_t; NULL = default stream */
 } mda_params;
 

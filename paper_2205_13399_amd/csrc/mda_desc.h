@@ -1,0 +1,75 @@
+// mda_desc.h -- device-visible description of one annealing run and the work
+// items of a (batched) persistent launch.  Shared by the kernels and the host
+// library of the MI355X multi-objective Digital Annealer.
+#pragma once
+
+#include <stdint.h>
+
+namespace mda {
+
+// Counter word 3 of every Philox call names what the draw is for.
+enum : uint32_t { kTagAcc = 0, kTagSel = 1, kTagInit = 2, kTagArc = 3 };
+
+enum : int32_t { kPathDense = 1, kPathKron = 2 };
+enum : int32_t { kKronSym = 0, kKronGen = 1 };
+
+// Per-replica scalar statistics/state block (int64 words).
+enum : int32_t {
+    kStE1 = 0, kStE2 = 1, kStEoff = 2, kStMoves = 3, kStScanned = 4, kStRng = 5,
+    kStArch = 6, kStDetailed = 7, kStWords = 8
+};
+
+// Largest n of the one-replica-per-wave kernels (lane = location).
+constexpr int kMaxWaveN = 64;
+
+// Row stride of every per-lane operand on the device: rows of n entries are
+// padded with zeros to kLD, so lanes beyond n always read zero.
+constexpr int kLD = 64;
+
+struct RunDesc {
+    // problem
+    int32_t n, m;              // facilities, bits
+    int32_t s;                 // archive capacity
+    int32_t path;              // kPathDense | kPathKron
+    int32_t kform;             // kKronSym | kKronGen
+    int32_t accept, archive, escape;
+    int32_t two_alpha1, two_alpha2;
+    int32_t R;                 // replicas
+    int32_t trace_R;           // replicas [0, trace_R) record their flips
+    uint32_t key0, key1;       // Philox key
+    uint32_t steps;            // annealing steps
+    uint32_t ntab;             // temperature-table entries; T_t = T[min(t, ntab) - 1]
+    int32_t pad0;
+    int64_t beta;
+    int64_t q1, q2;
+    // schedule tables
+    const int64_t *T;          // fixed-point temperature, 8 fractional bits
+    const uint32_t *thrmax;    // (T * LNT[0]) >> 24
+    // Kronecker operands, n rows of kLD int32 (zero padded), row i' (or u'):
+    //   P_k[(i,u)][(i',u')] = KA_k[i'][i] * DA[u'][u] (+ KB_k[i'][i] * DB[u'][u])
+    //                         + 2 alpha_k [(i == i') != (u == u')]
+    const int32_t *KA1, *KA2, *KB1, *KB2, *DA, *DB;
+    // dense operands: symmetric P_k, m rows of n * kLD int32, entry (j, v) of
+    // row a at j * kLD + v
+    const int32_t *P1, *P2;
+    const int32_t *diag1, *diag2;   // d_k[(i,u)] = P_k[a][a] at i * kLD + u
+    // outputs and archives
+    uint64_t *x;               // [R][64] column masks: bit i of word u is x_{i,u}
+    int32_t *h;                // [R][2][m] local fields (canonical order)
+    int64_t *st;               // [R][kStWords]
+    int64_t *archE;            // [R][s][2]
+    uint64_t *archX;           // [R][s][n]
+    uint8_t *nd;               // [R][s] 1 = not dominated within its archive
+    int32_t *trace;            // [trace_R][steps]
+    // plain-form state (one launch per step)
+    int32_t *pe;               // [R][2][NS][64]
+    int32_t ns_plain;          // NS of the plain state layout
+    int32_t pad1;
+};
+
+struct WorkItem {
+    int32_t run;      // index into the RunDesc array
+    int32_t replica;
+};
+
+}  // namespace mda

@@ -1,0 +1,822 @@
+// mda_host.cpp -- C ABI of the MI355X multi-objective Digital Annealer
+// (declared and documented in include/mda.h).  Host side: QUBO operands of the
+// bi-objective QAP (Sec. 2 of Ayodele et al., GECCO 2022), the fixed-point
+// schedule and threshold tables, device memory, launches and result readout.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "mda.h"
+#include "mda_desc.h"
+
+namespace mda {
+int ns_for(int n);
+hipError_t launch_persistent(int ns, const RunDesc *runs, const WorkItem *work, int nwork, int *counter,
+                             const int32_t *lnt, int grid, int block, hipStream_t stream);
+hipError_t launch_plain(int ns, const RunDesc *run, int R, uint32_t steps, const int32_t *lnt, int block,
+                        hipStream_t stream);
+hipError_t launch_nondominated(const RunDesc *runs, const WorkItem *work, int nwork, hipStream_t stream);
+hipError_t launch_build_dense(int n, const int32_t *F, const int32_t *Dm, int32_t two_alpha, int32_t *P,
+                              hipStream_t stream);
+hipError_t persistent_occupancy(int ns, int block, int *blocks_per_cu);
+}  // namespace mda
+
+using namespace mda;
+
+// ---------------------------------------------------------------- errors
+
+static thread_local std::string g_err;
+
+static int fail(int code, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+#define HIP_TRY(expr)                                                                 \
+    do {                                                                              \
+        hipError_t e_ = (expr);                                                       \
+        if (e_ != hipSuccess)                                                         \
+            return fail(MDA_EDEVICE, "%s failed: %s", #expr, hipGetErrorString(e_)); \
+    } while (0)
+
+extern "C" const char *mda_last_error(void)
+{
+    return g_err.c_str();
+}
+
+// ---------------------------------------------------------------- device memory
+
+static mda_alloc_fn g_alloc = nullptr;
+static mda_free_fn g_release = nullptr;
+static void *g_ctx = nullptr;
+
+extern "C" int mda_set_allocator(mda_alloc_fn alloc, mda_free_fn release, void *ctx)
+{
+    if ((alloc == nullptr) != (release == nullptr)) return fail(MDA_EINVAL, "allocator and release must both be set");
+    g_alloc = alloc;
+    g_release = release;
+    g_ctx = ctx;
+    return MDA_OK;
+}
+
+namespace {
+
+struct DevBuf {
+    void *p = nullptr;
+    size_t bytes = 0;
+    hipStream_t stream = nullptr;
+    mda_free_fn release = nullptr;
+    void *ctx = nullptr;
+};
+
+struct DevPool {
+    std::vector<DevBuf> bufs;
+    int64_t total = 0;
+
+    template <class T>
+    T *alloc(size_t count, hipStream_t stream)
+    {
+        size_t bytes = count * sizeof(T);
+        if (bytes == 0) bytes = 256;
+        bytes = (bytes + 255) & ~(size_t)255;
+        void *p = nullptr;
+        DevBuf b;
+        if (g_alloc) {
+            p = g_alloc(bytes, (void *)stream, g_ctx);
+            b.release = g_release;
+            b.ctx = g_ctx;
+        } else if (hipMalloc(&p, bytes) != hipSuccess) {
+            p = nullptr;
+        }
+        if (!p) return nullptr;
+        b.p = p;
+        b.bytes = bytes;
+        b.stream = stream;
+        bufs.push_back(b);
+        total += (int64_t)bytes;
+        return static_cast<T *>(p);
+    }
+
+    void release_all()
+    {
+        for (auto &b : bufs) {
+            if (b.release) b.release(b.p, b.bytes, (void *)b.stream, b.ctx);
+            else (void)hipFree(b.p);
+        }
+        bufs.clear();
+        total = 0;
+    }
+};
+
+// Quantised -ln(u): LNT[k] = round(-ln((k + 1/2) / 4096) * 2^16).
+void threshold_table(int32_t *lnt)
+{
+    for (int k = 0; k < 4096; ++k) lnt[k] = (int32_t)std::llround(-std::log((k + 0.5) / 4096.0) * 65536.0);
+}
+
+// Geometric cooling evaluated at the top of every step; T_t = floor(256 delta_t).
+// Returns the number of entries until the temperature stops changing.
+int64_t temperature_table(double delta0, double deltaf, double xi, int64_t steps, std::vector<int64_t> &T)
+{
+    T.clear();
+    double delta = delta0;
+    for (int64_t t = 1; t <= steps; ++t) {
+        bool cooled = false;
+        if (delta > deltaf) {
+            delta = delta * (1.0 - xi);
+            cooled = true;
+        }
+        T.push_back((int64_t)std::floor(delta * 256.0));
+        if (!cooled && t > 1) break;   // constant from here on
+    }
+    return (int64_t)T.size();
+}
+
+}  // namespace
+
+extern "C" int mda_threshold_table(int32_t *lnt4096)
+{
+    if (!lnt4096) return fail(MDA_EINVAL, "null table");
+    threshold_table(lnt4096);
+    return MDA_OK;
+}
+
+extern "C" int mda_temperature_table(double delta0, double deltaf, double xi, int64_t steps, int64_t *T)
+{
+    if (!T || steps < 1) return fail(MDA_EINVAL, "bad arguments");
+    std::vector<int64_t> tab;
+    temperature_table(delta0, deltaf, xi, steps, tab);
+    for (int64_t t = 0; t < steps; ++t) T[t] = tab[std::min<int64_t>(t, (int64_t)tab.size() - 1)];
+    return MDA_OK;
+}
+
+// ---------------------------------------------------------------- QUBO handle
+
+struct mda_qubo {
+    int32_t n = 0, m = 0;
+    int32_t path = 0, kform = 0, symmetric = 0;
+    int64_t alpha[2] = {0, 0}, q[2] = {0, 0};
+    int64_t maxabs = 0;
+    std::vector<int32_t> F1, F2, D, diag1, diag2;
+    int32_t *dKA1 = nullptr, *dKA2 = nullptr, *dKB1 = nullptr, *dKB2 = nullptr, *dDA = nullptr, *dDB = nullptr;
+    int32_t *dP1 = nullptr, *dP2 = nullptr, *ddiag1 = nullptr, *ddiag2 = nullptr;
+    DevPool pool;
+    int refs = 1;   // the owner plus every run that uses it
+};
+
+static void qubo_release(mda_qubo *q)
+{
+    if (--q->refs == 0) {
+        (void)hipDeviceSynchronize();
+        q->pool.release_all();
+        delete q;
+    }
+}
+
+static bool is_symmetric(const std::vector<int32_t> &A, int n)
+{
+    for (int i = 0; i < n; ++i)
+        for (int j = i + 1; j < n; ++j)
+            if (A[i * n + j] != A[j * n + i]) return false;
+    return true;
+}
+
+// Entry (a, b), a <= b, of the upper-triangular cost QUBO C (Sec. 2.2).
+static inline int64_t cost_upper(const int32_t *F, const int32_t *Dm, int n, int a, int b)
+{
+    const int i = a / n, u = a % n, j = b / n, v = b % n;
+    if (a == b) return (int64_t)F[i * n + i] * Dm[u * n + u];
+    return (int64_t)F[i * n + j] * Dm[u * n + v] + (int64_t)F[j * n + i] * Dm[v * n + u];
+}
+
+extern "C" int qubo_build_bqap(int32_t n, const int32_t *F1, const int32_t *F2, const int32_t *D,
+                               const mda_build_opts *opts, void *stream_, mda_qubo **out)
+{
+    if (!out) return fail(MDA_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (n < 2 || n > 100) return fail(MDA_EINVAL, "n = %d outside [2, 100]", n);
+    if (!F1 || !F2 || !D) return fail(MDA_EINVAL, "F1, F2 and D must be non-NULL");
+    mda_build_opts o{MDA_PEN_2MAX, MDA_PATH_AUTO, 0};
+    if (opts) o = *opts;
+    if (o.penalty != MDA_PEN_2MAX && o.penalty != MDA_PEN_VL) return fail(MDA_EINVAL, "unknown penalty %d", o.penalty);
+    if (o.path < MDA_PATH_AUTO || o.path > MDA_PATH_KRON) return fail(MDA_EINVAL, "unknown path %d", o.path);
+    if (n > kMaxWaveN) return fail(MDA_EINVAL, "n = %d: this build anneals n <= %d", n, kMaxWaveN);
+    const int64_t budget = o.dense_budget > 0 ? o.dense_budget : (int64_t)2 << 30;
+    hipStream_t stream = (hipStream_t)stream_;
+
+    std::unique_ptr<mda_qubo> q(new mda_qubo);
+    const int m = n * n;
+    q->n = n;
+    q->m = m;
+    const size_t nn = (size_t)n * n;
+    q->F1.assign(F1, F1 + nn);
+    q->F2.assign(F2, F2 + nn);
+    q->D.assign(D, D + nn);
+    const int32_t *Fk[2] = {q->F1.data(), q->F2.data()};
+    const int32_t *Dm = q->D.data();
+
+    // Penalty weights (Eq. wqubom): 2 max|C_k|, or Eq. (vermap)/(wvermaa) on the
+    // symmetric form of C_k.
+    for (int k = 0; k < 2; ++k) {
+        int64_t mx = 0;
+        for (int a = 0; a < m; ++a)
+            for (int b = a; b < m; ++b) mx = std::max<int64_t>(mx, std::llabs(cost_upper(Fk[k], Dm, n, a, b)));
+        q->maxabs = std::max(q->maxabs, mx);
+        int64_t alpha = 2 * mx;
+        if (o.penalty == MDA_PEN_VL) {
+            int64_t w = INT64_MIN;
+            for (int a = 0; a < m; ++a) {
+                const int64_t caa = cost_upper(Fk[k], Dm, n, a, a);
+                int64_t neg = -caa, pos = caa;
+                for (int b = 0; b < m; ++b) {
+                    if (b == a) continue;
+                    const int64_t v = cost_upper(Fk[k], Dm, n, std::min(a, b), std::max(a, b));
+                    if (v < 0) neg -= v;
+                    if (v > 0) pos += v;
+                }
+                w = std::max(w, std::max(neg, pos));
+            }
+            alpha = (w + 1) / 2;
+        }
+        q->alpha[k] = alpha;
+        q->q[k] = alpha * 2 * n;
+        if (2 * alpha * n >= (int64_t)1 << 29)
+            return fail(MDA_EOVERFLOW, "penalty 2*alpha_%d*n = %lld exceeds 2^29", k + 1, (long long)(2 * alpha * n));
+        // Every local field |P_aa + sum_b P_ab x_b| must fit int32.
+        for (int a = 0; a < m; ++a) {
+            const int i = a / n, u = a % n;
+            int64_t s = std::llabs(cost_upper(Fk[k], Dm, n, a, a) - 2 * alpha);
+            for (int b = 0; b < m; ++b) {
+                if (b == a) continue;
+                const int j = b / n, v = b % n;
+                int64_t p = cost_upper(Fk[k], Dm, n, std::min(a, b), std::max(a, b));
+                if ((i == j) != (u == v)) p += 2 * alpha;
+                s += std::llabs(p);
+            }
+            if (s > INT32_MAX - 1)
+                return fail(MDA_EOVERFLOW, "objective %d: bit %d has sum |P_ab| = %lld > 2^31-2", k + 1, a, (long long)s);
+        }
+    }
+    q->diag1.resize(m);
+    q->diag2.resize(m);
+    for (int a = 0; a < m; ++a) {
+        q->diag1[a] = (int32_t)(cost_upper(Fk[0], Dm, n, a, a) - 2 * q->alpha[0]);
+        q->diag2[a] = (int32_t)(cost_upper(Fk[1], Dm, n, a, a) - 2 * q->alpha[1]);
+    }
+
+    // Kronecker operands.
+    const bool dsym = is_symmetric(q->D, n);
+    const bool fsym = is_symmetric(q->F1, n) && is_symmetric(q->F2, n);
+    q->symmetric = (dsym || fsym) ? 1 : 0;
+    std::vector<int32_t> KA[2], KB[2], DA, DB;
+    int64_t maxop = 0;
+    auto track = [&](const std::vector<int32_t> &v) {
+        for (int32_t e : v) maxop = std::max<int64_t>(maxop, std::llabs((int64_t)e));
+    };
+    if (dsym || fsym) {
+        q->kform = kKronSym;
+        for (int k = 0; k < 2; ++k) {
+            KA[k].resize(nn);
+            for (int a = 0; a < n; ++a)
+                for (int b = 0; b < n; ++b)
+                    KA[k][a * n + b] = dsym ? Fk[k][a * n + b] + Fk[k][b * n + a] : Fk[k][a * n + b];
+            track(KA[k]);
+        }
+        DA.resize(nn);
+        for (int a = 0; a < n; ++a)
+            for (int b = 0; b < n; ++b) DA[a * n + b] = dsym ? Dm[a * n + b] : Dm[a * n + b] + Dm[b * n + a];
+        track(DA);
+    } else {
+        q->kform = kKronGen;
+        for (int k = 0; k < 2; ++k) {
+            KA[k].resize(nn);
+            KB[k].assign(Fk[k], Fk[k] + nn);
+            for (int a = 0; a < n; ++a)
+                for (int b = 0; b < n; ++b) KA[k][a * n + b] = Fk[k][b * n + a];
+            track(KA[k]);
+            track(KB[k]);
+        }
+        DA.resize(nn);
+        DB.assign(Dm, Dm + nn);
+        for (int a = 0; a < n; ++a)
+            for (int b = 0; b < n; ++b) DA[a * n + b] = Dm[b * n + a];
+        track(DA);
+    }
+    const bool kron_ok = maxop < (1 << 23);   // 24-bit multiply-adds
+    const bool dense_fits = 8 * (int64_t)m * n * kLD <= budget;
+    if (o.path == MDA_PATH_KRON) {
+        if (!kron_ok) return fail(MDA_EOVERFLOW, "Kronecker operands exceed the 24-bit multiplier range");
+        q->path = kPathKron;
+    } else if (o.path == MDA_PATH_DENSE) {
+        q->path = kPathDense;
+    } else {
+        q->path = (dense_fits || !kron_ok) ? kPathDense : kPathKron;
+    }
+
+    // Uploads.  Per-lane operands go up as n rows of kLD entries, zero padded.
+    auto up = [&](const std::vector<int32_t> &h) -> int32_t * {
+        int32_t *d = q->pool.alloc<int32_t>(h.size(), stream);
+        if (d && hipMemcpyAsync(d, h.data(), h.size() * sizeof(int32_t), hipMemcpyHostToDevice, stream) != hipSuccess)
+            return nullptr;
+        return d;
+    };
+    auto pad = [&](const std::vector<int32_t> &h, int rows) {
+        std::vector<int32_t> o((size_t)rows * kLD, 0);
+        for (int a = 0; a < n; ++a)
+            for (int b = 0; b < n; ++b) o[(size_t)a * kLD + b] = h[(size_t)a * n + b];
+        return o;
+    };
+    // the diagonal is read for every register slot (up to kMaxWaveN rows)
+    q->ddiag1 = up(pad(q->diag1, kMaxWaveN));
+    q->ddiag2 = up(pad(q->diag2, kMaxWaveN));
+    if (!q->ddiag1 || !q->ddiag2) return fail(MDA_ENOMEM, "device allocation failed");
+    if (q->path == kPathKron) {
+        q->dKA1 = up(pad(KA[0], n));
+        q->dKA2 = up(pad(KA[1], n));
+        q->dDA = up(pad(DA, n));
+        if (!q->dKA1 || !q->dKA2 || !q->dDA) return fail(MDA_ENOMEM, "device allocation failed");
+        if (q->kform == kKronGen) {
+            q->dKB1 = up(pad(KB[0], n));
+            q->dKB2 = up(pad(KB[1], n));
+            q->dDB = up(pad(DB, n));
+            if (!q->dKB1 || !q->dKB2 || !q->dDB) return fail(MDA_ENOMEM, "device allocation failed");
+        } else {
+            q->dKB1 = q->dKA1;
+            q->dKB2 = q->dKA2;
+            q->dDB = q->dDA;
+        }
+    } else {
+        int32_t *dF1 = up(q->F1), *dF2 = up(q->F2), *dD = up(q->D);
+        q->dP1 = q->pool.alloc<int32_t>((size_t)m * n * kLD, stream);
+        q->dP2 = q->pool.alloc<int32_t>((size_t)m * n * kLD, stream);
+        if (!dF1 || !dF2 || !dD || !q->dP1 || !q->dP2) return fail(MDA_ENOMEM, "device allocation failed");
+        HIP_TRY(launch_build_dense(n, dF1, dD, (int32_t)(2 * q->alpha[0]), q->dP1, stream));
+        HIP_TRY(launch_build_dense(n, dF2, dD, (int32_t)(2 * q->alpha[1]), q->dP2, stream));
+        q->dKA1 = q->dKA2 = q->dKB1 = q->dKB2 = q->dDA = q->dDB = dF1;   // unused on this path
+    }
+    HIP_TRY(hipStreamSynchronize(stream));
+    *out = q.release();
+    return MDA_OK;
+}
+
+extern "C" int qubo_info(const mda_qubo *q, mda_qubo_info *info)
+{
+    if (!q || !info) return fail(MDA_EINVAL, "NULL argument");
+    info->n = q->n;
+    info->m = q->m;
+    info->path = q->path == kPathDense ? MDA_PATH_DENSE : MDA_PATH_KRON;
+    info->symmetric = q->symmetric;
+    info->alpha1 = q->alpha[0];
+    info->alpha2 = q->alpha[1];
+    info->q1 = q->q[0];
+    info->q2 = q->q[1];
+    info->maxabs_c = q->maxabs;
+    info->device_bytes = q->pool.total;
+    return MDA_OK;
+}
+
+extern "C" void qubo_free(mda_qubo *q)
+{
+    if (q) qubo_release(q);
+}
+
+// ---------------------------------------------------------------- runs
+
+namespace {
+
+// Device resources of one launch, shared by the runs it contains.
+struct Launch {
+    DevPool pool;
+    RunDesc *ddesc = nullptr;
+    WorkItem *dwork = nullptr;
+    int nwork = 0;
+    int *dcounter = nullptr;
+    int32_t *dlnt = nullptr;
+    hipStream_t stream = nullptr;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    ~Launch()
+    {
+        if (stream || ev0) (void)hipStreamSynchronize(stream);
+        if (ev0) (void)hipEventDestroy(ev0);
+        if (ev1) (void)hipEventDestroy(ev1);
+        pool.release_all();
+    }
+};
+
+}  // namespace
+
+struct mda_run {
+    mda_qubo *q = nullptr;
+    mda_params p{};
+    RunDesc h{};                       // host copy of this run's descriptor
+    std::shared_ptr<Launch> launch;
+    DevPool pool;                      // this run's outputs and tables
+    ~mda_run()
+    {
+        if (launch) (void)hipStreamSynchronize(launch->stream);
+        pool.release_all();
+        launch.reset();
+        if (q) qubo_release(q);
+    }
+};
+
+extern "C" void mda_params_default(mda_params *p)
+{
+    if (!p) return;
+    std::memset(p, 0, sizeof *p);
+    p->replicas = 1;
+    p->archive_size = 0;
+    p->steps = 0;
+    p->delta0 = 0.0;
+    p->deltaf = 0.0;
+    p->xi = 0.001;
+    p->beta = -1;
+    p->accept = MDA_STRICT;
+    p->archive = MDA_EXPLORE;
+    p->escape = MDA_ESC_OFFSET;
+    p->variant = MDA_VARIANT_AUTO;
+}
+
+static int prepare_run(mda_qubo *q, const mda_params *pin, hipStream_t stream, mda_run **out)
+{
+    mda_params p = *pin;
+    if (p.replicas < 1) return fail(MDA_EINVAL, "replicas = %d", p.replicas);
+    if (p.steps == 0) p.steps = (int64_t)std::llround(0.25 * (double)q->m * (double)q->m);
+    if (p.steps < 1 || p.steps > 0xFFFFFFFFLL) return fail(MDA_EINVAL, "steps = %lld", (long long)p.steps);
+    if (p.accept != MDA_STRICT && p.accept != MDA_LENIENT) return fail(MDA_EINVAL, "accept = %d", p.accept);
+    if (p.archive != MDA_EXPLORE && p.archive != MDA_EXPLOIT) return fail(MDA_EINVAL, "archive = %d", p.archive);
+    if (p.escape != MDA_ESC_OFFSET && p.escape != MDA_ESC_ARCHIVE) return fail(MDA_EINVAL, "escape = %d", p.escape);
+    if (p.archive_size < 0) return fail(MDA_EINVAL, "archive_size = %d", p.archive_size);
+    if (p.trace_replicas < 0 || p.trace_replicas > p.replicas) return fail(MDA_EINVAL, "trace_replicas = %d", p.trace_replicas);
+    if (p.delta0 <= 0.0) {
+        p.delta0 = 1e9 * (double)q->maxabs / 8388608.0;
+        p.deltaf = 1e4 * (double)q->maxabs / 8388608.0;
+        if (p.xi <= 0.0) p.xi = 0.001;
+    }
+    if (!(p.xi >= 0.0 && p.xi < 1.0)) return fail(MDA_EINVAL, "xi = %g", p.xi);
+    if (p.beta < 0) p.beta = std::max<int64_t>(1, (int64_t)std::floor(p.delta0 / (double)p.steps));
+
+    std::vector<int64_t> T;
+    temperature_table(p.delta0, p.deltaf, p.xi, p.steps, T);
+    int32_t lnt[4096];
+    threshold_table(lnt);
+    std::vector<uint32_t> thrmax(T.size());
+    for (size_t t = 0; t < T.size(); ++t) {
+        if (T[t] < 0 || T[t] > ((int64_t)1 << 43)) return fail(MDA_EOVERFLOW, "temperature %lld out of range", (long long)T[t]);
+        const uint64_t v = ((uint64_t)T[t] * (uint64_t)lnt[0]) >> 24;
+        if (v > 0xFFFFFFFEull) return fail(MDA_EOVERFLOW, "largest acceptance threshold %llu exceeds 2^32-2 (delta0 too large)", (unsigned long long)v);
+        thrmax[t] = (uint32_t)v;
+    }
+
+    std::unique_ptr<mda_run> r(new mda_run);
+    r->p = p;
+    const int n = q->n, m = q->m, R = p.replicas;
+    const int s = p.archive_size > 0 ? p.archive_size : m;
+    RunDesc &d = r->h;
+    std::memset(&d, 0, sizeof d);
+    d.n = n;
+    d.m = m;
+    d.s = s;
+    d.path = q->path;
+    d.kform = q->kform;
+    d.accept = p.accept;
+    d.archive = p.archive;
+    d.escape = p.escape;
+    d.two_alpha1 = (int32_t)(2 * q->alpha[0]);
+    d.two_alpha2 = (int32_t)(2 * q->alpha[1]);
+    d.R = R;
+    d.trace_R = p.trace_replicas;
+    d.key0 = (uint32_t)p.seed;
+    d.key1 = (uint32_t)(p.seed >> 32);
+    d.steps = (uint32_t)p.steps;
+    d.ntab = (uint32_t)T.size();
+    d.beta = p.beta;
+    d.q1 = q->q[0];
+    d.q2 = q->q[1];
+    d.KA1 = q->dKA1; d.KA2 = q->dKA2; d.KB1 = q->dKB1; d.KB2 = q->dKB2; d.DA = q->dDA; d.DB = q->dDB;
+    d.P1 = q->dP1; d.P2 = q->dP2;
+    d.diag1 = q->ddiag1; d.diag2 = q->ddiag2;
+
+    DevPool &pool = r->pool;
+    int64_t *dT = pool.alloc<int64_t>(T.size(), stream);
+    uint32_t *dthr = pool.alloc<uint32_t>(T.size(), stream);
+    d.x = pool.alloc<uint64_t>((size_t)R * 64, stream);
+    d.h = pool.alloc<int32_t>((size_t)R * 2 * m, stream);
+    d.st = pool.alloc<int64_t>((size_t)R * kStWords, stream);
+    d.archE = pool.alloc<int64_t>((size_t)R * s * 2, stream);
+    d.archX = pool.alloc<uint64_t>((size_t)R * s * n, stream);
+    d.nd = pool.alloc<uint8_t>((size_t)R * s, stream);
+    d.trace = pool.alloc<int32_t>((size_t)std::max(1, p.trace_replicas) * (size_t)(p.trace_replicas ? p.steps : 1), stream);
+    const int ns = ns_for(n);
+    d.ns_plain = ns;
+    if (p.variant == MDA_VARIANT_PLAIN) d.pe = pool.alloc<int32_t>((size_t)R * 2 * ns * 64, stream);
+    if (!dT || !dthr || !d.x || !d.h || !d.st || !d.archE || !d.archX || !d.nd || !d.trace ||
+        (p.variant == MDA_VARIANT_PLAIN && !d.pe))
+        return fail(MDA_ENOMEM, "device allocation failed for the run (%lld bytes so far)", (long long)pool.total);
+    HIP_TRY(hipMemcpyAsync(dT, T.data(), T.size() * sizeof(int64_t), hipMemcpyHostToDevice, stream));
+    HIP_TRY(hipMemcpyAsync(dthr, thrmax.data(), thrmax.size() * sizeof(uint32_t), hipMemcpyHostToDevice, stream));
+    HIP_TRY(hipMemsetAsync(d.nd, 0, (size_t)R * s, stream));
+    d.T = dT;
+    d.thrmax = dthr;
+    q->refs++;
+    r->q = q;
+    *out = r.release();
+    return MDA_OK;
+}
+
+// Threads per block: 1 to 4 waves (the kernels are built for at most 256).
+static int default_block(int wpb)
+{
+    if (wpb <= 0) wpb = 4;
+    if (wpb > 4) wpb = 4;
+    return 64 * wpb;
+}
+
+extern "C" int da_run_batch(const mda_qubo *const *qs, const mda_params *ps, int32_t count, mda_run **outs)
+{
+    if (!qs || !ps || !outs || count < 1) return fail(MDA_EINVAL, "bad batch arguments");
+    for (int i = 0; i < count; ++i) outs[i] = nullptr;
+    hipStream_t stream = (hipStream_t)ps[0].stream;
+    {
+        // an error left by earlier asynchronous work is reported as such
+        const hipError_t pending = hipGetLastError();
+        if (pending != hipSuccess)
+            return fail(MDA_EDEVICE, "pending device error before the launch: %s", hipGetErrorString(pending));
+    }
+    const bool plain = ps[0].variant == MDA_VARIANT_PLAIN;
+    if (plain && count != 1) return fail(MDA_EINVAL, "the plain form runs one instance per call");
+    std::vector<std::unique_ptr<mda_run>> runs;
+    for (int i = 0; i < count; ++i) {
+        if (!qs[i]) return fail(MDA_EINVAL, "qubo %d is NULL", i);
+        if (ps[i].stream != ps[0].stream) return fail(MDA_EINVAL, "all runs of a batch share one stream");
+        if ((ps[i].variant == MDA_VARIANT_PLAIN) != plain) return fail(MDA_EINVAL, "mixed variants in a batch");
+        mda_run *r = nullptr;
+        const int rc = prepare_run(const_cast<mda_qubo *>(qs[i]), &ps[i], stream, &r);
+        if (rc) return rc;
+        runs.emplace_back(r);
+    }
+    auto L = std::make_shared<Launch>();
+    L->stream = stream;
+    int ns = 8;
+    std::vector<RunDesc> descs;
+    std::vector<WorkItem> work;
+    for (int i = 0; i < count; ++i) {
+        descs.push_back(runs[i]->h);
+        ns = std::max(ns, ns_for(runs[i]->h.n));
+    }
+    // Work list, largest instances first (uneven sizes pack better).
+    std::vector<int> order(count);
+    for (int i = 0; i < count; ++i) order[i] = i;
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+        return (int64_t)descs[a].m * descs[a].steps > (int64_t)descs[b].m * descs[b].steps;
+    });
+    for (int i : order)
+        for (int rr = 0; rr < descs[i].R; ++rr) work.push_back(WorkItem{i, rr});
+    L->nwork = (int)work.size();
+    L->ddesc = L->pool.alloc<RunDesc>(descs.size(), stream);
+    L->dwork = L->pool.alloc<WorkItem>(work.size(), stream);
+    L->dcounter = L->pool.alloc<int>(1, stream);
+    L->dlnt = L->pool.alloc<int32_t>(4096, stream);
+    if (!L->ddesc || !L->dwork || !L->dcounter || !L->dlnt) return fail(MDA_ENOMEM, "device allocation failed");
+    int32_t lnt[4096];
+    threshold_table(lnt);
+    HIP_TRY(hipMemcpyAsync(L->ddesc, descs.data(), descs.size() * sizeof(RunDesc), hipMemcpyHostToDevice, stream));
+    HIP_TRY(hipMemcpyAsync(L->dwork, work.data(), work.size() * sizeof(WorkItem), hipMemcpyHostToDevice, stream));
+    HIP_TRY(hipMemcpyAsync(L->dlnt, lnt, sizeof lnt, hipMemcpyHostToDevice, stream));
+    HIP_TRY(hipEventCreate(&L->ev0));
+    HIP_TRY(hipEventCreate(&L->ev1));
+    const int block = default_block(ps[0].waves_per_block);
+    HIP_TRY(hipEventRecord(L->ev0, stream));
+    if (plain) {
+        HIP_TRY(launch_plain(ns, L->ddesc, descs[0].R, descs[0].steps, L->dlnt, block, stream));
+    } else {
+        int dev = 0, cus = 0, per_cu = 0;
+        HIP_TRY(hipGetDevice(&dev));
+        HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+        HIP_TRY(persistent_occupancy(ns, block, &per_cu));
+        if (per_cu < 1) per_cu = 1;
+        const int wpb = block / 64;
+        int grid = cus * per_cu;
+        const int need = (L->nwork + wpb - 1) / wpb;
+        if (grid > need) grid = need;
+        const hipError_t le = launch_persistent(ns, L->ddesc, L->dwork, L->nwork, L->dcounter, L->dlnt, grid, block, stream);
+        if (le != hipSuccess)
+            return fail(MDA_EDEVICE, "persistent launch (ns %d, grid %d, block %d, %d blocks/CU) failed: %s", ns, grid,
+                        block, per_cu, hipGetErrorString(le));
+    }
+    HIP_TRY(launch_nondominated(L->ddesc, L->dwork, L->nwork, stream));
+    HIP_TRY(hipEventRecord(L->ev1, stream));
+    for (int i = 0; i < count; ++i) {
+        runs[i]->launch = L;
+        outs[i] = runs[i].release();
+    }
+    return MDA_OK;
+}
+
+extern "C" int da_run(const mda_qubo *q, const mda_params *p, mda_run **out)
+{
+    if (!out) return fail(MDA_EINVAL, "out is NULL");
+    if (!q || !p) return fail(MDA_EINVAL, "NULL argument");
+    return da_run_batch(&q, p, 1, out);
+}
+
+extern "C" int da_sync(mda_run *r)
+{
+    if (!r || !r->launch) return fail(MDA_EINVAL, "NULL run");
+    HIP_TRY(hipStreamSynchronize(r->launch->stream));
+    return MDA_OK;
+}
+
+extern "C" int da_elapsed_ms(mda_run *r, double *ms)
+{
+    if (!r || !r->launch || !ms) return fail(MDA_EINVAL, "NULL argument");
+    HIP_TRY(hipEventSynchronize(r->launch->ev1));
+    float f = 0.f;
+    HIP_TRY(hipEventElapsedTime(&f, r->launch->ev0, r->launch->ev1));
+    *ms = f;
+    return MDA_OK;
+}
+
+extern "C" void da_run_free(mda_run *r)
+{
+    delete r;
+}
+
+// ---------------------------------------------------------------- readout
+
+namespace {
+
+struct Entry {
+    int64_t e1, e2;
+    int32_t replica, slot;
+};
+
+}  // namespace
+
+static int copy_d2h(void *dst, const void *src, size_t bytes, hipStream_t s)
+{
+    HIP_TRY(hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    return MDA_OK;
+}
+
+extern "C" int da_stats(mda_run *r, int64_t *moves, int64_t *scanned, int64_t *rng_blocks, int64_t *archived)
+{
+    if (!r) return fail(MDA_EINVAL, "NULL run");
+    const RunDesc &d = r->h;
+    std::vector<int64_t> st((size_t)d.R * kStWords);
+    int rc = copy_d2h(st.data(), d.st, st.size() * sizeof(int64_t), r->launch->stream);
+    if (rc) return rc;
+    int64_t mv = 0, sc = 0, rb = 0, ar = 0;
+    for (int i = 0; i < d.R; ++i) {
+        mv += st[(size_t)i * kStWords + kStMoves];
+        sc += st[(size_t)i * kStWords + kStScanned];
+        rb += st[(size_t)i * kStWords + kStRng];
+        ar += st[(size_t)i * kStWords + kStArch];
+    }
+    if (moves) *moves = mv;
+    if (scanned) *scanned = sc;
+    if (rng_blocks) *rng_blocks = rb;
+    if (archived) *archived = ar;
+    return MDA_OK;
+}
+
+extern "C" int da_state_get(mda_run *r, int32_t replica, mda_state *out)
+{
+    if (!r || !out) return fail(MDA_EINVAL, "NULL argument");
+    const RunDesc &d = r->h;
+    if (replica < 0 || replica >= d.R) return fail(MDA_EINVAL, "replica %d outside [0, %d)", replica, d.R);
+    hipStream_t s = r->launch->stream;
+    int64_t st[kStWords];
+    int rc = copy_d2h(st, d.st + (size_t)replica * kStWords, sizeof st, s);
+    if (rc) return rc;
+    out->e1 = st[kStE1];
+    out->e2 = st[kStE2];
+    out->e_offset = st[kStEoff];
+    out->moves = st[kStMoves];
+    out->scanned = st[kStScanned];
+    out->rng_blocks = st[kStRng];
+    const int n = d.n, m = d.m;
+    if (out->x) {
+        uint64_t cols[64];
+        rc = copy_d2h(cols, d.x + (size_t)replica * 64, sizeof cols, s);
+        if (rc) return rc;
+        for (int i = 0; i < n; ++i)
+            for (int u = 0; u < n; ++u) out->x[i * n + u] = (uint8_t)((cols[u] >> i) & 1ull);
+    }
+    if (out->h1 && (rc = copy_d2h(out->h1, d.h + (size_t)replica * 2 * m, (size_t)m * 4, s))) return rc;
+    if (out->h2 && (rc = copy_d2h(out->h2, d.h + (size_t)replica * 2 * m + m, (size_t)m * 4, s))) return rc;
+    if (out->trace) {
+        if (replica >= d.trace_R) return fail(MDA_EINVAL, "replica %d was not traced", replica);
+        rc = copy_d2h(out->trace, d.trace + (size_t)replica * d.steps, (size_t)d.steps * 4, s);
+        if (rc) return rc;
+    }
+    return MDA_OK;
+}
+
+extern "C" int archive_get(mda_run *r, int32_t replica, int32_t raw, mda_archive_out *out, int64_t *count)
+{
+    if (!r || !count) return fail(MDA_EINVAL, "NULL argument");
+    const RunDesc &d = r->h;
+    if (replica < -1 || replica >= d.R) return fail(MDA_EINVAL, "replica %d outside [-1, %d)", replica, d.R);
+    if (raw && replica < 0) return fail(MDA_EINVAL, "the raw archive is per replica");
+    hipStream_t s = r->launch->stream;
+    const int n = d.n, m = d.m, S = d.s;
+    const int r0 = replica < 0 ? 0 : replica, r1 = replica < 0 ? d.R : replica + 1;
+    const int nr = r1 - r0;
+    std::vector<int64_t> st((size_t)nr * kStWords);
+    int rc = copy_d2h(st.data(), d.st + (size_t)r0 * kStWords, st.size() * sizeof(int64_t), s);
+    if (rc) return rc;
+    std::vector<int64_t> E((size_t)nr * S * 2);
+    rc = copy_d2h(E.data(), d.archE + (size_t)r0 * S * 2, E.size() * sizeof(int64_t), s);
+    if (rc) return rc;
+    std::vector<uint8_t> nd((size_t)nr * S);
+    rc = copy_d2h(nd.data(), d.nd + (size_t)r0 * S, nd.size(), s);
+    if (rc) return rc;
+
+    std::vector<Entry> ent;
+    for (int k = 0; k < nr; ++k) {
+        const int asz = (int)st[(size_t)k * kStWords + kStArch];
+        for (int e = 0; e < asz; ++e) {
+            if (!raw && !nd[(size_t)k * S + e]) continue;
+            ent.push_back(Entry{E[((size_t)k * S + e) * 2], E[((size_t)k * S + e) * 2 + 1], r0 + k, e});
+        }
+    }
+    if (!raw) {
+        // Non-dominated union (Sec. 3.3), duplicates reduced to the lowest (replica, slot).
+        std::sort(ent.begin(), ent.end(), [](const Entry &a, const Entry &b) {
+            if (a.e1 != b.e1) return a.e1 < b.e1;
+            if (a.e2 != b.e2) return a.e2 < b.e2;
+            if (a.replica != b.replica) return a.replica < b.replica;
+            return a.slot < b.slot;
+        });
+        std::vector<Entry> keep;
+        int64_t best2 = INT64_MAX;
+        for (const Entry &e : ent) {
+            if (e.e2 < best2) {
+                keep.push_back(e);
+                best2 = e.e2;
+            }
+        }
+        ent.swap(keep);
+    }
+    *count = (int64_t)ent.size();
+    if (!out) return MDA_OK;
+    if (out->cap < (int64_t)ent.size()) return fail(MDA_ERANGE, "capacity %lld < %lld entries", (long long)out->cap, (long long)ent.size());
+    const int words = (m + 31) / 32;
+    std::vector<uint64_t> cols((size_t)n);
+    for (size_t k = 0; k < ent.size(); ++k) {
+        const Entry &e = ent[k];
+        if (out->e1) out->e1[k] = e.e1;
+        if (out->e2) out->e2[k] = e.e2;
+        if (out->replica) out->replica[k] = e.replica;
+        if (out->slot) out->slot[k] = e.slot;
+        if (out->xbits || out->perm || out->feasible) {
+            rc = copy_d2h(cols.data(), d.archX + ((size_t)e.replica * S + e.slot) * n, (size_t)n * 8, s);
+            if (rc) return rc;
+            bool feas = true;
+            std::vector<int> perm(n, -1);
+            std::vector<int> colsum(n, 0);
+            for (int i = 0; i < n; ++i) {
+                int cnt = 0;
+                for (int u = 0; u < n; ++u) {
+                    if ((cols[u] >> i) & 1ull) {
+                        ++cnt;
+                        ++colsum[u];
+                        perm[i] = u;
+                    }
+                }
+                if (cnt != 1) feas = false;
+            }
+            for (int u = 0; u < n; ++u)
+                if (colsum[u] != 1) feas = false;
+            if (out->feasible) out->feasible[k] = feas ? 1 : 0;
+            if (out->perm)
+                for (int i = 0; i < n; ++i) out->perm[k * n + i] = feas ? perm[i] : -1;
+            if (out->xbits) {
+                uint32_t *w = out->xbits + k * words;
+                std::memset(w, 0, (size_t)words * 4);
+                for (int i = 0; i < n; ++i)
+                    for (int u = 0; u < n; ++u)
+                        if ((cols[u] >> i) & 1ull) {
+                            const int a = i * n + u;
+                            w[a >> 5] |= 1u << (a & 31);
+                        }
+            }
+        }
+    }
+    return MDA_OK;
+}

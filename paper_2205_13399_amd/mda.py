@@ -1,0 +1,353 @@
+"""Python binding of the MI355X multi-objective Digital Annealer C ABI (``include/mda.h``).
+
+Argument marshalling only: every step of the annealing path runs in the HIP
+kernels of ``libmda.so``.  PyTorch supplies device memory (through the caching
+allocator hook) and streams.  The library must be built (``build.py``); importing
+this module without it raises, there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+from typing import Optional, Sequence
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libmda.so")
+
+MDA_OK, MDA_EINVAL, MDA_EOVERFLOW, MDA_ENOMEM, MDA_EDEVICE, MDA_ERANGE, MDA_EBUSY = 0, -1, -2, -3, -4, -5, -6
+PEN_2MAX, PEN_VL = 0, 1
+PATH_AUTO, PATH_DENSE, PATH_KRON = 0, 1, 2
+STRICT, LENIENT = 0, 1
+EXPLORE, EXPLOIT = 0, 1
+ESC_OFFSET, ESC_ARCHIVE = 0, 1
+VARIANT_AUTO, VARIANT_PERSISTENT, VARIANT_PLAIN = 0, 1, 2
+
+_ERRNAMES = {MDA_EINVAL: "EINVAL", MDA_EOVERFLOW: "EOVERFLOW", MDA_ENOMEM: "ENOMEM",
+             MDA_EDEVICE: "EDEVICE", MDA_ERANGE: "ERANGE", MDA_EBUSY: "EBUSY"}
+
+
+class MdaError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__("%s (%d): %s" % (_ERRNAMES.get(code, "?"), code, msg))
+        self.code = code
+
+
+class BuildOpts(C.Structure):
+    _fields_ = [("penalty", C.c_int32), ("path", C.c_int32), ("dense_budget", C.c_int64)]
+
+
+class QuboInfo(C.Structure):
+    _fields_ = [("n", C.c_int32), ("m", C.c_int32), ("path", C.c_int32), ("symmetric", C.c_int32),
+                ("alpha1", C.c_int64), ("alpha2", C.c_int64), ("q1", C.c_int64), ("q2", C.c_int64),
+                ("maxabs_c", C.c_int64), ("device_bytes", C.c_int64)]
+
+
+class Params(C.Structure):
+    _fields_ = [("replicas", C.c_int32), ("archive_size", C.c_int32), ("steps", C.c_int64),
+                ("delta0", C.c_double), ("deltaf", C.c_double), ("xi", C.c_double),
+                ("beta", C.c_int64), ("accept", C.c_int32), ("archive", C.c_int32),
+                ("escape", C.c_int32), ("variant", C.c_int32), ("seed", C.c_uint64),
+                ("trace_replicas", C.c_int32), ("waves_per_block", C.c_int32),
+                ("stream", C.c_void_p)]
+
+
+class ArchiveOut(C.Structure):
+    _fields_ = [("cap", C.c_int64), ("e1", C.c_void_p), ("e2", C.c_void_p), ("replica", C.c_void_p),
+                ("slot", C.c_void_p), ("feasible", C.c_void_p), ("xbits", C.c_void_p),
+                ("perm", C.c_void_p)]
+
+
+class State(C.Structure):
+    _fields_ = [("x", C.c_void_p), ("h1", C.c_void_p), ("h2", C.c_void_p), ("e1", C.c_int64),
+                ("e2", C.c_int64), ("e_offset", C.c_int64), ("moves", C.c_int64),
+                ("scanned", C.c_int64), ("rng_blocks", C.c_int64), ("trace", C.c_void_p)]
+
+
+ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p)
+FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p)
+
+_lib = None
+
+
+def lib():
+    """Loads ``libmda.so`` (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError("libmda.so not found at %s: run paper_2205_13399_amd/build.py" % LIB_PATH)
+    L = C.CDLL(LIB_PATH)
+    vp, i32, i64 = C.c_void_p, C.c_int32, C.c_int64
+    L.qubo_build_bqap.argtypes = [i32, vp, vp, vp, C.POINTER(BuildOpts), vp, C.POINTER(vp)]
+    L.qubo_build_bqap.restype = C.c_int
+    L.qubo_info.argtypes = [vp, C.POINTER(QuboInfo)]
+    L.qubo_info.restype = C.c_int
+    L.qubo_free.argtypes = [vp]
+    L.qubo_free.restype = None
+    L.mda_params_default.argtypes = [C.POINTER(Params)]
+    L.mda_params_default.restype = None
+    L.da_run.argtypes = [vp, C.POINTER(Params), C.POINTER(vp)]
+    L.da_run.restype = C.c_int
+    L.da_run_batch.argtypes = [C.POINTER(vp), C.POINTER(Params), i32, C.POINTER(vp)]
+    L.da_run_batch.restype = C.c_int
+    L.da_sync.argtypes = [vp]
+    L.da_sync.restype = C.c_int
+    L.da_elapsed_ms.argtypes = [vp, C.POINTER(C.c_double)]
+    L.da_elapsed_ms.restype = C.c_int
+    L.archive_get.argtypes = [vp, i32, i32, C.POINTER(ArchiveOut), C.POINTER(i64)]
+    L.archive_get.restype = C.c_int
+    L.da_state_get.argtypes = [vp, i32, C.POINTER(State)]
+    L.da_state_get.restype = C.c_int
+    L.da_stats.argtypes = [vp, C.POINTER(i64), C.POINTER(i64), C.POINTER(i64), C.POINTER(i64)]
+    L.da_stats.restype = C.c_int
+    L.da_run_free.argtypes = [vp]
+    L.da_run_free.restype = None
+    L.mda_set_allocator.argtypes = [ALLOC_FN, FREE_FN, vp]
+    L.mda_set_allocator.restype = C.c_int
+    L.mda_last_error.argtypes = []
+    L.mda_last_error.restype = C.c_char_p
+    L.mda_threshold_table.argtypes = [vp]
+    L.mda_threshold_table.restype = C.c_int
+    L.mda_temperature_table.argtypes = [C.c_double, C.c_double, C.c_double, i64, vp]
+    L.mda_temperature_table.restype = C.c_int
+    _lib = L
+    return L
+
+
+EXPORTED = ["qubo_build_bqap", "qubo_info", "qubo_free", "mda_params_default", "da_run", "da_run_batch",
+            "da_sync", "da_elapsed_ms", "archive_get", "da_state_get", "da_stats", "da_run_free",
+            "mda_set_allocator", "mda_last_error", "mda_threshold_table", "mda_temperature_table"]
+
+
+def _check(rc: int):
+    if rc != MDA_OK:
+        raise MdaError(rc, lib().mda_last_error().decode())
+
+
+def _ptr(a: np.ndarray):
+    return a.ctypes.data_as(C.c_void_p)
+
+
+# ---------------------------------------------------------------- allocator
+
+_alloc_keep = []
+
+
+def use_torch_allocator():
+    """Routes the library's device allocations through PyTorch's caching allocator."""
+    import torch
+
+    def _alloc(nbytes, stream, ctx):
+        try:
+            return int(torch.cuda.caching_allocator_alloc(int(nbytes), stream=torch.cuda.current_stream()))
+        except Exception:
+            return None
+
+    def _free(ptr, nbytes, stream, ctx):
+        try:
+            torch.cuda.caching_allocator_delete(int(ptr))
+        except Exception:
+            pass
+
+    fa, ff = ALLOC_FN(_alloc), FREE_FN(_free)
+    _alloc_keep[:] = [fa, ff]
+    _check(lib().mda_set_allocator(fa, ff, None))
+
+
+def use_hip_allocator():
+    _check(lib().mda_set_allocator(ALLOC_FN(), FREE_FN(), None))
+    _alloc_keep.clear()
+
+
+def current_stream_handle() -> Optional[int]:
+    try:
+        import torch
+        if torch.cuda.is_available():
+            return int(torch.cuda.current_stream().cuda_stream)
+    except Exception:
+        pass
+    return None
+
+
+# ---------------------------------------------------------------- host tables
+
+def threshold_table() -> np.ndarray:
+    out = np.zeros(4096, np.int32)
+    _check(lib().mda_threshold_table(_ptr(out)))
+    return out
+
+
+def temperature_table(delta0: float, deltaf: float, xi: float, steps: int) -> np.ndarray:
+    out = np.zeros(int(steps), np.int64)
+    _check(lib().mda_temperature_table(float(delta0), float(deltaf), float(xi), int(steps), _ptr(out)))
+    return out
+
+
+# ---------------------------------------------------------------- handles
+
+class Qubo:
+    """qubo_build_bqap: the penalised QUBOs Y, Z of one bi-objective QAP instance."""
+
+    def __init__(self, F1, F2, D, penalty: int = PEN_2MAX, path: int = PATH_AUTO,
+                 dense_budget: int = 0, stream: Optional[int] = None):
+        F1 = np.ascontiguousarray(F1, np.int32)
+        F2 = np.ascontiguousarray(F2, np.int32)
+        D = np.ascontiguousarray(D, np.int32)
+        n = int(D.shape[0])
+        if F1.shape != (n, n) or F2.shape != (n, n) or D.shape != (n, n):
+            raise ValueError("F1, F2, D must be n x n")
+        self._h = C.c_void_p()
+        opts = BuildOpts(int(penalty), int(path), int(dense_budget))
+        s = current_stream_handle() if stream is None else stream
+        _check(lib().qubo_build_bqap(n, _ptr(F1), _ptr(F2), _ptr(D), C.byref(opts),
+                                     C.c_void_p(s) if s else None, C.byref(self._h)))
+        self.n = n
+        self.m = n * n
+
+    @property
+    def handle(self):
+        return self._h
+
+    def info(self) -> QuboInfo:
+        inf = QuboInfo()
+        _check(lib().qubo_info(self._h, C.byref(inf)))
+        return inf
+
+    def close(self):
+        if self._h:
+            lib().qubo_free(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def make_params(replicas: int, steps: int, seed: int, *, archive_size: int = 0,
+                delta0: float = 0.0, deltaf: float = 0.0, xi: float = 0.001, beta: int = -1,
+                accept: int = STRICT, archive: int = EXPLORE, escape: int = ESC_OFFSET,
+                variant: int = VARIANT_AUTO, trace_replicas: int = 0, waves_per_block: int = 0,
+                stream: Optional[int] = None) -> Params:
+    p = Params()
+    lib().mda_params_default(C.byref(p))
+    p.replicas = int(replicas)
+    p.archive_size = int(archive_size)
+    p.steps = int(steps)
+    p.delta0 = float(delta0)
+    p.deltaf = float(deltaf)
+    p.xi = float(xi)
+    p.beta = int(beta)
+    p.accept = int(accept)
+    p.archive = int(archive)
+    p.escape = int(escape)
+    p.variant = int(variant)
+    p.seed = int(seed) & 0xFFFFFFFFFFFFFFFF
+    p.trace_replicas = int(trace_replicas)
+    p.waves_per_block = int(waves_per_block)
+    s = current_stream_handle() if stream is None else stream
+    p.stream = C.c_void_p(s) if s else None
+    return p
+
+
+@dataclass
+class ArchiveResult:
+    e1: np.ndarray
+    e2: np.ndarray
+    replica: np.ndarray
+    slot: np.ndarray
+    feasible: np.ndarray
+    xbits: Optional[np.ndarray]
+    perm: Optional[np.ndarray]
+
+    def __len__(self):
+        return len(self.e1)
+
+
+class Run:
+    """One da_run (or one member of a da_run_batch)."""
+
+    def __init__(self, handle: C.c_void_p, qubo: Qubo, params: Params):
+        self._h = handle
+        self.qubo = qubo           # keeps the QUBO alive on the Python side too
+        self.params = params
+
+    def sync(self):
+        _check(lib().da_sync(self._h))
+
+    def elapsed_ms(self) -> float:
+        ms = C.c_double()
+        _check(lib().da_elapsed_ms(self._h, C.byref(ms)))
+        return float(ms.value)
+
+    def archive(self, replica: int = -1, raw: bool = False, bits: bool = True) -> ArchiveResult:
+        cnt = C.c_int64()
+        _check(lib().archive_get(self._h, int(replica), int(raw), None, C.byref(cnt)))
+        k = int(cnt.value)
+        n, m = self.qubo.n, self.qubo.m
+        words = (m + 31) // 32
+        e1 = np.zeros(k, np.int64)
+        e2 = np.zeros(k, np.int64)
+        rep = np.zeros(k, np.int32)
+        slot = np.zeros(k, np.int32)
+        feas = np.zeros(k, np.uint8)
+        xb = np.zeros((k, words), np.uint32) if bits else None
+        perm = np.zeros((k, n), np.int32) if bits else None
+        out = ArchiveOut(k, _ptr(e1).value, _ptr(e2).value, _ptr(rep).value, _ptr(slot).value,
+                         _ptr(feas).value, _ptr(xb).value if bits else None,
+                         _ptr(perm).value if bits else None)
+        _check(lib().archive_get(self._h, int(replica), int(raw), C.byref(out), C.byref(cnt)))
+        return ArchiveResult(e1, e2, rep, slot, feas, xb, perm)
+
+    def state(self, replica: int, trace: bool = False) -> dict:
+        m = self.qubo.m
+        x = np.zeros(m, np.uint8)
+        h1 = np.zeros(m, np.int32)
+        h2 = np.zeros(m, np.int32)
+        tr = np.zeros(int(self.params.steps), np.int32) if trace else None
+        st = State(_ptr(x).value, _ptr(h1).value, _ptr(h2).value, 0, 0, 0, 0, 0, 0,
+                   _ptr(tr).value if trace else None)
+        _check(lib().da_state_get(self._h, int(replica), C.byref(st)))
+        res = dict(x=x, h1=h1, h2=h2, E1=int(st.e1), E2=int(st.e2), Eoff=int(st.e_offset),
+                   moves=int(st.moves), scanned=int(st.scanned), rng_blocks=int(st.rng_blocks))
+        if trace:
+            res["trace"] = tr
+        return res
+
+    def stats(self) -> dict:
+        a, b, c, d = C.c_int64(), C.c_int64(), C.c_int64(), C.c_int64()
+        _check(lib().da_stats(self._h, C.byref(a), C.byref(b), C.byref(c), C.byref(d)))
+        return dict(moves=int(a.value), scanned=int(b.value), rng_blocks=int(c.value),
+                    archived=int(d.value))
+
+    def close(self):
+        if self._h:
+            lib().da_run_free(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def da_run(q: Qubo, params: Params) -> Run:
+    h = C.c_void_p()
+    _check(lib().da_run(q.handle, C.byref(params), C.byref(h)))
+    return Run(h, q, params)
+
+
+def da_run_batch(qs: Sequence[Qubo], params: Sequence[Params]) -> list:
+    k = len(qs)
+    if k != len(params) or k == 0:
+        raise ValueError("one parameter block per QUBO")
+    harr = (C.c_void_p * k)(*[q.handle for q in qs])
+    parr = (Params * k)(*params)
+    outs = (C.c_void_p * k)()
+    _check(lib().da_run_batch(harr, parr, k, outs))
+    return [Run(C.c_void_p(outs[i]), qs[i], params[i]) for i in range(k)]

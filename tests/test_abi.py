@@ -1,0 +1,67 @@
+"""CPU checks of the C ABI library: it loads, exports every declared entry point,
+and its host tables equal the oracle's (no device call is made)."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def mda():
+    from paper_2205_13399_amd import mda as m
+    if not os.path.exists(m.LIB_PATH):
+        pytest.fail("libmda.so is not built (run __graft_entry__.build())")
+    m.lib()
+    return m
+
+
+def _declared():
+    text = open(os.path.join(ROOT, "include", "mda.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    text = "\n".join(ln for ln in text.split("\n") if not ln.lstrip().startswith("typedef"))
+    names = re.findall(r"^\s*(?:const\s+)?[a-z_0-9]+\s*\*?\s*([a-z_][a-z_0-9]*)\s*\(", text, flags=re.M)
+    return sorted(set(names))
+
+
+def test_exports_every_declared_symbol(mda):
+    lib = ctypes.CDLL(mda.LIB_PATH)
+    declared = _declared()
+    assert "qubo_build_bqap" in declared and "da_run" in declared and "archive_get" in declared
+    for name in declared:
+        assert hasattr(lib, name), name
+    assert set(declared) == set(mda.EXPORTED)
+
+
+def test_threshold_table_matches_oracle(mda, orc):
+    assert np.array_equal(mda.threshold_table(), orc.lnt())
+
+
+@pytest.mark.parametrize("d0,df,xi,steps", [(2.9e6, 29.5, 0.001, 20000), (1e5, 1e5, 0.001, 50),
+                                            (5e4, 10.0, 0.01, 3000), (123.0, 1.0, 0.0, 100)])
+def test_temperature_table_matches_oracle(mda, orc, d0, df, xi, steps):
+    assert np.array_equal(mda.temperature_table(d0, df, xi, steps), orc.temperature(d0, df, xi, steps))
+
+
+def test_params_default(mda):
+    p = mda.make_params(3, 100, 5)
+    assert p.replicas == 3 and p.steps == 100 and p.accept == mda.STRICT and p.archive == mda.EXPLORE
+    assert p.escape == mda.ESC_OFFSET and p.beta == -1
+
+
+def test_errors_without_device(mda):
+    h = ctypes.c_void_p()
+    F = np.zeros((3, 3), np.int32)
+    rc = mda.lib().qubo_build_bqap(1, F.ctypes.data_as(ctypes.c_void_p), F.ctypes.data_as(ctypes.c_void_p),
+                                   F.ctypes.data_as(ctypes.c_void_p), None, None, ctypes.byref(h))
+    assert rc == mda.MDA_EINVAL
+    assert b"n = 1" in mda.lib().mda_last_error()
+    rc = mda.lib().qubo_build_bqap(3, None, None, None, None, None, ctypes.byref(h))
+    assert rc == mda.MDA_EINVAL
+    assert mda.lib().da_run(None, None, None) == mda.MDA_EINVAL
+    assert mda.lib().archive_get(None, 0, 0, None, None) == mda.MDA_EINVAL
+    mda.lib().da_run_free(None)
+    mda.lib().qubo_free(None)
