@@ -1,0 +1,315 @@
+#!/usr/bin/env python3
+"""Throughput of the multi-objective Digital Annealer on the bi-objective QAP.
+
+One bench step is one pass of the whole hot path over one batch: for every
+instance of the workload, all replicas start from random bits, run every
+annealing step (energy differences of both objectives for all m bits,
+acceptance with the dynamic offset, choice of one flip, field update, archive
+update; Algorithm 3 with Eqs. cale, pacceptms), the per-replica non-dominated
+flags are computed and the merged non-dominated archive of each instance is
+copied to the host.  The QUBO operands are built once, before the timed region.
+
+Metric: bit-trials/s = sum over instances of replicas * m * annealing steps,
+divided by the wall time of the step.  The plain GPU form (one launch per
+annealing step, replica state in HBM) runs the same workload beside it, and
+the oracle is timed on a bounded sample on the host's cores.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
+Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+import synth  # noqa: E402
+
+# Workloads: (n, rho values, seed config, replicas, annealing steps, path, structured)
+WORKLOADS = {
+    # the headline: three n = 50 instances (2500 bits), correlations -0.75, 0, 0.75,
+    # 4096 replicas x 1e5 steps each, Kronecker field updates, one batched launch
+    "bqap-n50-x3-kron": dict(n=50, rhos=(-0.75, 0.0, 0.75), cfg=2, replicas=4096, steps=100_000,
+                             path="kron", structured=True),
+    "bqap-n25-kron": dict(n=25, rhos=(0.75,), cfg=1, replicas=1024, steps=100_000, path="kron",
+                          structured=True),
+    "bqap-n25-dense": dict(n=25, rhos=(0.75,), cfg=1, replicas=1024, steps=100_000, path="dense",
+                           structured=True),
+    "bqap-n8-dense": dict(n=8, rhos=(0.0,), cfg=0, replicas=16, steps=10_000, path="dense",
+                          structured=False),
+}
+
+# Peak of plain 32-bit integer VALU work: 256 CUs x 4 SIMDs x 16 lanes per clock
+# x 2.4 GHz (a wave64 VALU instruction occupies a 16-lane SIMD for 4 clocks).
+ALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
+
+# Algorithmic integer operations (lane-ops) of the annealing step:
+#   per bit-trial   combine the two energy differences (max or min) and compare
+#                   against the step's largest acceptance threshold        2
+#   per move        per bit, both objectives: column entry (product of the
+#                   flow and distance factors), penalty term, field add     6 per bit
+#   per random block one Philox4x32-10 call (10 rounds of two 32x32->64
+#                   products, four xors, two key additions)               100 per lane
+OPS_PER_BIT_TRIAL = 2
+OPS_PER_MOVE_BIT = 6
+OPS_PER_PHILOX = 100
+
+KERNEL_SOURCES = ("paper_2205_13399_amd/csrc/mda_kernels.hip", "paper_2205_13399_amd/csrc/mda_desc.h")
+
+
+def _log(msg):
+    print("[bench] " + msg, file=sys.stderr, flush=True)
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for rel in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(workload: str):
+    """HBM bytes per launch of the persistent kernel from the committed counter
+    summary, or None when there is none or the kernel source has changed since."""
+    path = os.path.join(ROOT, "profiles", "traffic_k_persistent_%s.md" % workload)
+    if not os.path.exists(path):
+        return None
+    fields = {}
+    with open(path) as f:
+        for line in f:
+            if ":" in line and line.startswith("- "):
+                k, v = line[2:].split(":", 1)
+                fields[k.strip()] = v.strip()
+    if fields.get("kernel_source_sha256_16") != kernel_source_hash():
+        return None
+    try:
+        return float(fields["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def make_instances(w):
+    out = []
+    for idx, rho in enumerate(w["rhos"]):
+        seed = 0 if w["cfg"] == 0 else synth.instance_seed(w["cfg"], idx)
+        out.append(synth.make_instance(w["n"], rho, seed, structured=w["structured"]))
+    return out
+
+
+# ---------------------------------------------------------------- oracle leg
+
+def _oracle_job(args):
+    import oracle
+    (n, F1, F2, D, r, steps, seed) = args
+    F1 = np.frombuffer(F1, np.int32).reshape(n, n)
+    F2 = np.frombuffer(F2, np.int32).reshape(n, n)
+    D = np.frombuffer(D, np.int32).reshape(n, n)
+    q = oracle.Qubo(F1, F2, D, 0)
+    d0, df, xi, beta = oracle.default_schedule(q.maxabs_c, steps)
+    t0 = time.perf_counter()
+    res = oracle.run_replica(q, r, steps, d0, df, xi, beta, seed)
+    dt = time.perf_counter() - t0
+    return r, dt, (res["E1"], res["E2"], res["Eoff"], res["moves"], res["arch_size"],
+                   res["arch_e1"].tobytes(), res["arch_e2"].tobytes())
+
+
+def cpu_baseline(inst, steps, replicas, cores):
+    """The oracle, unmodified, on a sample of replicas: one process per replica."""
+    import multiprocessing as mp
+    jobs = [(inst.n, inst.F1.tobytes(), inst.F2.tobytes(), inst.D.tobytes(), r, steps, inst.seed)
+            for r in replicas]
+    ctx = mp.get_context("spawn")
+    t0 = time.perf_counter()
+    with ctx.Pool(cores) as pool:
+        res = pool.map(_oracle_job, jobs, chunksize=1)
+    wall = time.perf_counter() - t0
+    return wall, {r: (dt, out) for r, dt, out in res}
+
+
+# ---------------------------------------------------------------- main
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2, help="timed bench steps")
+    ap.add_argument("--warmup", type=int, default=1, help="untimed bench steps")
+    ap.add_argument("--workload", default="bqap-n50-x3-kron", choices=sorted(WORKLOADS))
+    ap.add_argument("--anneal-steps", type=int, default=0, help="override the workload's annealing steps")
+    ap.add_argument("--replicas", type=int, default=0, help="override the workload's replicas")
+    ap.add_argument("--plain", type=int, default=1, help="plain-form comparison runs (0 = none)")
+    ap.add_argument("--cpu-replicas", type=int, default=16, help="oracle sample size (0 = skip)")
+    ap.add_argument("--cpu-cores", type=int, default=8, help="oracle worker processes")
+    ap.add_argument("--waves-per-block", type=int, default=0)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run a plain device copy of 1 GiB (counter calibration)")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print("bench.py measures one GPU: the replicas of this workload are independent and would "
+              "shard across GPUs with no per-step communication, but only the one-GPU path is "
+              "built; run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    from paper_2205_13399_amd import mda
+
+    w = dict(WORKLOADS[args.workload])
+    if args.anneal_steps:
+        w["steps"] = args.anneal_steps
+    if args.replicas:
+        w["replicas"] = args.replicas
+    R, steps, n = w["replicas"], w["steps"], w["n"]
+    m = n * n
+    path = mda.PATH_KRON if w["path"] == "kron" else mda.PATH_DENSE
+
+    torch.cuda.set_device(0)
+    mda.use_torch_allocator()
+    stream = torch.cuda.current_stream()
+    insts = make_instances(w)
+    _log("workload %s: %d instance(s) n=%d, %d replicas x %d steps, path %s"
+         % (args.workload, len(insts), n, R, steps, w["path"]))
+    qs = [mda.Qubo(i.F1, i.F2, i.D, path=path) for i in insts]
+    params = [mda.make_params(R, steps, i.seed, waves_per_block=args.waves_per_block) for i in insts]
+    torch.cuda.synchronize()
+
+    bit_trials_step = len(insts) * R * m * steps
+
+    def one_step():
+        runs = mda.da_run_batch(qs, params)
+        fronts = [r.archive(-1, bits=False) for r in runs]
+        return runs, fronts
+
+    for k in range(args.warmup):
+        runs, _ = one_step()
+        _log("warmup %d: kernel %.1f ms" % (k, runs[0].kernel_ms()))
+        for r in runs:
+            r.close()
+
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    kms, ems, stats, fronts_last, runs_last = [], [], [], None, None
+    for k in range(args.steps):
+        if runs_last:
+            # done with the previous step: its device memory goes back to the pool
+            for r in runs_last:
+                r.close()
+        runs, fronts = one_step()
+        kms.append(runs[0].kernel_ms())
+        ems.append(runs[0].elapsed_ms())
+        stats.append([r.stats() for r in runs])
+        runs_last, fronts_last = runs, fronts
+        _log("step %d: kernel %.1f ms, launch %.1f ms" % (k, kms[-1], ems[-1]))
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms_per_step = wall * 1e3 / max(1, args.steps)
+    value = bit_trials_step * args.steps / wall
+
+    # roofline of the persistent kernel: algorithmic lane-ops per launch / kernel time
+    st = stats[-1]
+    moves = sum(s["moves"] for s in st)
+    rng_blocks = sum(s["rng_blocks"] for s in st)
+    ops = (OPS_PER_BIT_TRIAL * bit_trials_step + OPS_PER_MOVE_BIT * m * moves
+           + OPS_PER_PHILOX * 64 * rng_blocks)
+    kernel_ms = float(np.mean(kms))
+    achieved = ops / (kernel_ms * 1e-3) / 1e12
+    traffic = measured_traffic(args.workload)
+    roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": round(ALU_PEAK_TOPS, 2),
+                "unit": "TOP/s", "frac": round(achieved / ALU_PEAK_TOPS, 4), "traffic": traffic,
+                "kernel": "k_persistent", "kernel_ms": round(kernel_ms, 3),
+                "ops_per_launch": ops}
+
+    out = {
+        "metric": "bit-trials/s", "value": value, "unit": "bit-trials/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "int32",
+        "data": "synthetic",
+        "config": {"workload": args.workload, "n": n, "m": m, "instances": len(insts),
+                   "rho": list(w["rhos"]), "replicas": R, "anneal_steps": steps,
+                   "path": w["path"], "launch": "persistent, all instances in one launch",
+                   "bit_trials_per_step": bit_trials_step},
+        "roofline": roofline,
+        "run_stats": {"moves_per_replica": moves / (len(insts) * R),
+                      "p_move": moves / (len(insts) * R * steps),
+                      "rng_blocks_per_replica": rng_blocks / (len(insts) * R),
+                      "archived_per_replica": sum(s["archived"] for s in st) / (len(insts) * R),
+                      "front_sizes": [len(f) for f in fronts_last],
+                      "front_feasible": [int(f.feasible.sum()) for f in fronts_last]},
+    }
+
+    # plain GPU form: one launch per annealing step, one instance per call
+    if args.plain > 0:
+        pl_bt, pl_s = 0, 0.0
+        for idx in range(min(args.plain, len(insts))):
+            pp = mda.make_params(R, steps, insts[idx].seed, variant=mda.VARIANT_PLAIN,
+                                 waves_per_block=args.waves_per_block)
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            pr = mda.da_run(qs[idx], pp)
+            fr = pr.archive(-1, bits=False)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t1
+            pl_bt += R * m * steps
+            pl_s += dt
+            # same result as the batched launch, replica by replica
+            same = True
+            for r in (0, R // 2, R - 1):
+                a, b = pr.state(r), runs_last[idx].state(r)
+                same &= (a["E1"], a["E2"], a["moves"]) == (b["E1"], b["E2"], b["moves"])
+            same &= np.array_equal(fr.e1, fronts_last[idx].e1) and np.array_equal(fr.e2, fronts_last[idx].e2)
+            _log("plain instance %d: %.2f s, identical to batched: %s" % (idx, dt, same))
+            pr.close()
+        pv = pl_bt / pl_s
+        out["plain"] = {"value": pv, "unit": "bit-trials/s", "instances": min(args.plain, len(insts)),
+                        "launch": "one launch per annealing step, state in HBM",
+                        "identical_results": bool(same)}
+        out["vs_plain"] = round(value / pv, 3)
+
+    if args.copy_calibration:
+        a = torch.empty(1 << 28, dtype=torch.int32, device="cuda")
+        b = torch.empty_like(a)
+        a.fill_(1)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        out["copy_calibration_bytes"] = {"read": a.numel() * 4, "write": b.numel() * 4}
+
+    # the oracle on a bounded sample, on host cores (rank 0, one GPU)
+    if args.cpu_replicas > 0:
+        ncpu = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
+        cores = max(1, min(args.cpu_replicas, args.cpu_cores, ncpu, 16))
+        sample = list(range(args.cpu_replicas))
+        inst = insts[len(insts) // 2]
+        idx = len(insts) // 2
+        _log("oracle: %d replicas of instance %d on %d cores" % (len(sample), idx, cores))
+        cw, res = cpu_baseline(inst, steps, sample, cores)
+        exact = True
+        for r, (dt, o) in res.items():
+            g = runs_last[idx].state(r)
+            a = runs_last[idx].archive(r, raw=True, bits=False)
+            exact &= (g["E1"], g["E2"], g["Eoff"], g["moves"], len(a)) == o[:5]
+            exact &= a.e1.tobytes() == o[5] and a.e2.tobytes() == o[6]
+        out["cpu_baseline"] = {"value": len(sample) * m * steps / cw, "unit": "bit-trials/s",
+                               "cores": cores, "kind": "oracle",
+                               "sample": "%d replicas x %d steps of the n=%d rho=%g instance, one process "
+                                         "per replica, %.1f s wall" % (len(sample), steps, n, inst.rho, cw),
+                               "bit_exact_vs_gpu": bool(exact)}
+    for r in runs_last:
+        r.close()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

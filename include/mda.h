@@ -144,6 +144,10 @@ int da_sync(mda_run *r);
 /* Device time of the run's launch in milliseconds (HIP events; synchronises). */
 int da_elapsed_ms(mda_run *r, double *ms);
 
+/* Device time of the annealing kernel(s) alone: initial state, all steps and
+ * the final state of every replica, without the non-dominated filter. */
+int da_kernel_ms(mda_run *r, double *ms);
+
 typedef struct {
     int64_t cap;          /* entries the arrays below can hold */
     int64_t *e1, *e2;     /* energies E_1, E_2 (Eq. mqap) */

@@ -18,7 +18,7 @@
 
 namespace mda {
 int ns_for(int n);
-hipError_t launch_persistent(int ns, const RunDesc *runs, const WorkItem *work, int nwork, int *counter,
+hipError_t launch_persistent(int ns, const RunDesc *runs, const WorkItem *work, int nwork,
                              const int32_t *lnt, int grid, int block, hipStream_t stream);
 hipError_t launch_plain(int ns, const RunDesc *run, int R, uint32_t steps, const int32_t *lnt, int block,
                         hipStream_t stream);
@@ -403,15 +403,17 @@ struct Launch {
     RunDesc *ddesc = nullptr;
     WorkItem *dwork = nullptr;
     int nwork = 0;
-    int *dcounter = nullptr;
     int32_t *dlnt = nullptr;
     hipStream_t stream = nullptr;
-    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;   // whole run
+    hipEvent_t evk0 = nullptr, evk1 = nullptr; // annealing kernel(s) only
     ~Launch()
     {
         if (stream || ev0) (void)hipStreamSynchronize(stream);
         if (ev0) (void)hipEventDestroy(ev0);
         if (ev1) (void)hipEventDestroy(ev1);
+        if (evk0) (void)hipEventDestroy(evk0);
+        if (evk1) (void)hipEventDestroy(evk1);
         pool.release_all();
     }
 };
@@ -588,9 +590,8 @@ extern "C" int da_run_batch(const mda_qubo *const *qs, const mda_params *ps, int
     L->nwork = (int)work.size();
     L->ddesc = L->pool.alloc<RunDesc>(descs.size(), stream);
     L->dwork = L->pool.alloc<WorkItem>(work.size(), stream);
-    L->dcounter = L->pool.alloc<int>(1, stream);
     L->dlnt = L->pool.alloc<int32_t>(4096, stream);
-    if (!L->ddesc || !L->dwork || !L->dcounter || !L->dlnt) return fail(MDA_ENOMEM, "device allocation failed");
+    if (!L->ddesc || !L->dwork || !L->dlnt) return fail(MDA_ENOMEM, "device allocation failed");
     int32_t lnt[4096];
     threshold_table(lnt);
     HIP_TRY(hipMemcpyAsync(L->ddesc, descs.data(), descs.size() * sizeof(RunDesc), hipMemcpyHostToDevice, stream));
@@ -598,8 +599,11 @@ extern "C" int da_run_batch(const mda_qubo *const *qs, const mda_params *ps, int
     HIP_TRY(hipMemcpyAsync(L->dlnt, lnt, sizeof lnt, hipMemcpyHostToDevice, stream));
     HIP_TRY(hipEventCreate(&L->ev0));
     HIP_TRY(hipEventCreate(&L->ev1));
+    HIP_TRY(hipEventCreate(&L->evk0));
+    HIP_TRY(hipEventCreate(&L->evk1));
     const int block = default_block(ps[0].waves_per_block);
     HIP_TRY(hipEventRecord(L->ev0, stream));
+    HIP_TRY(hipEventRecord(L->evk0, stream));
     if (plain) {
         HIP_TRY(launch_plain(ns, L->ddesc, descs[0].R, descs[0].steps, L->dlnt, block, stream));
     } else {
@@ -612,11 +616,12 @@ extern "C" int da_run_batch(const mda_qubo *const *qs, const mda_params *ps, int
         int grid = cus * per_cu;
         const int need = (L->nwork + wpb - 1) / wpb;
         if (grid > need) grid = need;
-        const hipError_t le = launch_persistent(ns, L->ddesc, L->dwork, L->nwork, L->dcounter, L->dlnt, grid, block, stream);
+        const hipError_t le = launch_persistent(ns, L->ddesc, L->dwork, L->nwork, L->dlnt, grid, block, stream);
         if (le != hipSuccess)
             return fail(MDA_EDEVICE, "persistent launch (ns %d, grid %d, block %d, %d blocks/CU) failed: %s", ns, grid,
                         block, per_cu, hipGetErrorString(le));
     }
+    HIP_TRY(hipEventRecord(L->evk1, stream));
     HIP_TRY(launch_nondominated(L->ddesc, L->dwork, L->nwork, stream));
     HIP_TRY(hipEventRecord(L->ev1, stream));
     for (int i = 0; i < count; ++i) {
@@ -646,6 +651,16 @@ extern "C" int da_elapsed_ms(mda_run *r, double *ms)
     HIP_TRY(hipEventSynchronize(r->launch->ev1));
     float f = 0.f;
     HIP_TRY(hipEventElapsedTime(&f, r->launch->ev0, r->launch->ev1));
+    *ms = f;
+    return MDA_OK;
+}
+
+extern "C" int da_kernel_ms(mda_run *r, double *ms)
+{
+    if (!r || !r->launch || !ms) return fail(MDA_EINVAL, "NULL argument");
+    HIP_TRY(hipEventSynchronize(r->launch->evk1));
+    float f = 0.f;
+    HIP_TRY(hipEventElapsedTime(&f, r->launch->evk0, r->launch->evk1));
     *ms = f;
     return MDA_OK;
 }

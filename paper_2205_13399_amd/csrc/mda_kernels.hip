@@ -690,9 +690,8 @@ __device__ __forceinline__ int path_variant(Desc *Dp)
 // all of its steps with the replica state in registers.
 template <int NS>
 __global__ void __launch_bounds__(256) k_persistent(const RunDesc *runs, const WorkItem *work, int nwork,
-                                                    int *counter, const int32_t *lnt_)
+                                                    const int32_t *lnt_)
 {
-    (void)counter;
     const int lane = __lane_id();
     const MDA_GLOBAL int32_t *lnt = (const MDA_GLOBAL int32_t *)lnt_;
     const int wpb = (int)(blockDim.x >> 6);
@@ -708,11 +707,6 @@ __global__ void __launch_bounds__(256) k_persistent(const RunDesc *runs, const W
         default: run_replica<NS, kPvKronGen>(Dp, r, lane, lnt); break;
         }
     }
-}
-
-__global__ void k_reset_counter(int *counter)
-{
-    if (threadIdx.x == 0) *counter = 0;
 }
 
 // Plain form: state lives in HBM between launches (one launch per step).
@@ -881,17 +875,13 @@ int ns_for(int n)
     return ns < 8 ? 8 : ns;
 }
 
-hipError_t launch_persistent(int ns, const RunDesc *runs, const WorkItem *work, int nwork, int *counter,
-                             const int32_t *lnt, int grid, int block, hipStream_t stream)
+hipError_t launch_persistent(int ns, const RunDesc *runs, const WorkItem *work, int nwork, const int32_t *lnt,
+                             int grid, int block, hipStream_t stream)
 {
-    hipLaunchKernelGGL(k_reset_counter, dim3(1), dim3(64), 0, stream, counter);
-    const hipError_t e0 = hipGetLastError();
-    if (e0 != hipSuccess) return e0;
     switch (ns) {
 #define X(N)                                                                                          \
     case N:                                                                                           \
-        hipLaunchKernelGGL(k_persistent<N>, dim3(grid), dim3(block), 0, stream, runs, work, nwork, counter, \
-                           lnt);                                                                      \
+        hipLaunchKernelGGL(k_persistent<N>, dim3(grid), dim3(block), 0, stream, runs, work, nwork, lnt); \
         break;
         MDA_NS_LIST(X)
 #undef X

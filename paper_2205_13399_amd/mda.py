@@ -97,6 +97,8 @@ def lib():
     L.da_sync.restype = C.c_int
     L.da_elapsed_ms.argtypes = [vp, C.POINTER(C.c_double)]
     L.da_elapsed_ms.restype = C.c_int
+    L.da_kernel_ms.argtypes = [vp, C.POINTER(C.c_double)]
+    L.da_kernel_ms.restype = C.c_int
     L.archive_get.argtypes = [vp, i32, i32, C.POINTER(ArchiveOut), C.POINTER(i64)]
     L.archive_get.restype = C.c_int
     L.da_state_get.argtypes = [vp, i32, C.POINTER(State)]
@@ -118,7 +120,7 @@ def lib():
 
 
 EXPORTED = ["qubo_build_bqap", "qubo_info", "qubo_free", "mda_params_default", "da_run", "da_run_batch",
-            "da_sync", "da_elapsed_ms", "archive_get", "da_state_get", "da_stats", "da_run_free",
+            "da_sync", "da_elapsed_ms", "da_kernel_ms", "archive_get", "da_state_get", "da_stats", "da_run_free",
             "mda_set_allocator", "mda_last_error", "mda_threshold_table", "mda_temperature_table"]
 
 
@@ -282,6 +284,11 @@ class Run:
     def elapsed_ms(self) -> float:
         ms = C.c_double()
         _check(lib().da_elapsed_ms(self._h, C.byref(ms)))
+        return float(ms.value)
+
+    def kernel_ms(self) -> float:
+        ms = C.c_double()
+        _check(lib().da_kernel_ms(self._h, C.byref(ms)))
         return float(ms.value)
 
     def archive(self, replica: int = -1, raw: bool = False, bits: bool = True) -> ArchiveResult:
