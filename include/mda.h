@@ -117,6 +117,10 @@ typedef struct {
     int32_t trace_replicas;   /* record the flipped bit of every step for replicas [0, k) */
     int32_t waves_per_block;  /* launch shape hint, 1..4 (larger is clamped); 0 = default; results do not depend on it */
     void *stream;             /* hipStream_t; NULL = default stream */
+    int32_t graph;            /* 1: capture the launch sequence (one persistent launch per register tile, then the
+                                 non-dominated flags) into a HIP graph and launch it; needs a created stream;
+                                 da_kernel_ms then times the whole graph.  0: launch directly */
+    int32_t reserved;         /* 0 */
 } mda_params;
 
 /* Fills p with the defaults of Table (param) and the benchmark settings. */
@@ -134,8 +138,12 @@ int da_run(const mda_qubo *q, const mda_params *p, mda_run **out);
 
 /*
  * Runs several independent MDA runs (instances of any size, each with its own
- * parameters and seed) in one persistent launch on ps[0].stream; each result is
- * identical to the corresponding da_run.  outs receives one handle per run.
+ * parameters and seed) together on ps[0].stream: the replicas of all runs form
+ * one work list, grouped by register tile (slots per lane, 8 * ceil(n / 8)),
+ * and each group is one persistent launch; with ps[0].graph the launches are
+ * one HIP graph.  Each result is identical to the corresponding da_run.  outs
+ * receives one handle per run.  All runs share the stream, variant and graph
+ * setting.
  */
 int da_run_batch(const mda_qubo *const *qs, const mda_params *ps, int32_t count, mda_run **outs);
 

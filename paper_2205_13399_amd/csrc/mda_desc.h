@@ -16,7 +16,13 @@ enum : int32_t { kKronSym = 0, kKronGen = 1 };
 // Per-replica scalar statistics/state block (int64 words).
 enum : int32_t {
     kStE1 = 0, kStE2 = 1, kStEoff = 2, kStMoves = 3, kStScanned = 4, kStRng = 5,
-    kStArch = 6, kStDetailed = 7, kStWords = 8
+    kStArch = 6, kStDetailed = 7, kStNd = 8, kStWords = 16
+};
+
+// One non-dominated archive entry gathered for the host merge.
+struct FrontEntry {
+    int64_t e1, e2;
+    int32_t replica, slot;
 };
 
 // Largest n of the one-replica-per-wave kernels (lane = location).

@@ -23,6 +23,8 @@ hipError_t launch_persistent(int ns, const RunDesc *runs, const WorkItem *work, 
 hipError_t launch_plain(int ns, const RunDesc *run, int R, uint32_t steps, const int32_t *lnt, int block,
                         hipStream_t stream);
 hipError_t launch_nondominated(const RunDesc *runs, const WorkItem *work, int nwork, hipStream_t stream);
+hipError_t launch_front_gather(const int64_t *archE, const uint8_t *nd, const int64_t *st, int s, int r0, int nr,
+                               const int64_t *offs, FrontEntry *out, hipStream_t stream);
 hipError_t launch_build_dense(int n, const int32_t *F, const int32_t *Dm, int32_t two_alpha, int32_t *P,
                               hipStream_t stream);
 hipError_t persistent_occupancy(int ns, int block, int *blocks_per_cu);
@@ -407,9 +409,13 @@ struct Launch {
     hipStream_t stream = nullptr;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;   // whole run
     hipEvent_t evk0 = nullptr, evk1 = nullptr; // annealing kernel(s) only
+    hipGraph_t graph = nullptr;                // captured launch sequence, if any
+    hipGraphExec_t graph_exec = nullptr;
     ~Launch()
     {
         if (stream || ev0) (void)hipStreamSynchronize(stream);
+        if (graph_exec) (void)hipGraphExecDestroy(graph_exec);
+        if (graph) (void)hipGraphDestroy(graph);
         if (ev0) (void)hipEventDestroy(ev0);
         if (ev1) (void)hipEventDestroy(ev1);
         if (evk0) (void)hipEventDestroy(evk0);
@@ -426,6 +432,8 @@ struct mda_run {
     RunDesc h{};                       // host copy of this run's descriptor
     std::shared_ptr<Launch> launch;
     DevPool pool;                      // this run's outputs and tables
+    std::vector<FrontEntry> merged;    // non-dominated union over replicas, once computed
+    bool merged_ok = false;
     ~mda_run()
     {
         if (launch) (void)hipStreamSynchronize(launch->stream);
@@ -560,11 +568,13 @@ extern "C" int da_run_batch(const mda_qubo *const *qs, const mda_params *ps, int
     }
     const bool plain = ps[0].variant == MDA_VARIANT_PLAIN;
     if (plain && count != 1) return fail(MDA_EINVAL, "the plain form runs one instance per call");
+    if (plain && ps[0].graph) return fail(MDA_EINVAL, "the plain form is launched step by step, not as a graph");
     std::vector<std::unique_ptr<mda_run>> runs;
     for (int i = 0; i < count; ++i) {
         if (!qs[i]) return fail(MDA_EINVAL, "qubo %d is NULL", i);
         if (ps[i].stream != ps[0].stream) return fail(MDA_EINVAL, "all runs of a batch share one stream");
         if ((ps[i].variant == MDA_VARIANT_PLAIN) != plain) return fail(MDA_EINVAL, "mixed variants in a batch");
+        if ((ps[i].graph != 0) != (ps[0].graph != 0)) return fail(MDA_EINVAL, "mixed graph settings in a batch");
         mda_run *r = nullptr;
         const int rc = prepare_run(const_cast<mda_qubo *>(qs[i]), &ps[i], stream, &r);
         if (rc) return rc;
@@ -572,21 +582,35 @@ extern "C" int da_run_batch(const mda_qubo *const *qs, const mda_params *ps, int
     }
     auto L = std::make_shared<Launch>();
     L->stream = stream;
-    int ns = 8;
+    const bool graph = ps[0].graph != 0;
+    if (graph && !stream) return fail(MDA_EINVAL, "graph launches need a created stream, not the default one");
     std::vector<RunDesc> descs;
-    std::vector<WorkItem> work;
+    std::vector<int> tile(count);   // register tile (slots per lane) of each run
     for (int i = 0; i < count; ++i) {
         descs.push_back(runs[i]->h);
-        ns = std::max(ns, ns_for(runs[i]->h.n));
+        tile[i] = ns_for(runs[i]->h.n);
     }
-    // Work list, largest instances first (uneven sizes pack better).
+    // Work list: runs grouped by register tile, largest tile first (one
+    // persistent launch per tile, each with the occupancy of its own register
+    // budget); within a tile, largest instances first so that the round-robin
+    // assignment ends with the short items.
     std::vector<int> order(count);
     for (int i = 0; i < count; ++i) order[i] = i;
     std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+        if (tile[a] != tile[b]) return tile[a] > tile[b];
         return (int64_t)descs[a].m * descs[a].steps > (int64_t)descs[b].m * descs[b].steps;
     });
-    for (int i : order)
+    struct Group {
+        int ns, off, cnt;
+    };
+    std::vector<Group> groups;
+    std::vector<WorkItem> work;
+    for (int i : order) {
+        if (groups.empty() || groups.back().ns != tile[i]) groups.push_back(Group{tile[i], (int)work.size(), 0});
         for (int rr = 0; rr < descs[i].R; ++rr) work.push_back(WorkItem{i, rr});
+        groups.back().cnt += descs[i].R;
+    }
+    if (plain && groups.size() != 1) return fail(MDA_EINVAL, "the plain form runs one instance per call");
     L->nwork = (int)work.size();
     L->ddesc = L->pool.alloc<RunDesc>(descs.size(), stream);
     L->dwork = L->pool.alloc<WorkItem>(work.size(), stream);
@@ -602,27 +626,56 @@ extern "C" int da_run_batch(const mda_qubo *const *qs, const mda_params *ps, int
     HIP_TRY(hipEventCreate(&L->evk0));
     HIP_TRY(hipEventCreate(&L->evk1));
     const int block = default_block(ps[0].waves_per_block);
+    int dev = 0, cus = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+
+    // The launch sequence: the annealing kernel(s), then the non-dominated
+    // flags.  Either enqueued directly or captured into one graph.
+    auto enqueue = [&](bool timed) -> int {
+        if (timed) HIP_TRY(hipEventRecord(L->evk0, stream));
+        if (plain) {
+            HIP_TRY(launch_plain(groups[0].ns, L->ddesc, descs[0].R, descs[0].steps, L->dlnt, block, stream));
+        } else {
+            for (const Group &g : groups) {
+                int per_cu = 0;
+                HIP_TRY(persistent_occupancy(g.ns, block, &per_cu));
+                if (per_cu < 1) per_cu = 1;
+                const int wpb = block / 64;
+                int grid = cus * per_cu;
+                const int need = (g.cnt + wpb - 1) / wpb;
+                if (grid > need) grid = need;
+                const hipError_t le = launch_persistent(g.ns, L->ddesc, L->dwork + g.off, g.cnt, L->dlnt, grid, block, stream);
+                if (le != hipSuccess)
+                    return fail(MDA_EDEVICE, "persistent launch (ns %d, grid %d, block %d, %d blocks/CU) failed: %s", g.ns,
+                                grid, block, per_cu, hipGetErrorString(le));
+            }
+        }
+        if (timed) HIP_TRY(hipEventRecord(L->evk1, stream));
+        HIP_TRY(launch_nondominated(L->ddesc, L->dwork, L->nwork, stream));
+        return MDA_OK;
+    };
     HIP_TRY(hipEventRecord(L->ev0, stream));
-    HIP_TRY(hipEventRecord(L->evk0, stream));
-    if (plain) {
-        HIP_TRY(launch_plain(ns, L->ddesc, descs[0].R, descs[0].steps, L->dlnt, block, stream));
+    if (graph) {
+        // captured on the caller's stream; no memset or event inside the graph
+        HIP_TRY(hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal));
+        const int rc = enqueue(false);
+        hipGraph_t g = nullptr;
+        const hipError_t ce = hipStreamEndCapture(stream, &g);
+        if (rc) {
+            if (g) (void)hipGraphDestroy(g);
+            return rc;
+        }
+        if (ce != hipSuccess) return fail(MDA_EDEVICE, "graph capture failed: %s", hipGetErrorString(ce));
+        L->graph = g;
+        HIP_TRY(hipGraphInstantiate(&L->graph_exec, g, nullptr, nullptr, 0));
+        HIP_TRY(hipEventRecord(L->evk0, stream));
+        HIP_TRY(hipGraphLaunch(L->graph_exec, stream));
+        HIP_TRY(hipEventRecord(L->evk1, stream));
     } else {
-        int dev = 0, cus = 0, per_cu = 0;
-        HIP_TRY(hipGetDevice(&dev));
-        HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
-        HIP_TRY(persistent_occupancy(ns, block, &per_cu));
-        if (per_cu < 1) per_cu = 1;
-        const int wpb = block / 64;
-        int grid = cus * per_cu;
-        const int need = (L->nwork + wpb - 1) / wpb;
-        if (grid > need) grid = need;
-        const hipError_t le = launch_persistent(ns, L->ddesc, L->dwork, L->nwork, L->dlnt, grid, block, stream);
-        if (le != hipSuccess)
-            return fail(MDA_EDEVICE, "persistent launch (ns %d, grid %d, block %d, %d blocks/CU) failed: %s", ns, grid,
-                        block, per_cu, hipGetErrorString(le));
+        const int rc = enqueue(true);
+        if (rc) return rc;
     }
-    HIP_TRY(hipEventRecord(L->evk1, stream));
-    HIP_TRY(launch_nondominated(L->ddesc, L->dwork, L->nwork, stream));
     HIP_TRY(hipEventRecord(L->ev1, stream));
     for (int i = 0; i < count; ++i) {
         runs[i]->launch = L;
@@ -671,15 +724,6 @@ extern "C" void da_run_free(mda_run *r)
 }
 
 // ---------------------------------------------------------------- readout
-
-namespace {
-
-struct Entry {
-    int64_t e1, e2;
-    int32_t replica, slot;
-};
-
-}  // namespace
 
 static int copy_d2h(void *dst, const void *src, size_t bytes, hipStream_t s)
 {
@@ -742,6 +786,40 @@ extern "C" int da_state_get(mda_run *r, int32_t replica, mda_state *out)
     return MDA_OK;
 }
 
+namespace {
+
+struct TmpPool {
+    DevPool pool;
+    ~TmpPool() { pool.release_all(); }
+};
+
+}  // namespace
+
+// Flagged (non-dominated within their archive) entries of replicas
+// [r0, r0 + nr), compacted on the device and copied back; st holds those
+// replicas' statistics blocks.
+static int gather_flagged(mda_run *r, int r0, int nr, const std::vector<int64_t> &st, std::vector<FrontEntry> &ent)
+{
+    const RunDesc &d = r->h;
+    hipStream_t s = r->launch->stream;
+    std::vector<int64_t> offs((size_t)nr);
+    int64_t total = 0;
+    for (int k = 0; k < nr; ++k) {
+        offs[k] = total;
+        total += std::max<int64_t>(0, st[(size_t)k * kStWords + kStNd]);
+    }
+    ent.clear();
+    if (total == 0) return MDA_OK;
+    TmpPool tmp;
+    int64_t *doffs = tmp.pool.alloc<int64_t>((size_t)nr, s);
+    FrontEntry *dout = tmp.pool.alloc<FrontEntry>((size_t)total, s);
+    if (!doffs || !dout) return fail(MDA_ENOMEM, "device allocation failed for %lld front entries", (long long)total);
+    HIP_TRY(hipMemcpyAsync(doffs, offs.data(), offs.size() * sizeof(int64_t), hipMemcpyHostToDevice, s));
+    HIP_TRY(launch_front_gather(d.archE, d.nd, d.st, d.s, r0, nr, doffs, dout, s));
+    ent.resize((size_t)total);
+    return copy_d2h(ent.data(), dout, ent.size() * sizeof(FrontEntry), s);
+}
+
 extern "C" int archive_get(mda_run *r, int32_t replica, int32_t raw, mda_archive_out *out, int64_t *count)
 {
     if (!r || !count) return fail(MDA_EINVAL, "NULL argument");
@@ -752,85 +830,107 @@ extern "C" int archive_get(mda_run *r, int32_t replica, int32_t raw, mda_archive
     const int n = d.n, m = d.m, S = d.s;
     const int r0 = replica < 0 ? 0 : replica, r1 = replica < 0 ? d.R : replica + 1;
     const int nr = r1 - r0;
-    std::vector<int64_t> st((size_t)nr * kStWords);
-    int rc = copy_d2h(st.data(), d.st + (size_t)r0 * kStWords, st.size() * sizeof(int64_t), s);
-    if (rc) return rc;
-    std::vector<int64_t> E((size_t)nr * S * 2);
-    rc = copy_d2h(E.data(), d.archE + (size_t)r0 * S * 2, E.size() * sizeof(int64_t), s);
-    if (rc) return rc;
-    std::vector<uint8_t> nd((size_t)nr * S);
-    rc = copy_d2h(nd.data(), d.nd + (size_t)r0 * S, nd.size(), s);
-    if (rc) return rc;
+    int rc = MDA_OK;
 
-    std::vector<Entry> ent;
-    for (int k = 0; k < nr; ++k) {
-        const int asz = (int)st[(size_t)k * kStWords + kStArch];
-        for (int e = 0; e < asz; ++e) {
-            if (!raw && !nd[(size_t)k * S + e]) continue;
-            ent.push_back(Entry{E[((size_t)k * S + e) * 2], E[((size_t)k * S + e) * 2 + 1], r0 + k, e});
-        }
-    }
-    if (!raw) {
-        // Non-dominated union (Sec. 3.3), duplicates reduced to the lowest (replica, slot).
-        std::sort(ent.begin(), ent.end(), [](const Entry &a, const Entry &b) {
-            if (a.e1 != b.e1) return a.e1 < b.e1;
-            if (a.e2 != b.e2) return a.e2 < b.e2;
-            if (a.replica != b.replica) return a.replica < b.replica;
-            return a.slot < b.slot;
-        });
-        std::vector<Entry> keep;
-        int64_t best2 = INT64_MAX;
-        for (const Entry &e : ent) {
-            if (e.e2 < best2) {
-                keep.push_back(e);
-                best2 = e.e2;
+    std::vector<FrontEntry> local;
+    const std::vector<FrontEntry> *src = &local;
+    if (replica < 0 && r->merged_ok) {
+        src = &r->merged;
+    } else {
+        std::vector<int64_t> st((size_t)nr * kStWords);
+        rc = copy_d2h(st.data(), d.st + (size_t)r0 * kStWords, st.size() * sizeof(int64_t), s);
+        if (rc) return rc;
+        if (raw) {
+            // the ordered archive of one replica as stored
+            const int asz = (int)std::min<int64_t>(std::max<int64_t>(0, st[kStArch]), S);
+            std::vector<int64_t> E((size_t)asz * 2);
+            if (asz && (rc = copy_d2h(E.data(), d.archE + (size_t)replica * S * 2, E.size() * sizeof(int64_t), s)))
+                return rc;
+            for (int e = 0; e < asz; ++e) local.push_back(FrontEntry{E[2 * (size_t)e], E[2 * (size_t)e + 1], replica, e});
+        } else {
+            rc = gather_flagged(r, r0, nr, st, local);
+            if (rc) return rc;
+            // Non-dominated union (Sec. 3.3): sort by (E1, E2, replica, slot) and keep
+            // the strictly decreasing E2 staircase, so equal points reduce to the
+            // lowest (replica, slot).
+            std::sort(local.begin(), local.end(), [](const FrontEntry &a, const FrontEntry &b) {
+                if (a.e1 != b.e1) return a.e1 < b.e1;
+                if (a.e2 != b.e2) return a.e2 < b.e2;
+                if (a.replica != b.replica) return a.replica < b.replica;
+                return a.slot < b.slot;
+            });
+            std::vector<FrontEntry> keep;
+            int64_t best2 = INT64_MAX;
+            for (const FrontEntry &e : local) {
+                if (e.e2 < best2) {
+                    keep.push_back(e);
+                    best2 = e.e2;
+                }
+            }
+            local.swap(keep);
+            if (replica < 0) {
+                r->merged = local;
+                r->merged_ok = true;
             }
         }
-        ent.swap(keep);
     }
+    const std::vector<FrontEntry> &ent = *src;
     *count = (int64_t)ent.size();
     if (!out) return MDA_OK;
     if (out->cap < (int64_t)ent.size()) return fail(MDA_ERANGE, "capacity %lld < %lld entries", (long long)out->cap, (long long)ent.size());
+    const size_t k_n = ent.size();
+    std::vector<uint64_t> cols;
+    if (out->xbits || out->perm || out->feasible) {
+        // column masks of every returned entry: one contiguous copy for a raw
+        // archive, one copy per entry otherwise, then a single wait
+        cols.resize(k_n * (size_t)n);
+        if (raw) {
+            if (k_n) HIP_TRY(hipMemcpyAsync(cols.data(), d.archX + (size_t)replica * S * n, cols.size() * 8, hipMemcpyDeviceToHost, s));
+        } else {
+            for (size_t k = 0; k < k_n; ++k)
+                HIP_TRY(hipMemcpyAsync(cols.data() + k * n, d.archX + ((size_t)ent[k].replica * S + ent[k].slot) * n,
+                                       (size_t)n * 8, hipMemcpyDeviceToHost, s));
+        }
+        HIP_TRY(hipStreamSynchronize(s));
+    }
     const int words = (m + 31) / 32;
-    std::vector<uint64_t> cols((size_t)n);
-    for (size_t k = 0; k < ent.size(); ++k) {
-        const Entry &e = ent[k];
+    std::vector<int> perm(n), colsum(n);
+    for (size_t k = 0; k < k_n; ++k) {
+        const FrontEntry &e = ent[k];
         if (out->e1) out->e1[k] = e.e1;
         if (out->e2) out->e2[k] = e.e2;
         if (out->replica) out->replica[k] = e.replica;
         if (out->slot) out->slot[k] = e.slot;
-        if (out->xbits || out->perm || out->feasible) {
-            rc = copy_d2h(cols.data(), d.archX + ((size_t)e.replica * S + e.slot) * n, (size_t)n * 8, s);
-            if (rc) return rc;
-            bool feas = true;
-            std::vector<int> perm(n, -1);
-            std::vector<int> colsum(n, 0);
-            for (int i = 0; i < n; ++i) {
-                int cnt = 0;
-                for (int u = 0; u < n; ++u) {
-                    if ((cols[u] >> i) & 1ull) {
-                        ++cnt;
-                        ++colsum[u];
-                        perm[i] = u;
-                    }
+        if (cols.empty()) continue;
+        const uint64_t *c = cols.data() + k * n;
+        bool feas = true;
+        std::fill(perm.begin(), perm.end(), -1);
+        std::fill(colsum.begin(), colsum.end(), 0);
+        for (int i = 0; i < n; ++i) {
+            int cnt = 0;
+            for (int u = 0; u < n; ++u) {
+                if ((c[u] >> i) & 1ull) {
+                    ++cnt;
+                    ++colsum[u];
+                    perm[i] = u;
                 }
-                if (cnt != 1) feas = false;
             }
-            for (int u = 0; u < n; ++u)
-                if (colsum[u] != 1) feas = false;
-            if (out->feasible) out->feasible[k] = feas ? 1 : 0;
-            if (out->perm)
-                for (int i = 0; i < n; ++i) out->perm[k * n + i] = feas ? perm[i] : -1;
-            if (out->xbits) {
-                uint32_t *w = out->xbits + k * words;
-                std::memset(w, 0, (size_t)words * 4);
-                for (int i = 0; i < n; ++i)
-                    for (int u = 0; u < n; ++u)
-                        if ((cols[u] >> i) & 1ull) {
-                            const int a = i * n + u;
-                            w[a >> 5] |= 1u << (a & 31);
-                        }
-            }
+            if (cnt != 1) feas = false;
+        }
+        for (int u = 0; u < n; ++u)
+            if (colsum[u] != 1) feas = false;
+        if (out->feasible) out->feasible[k] = feas ? 1 : 0;
+        if (out->perm)
+            for (int i = 0; i < n; ++i) out->perm[k * n + i] = feas ? perm[i] : -1;
+        if (out->xbits) {
+            uint32_t *w = out->xbits + k * words;
+            std::memset(w, 0, (size_t)words * 4);
+            for (int i = 0; i < n; ++i)
+                for (int u = 0; u < n; ++u)
+                    if ((c[u] >> i) & 1ull) {
+                        const int a = i * n + u;
+                        w[a >> 5] |= 1u << (a & 31);
+                    }
         }
     }
     return MDA_OK;

@@ -62,6 +62,9 @@ struct U4 {
 __device__ __forceinline__ U4 philox10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
                                        uint32_t k0, uint32_t k1)
 {
+    // the round keys are derived here, at each call, instead of being hoisted
+    // out of the annealing loop into twenty long-lived scalar registers
+    asm volatile("" : "+s"(k0), "+s"(k1));
 #pragma unroll
     for (int round = 0; round < 10; ++round) {
         if (round) {
@@ -162,7 +165,6 @@ __device__ __forceinline__ int wave_sum(int v)
 // Fields read on every step, kept in scalar registers.
 struct Hot {
     int n;
-    int strict;
     int escape;
     int trace_R;
     uint32_t steps, ntab, key0, key1;
@@ -175,7 +177,6 @@ __device__ __forceinline__ Hot load_hot(Desc *Dp)
 {
     Hot h;
     h.n = Dp->n;
-    h.strict = Dp->accept == 0;
     h.escape = Dp->escape;
     h.trace_R = Dp->trace_R;
     h.steps = Dp->steps;
@@ -511,16 +512,28 @@ __device__ __forceinline__ void init_replica(Desc *Dp, Replica<NS> &S, int r, in
     fields_from_scratch<NS, PV>(Dp, S, lane);
 }
 
-// One annealing step t of replica r.  Returns the flipped bit or -1.
-template <int NS, int PV>
-__device__ __forceinline__ int anneal_step(Desc *Dp, const Hot &H, Replica<NS> &S, int r, uint32_t t, int lane_,
-                                           const MDA_GLOBAL int32_t *lnt)
+// Acceptance rule (template argument AM): strict (Eq. pacceptms) or lenient
+// (Eq. pacceptml).
+enum : int { kAmStrict = 0, kAmLenient = 1 };
+
+// Index into the temperature tables for step t (the schedule is constant after
+// its last entry).
+__device__ __forceinline__ uint32_t table_index(uint32_t t, uint32_t ntab)
 {
+    return ((t < ntab) ? t : ntab) - 1u;
+}
+
+// One annealing step t of replica r whose largest acceptance threshold
+// (T_t * LNT[0]) >> 24 is thrmax.  Returns the flipped bit or -1.
+template <int NS, int PV, int AM>
+__device__ __forceinline__ int anneal_step(Desc *Dp, const Hot &H, Replica<NS> &S, int r, uint32_t t, int lane_,
+                                           const MDA_GLOBAL int32_t *lnt, uint32_t thrmax)
+{
+    constexpr bool strict = AM == kAmStrict;
     const int lane = lane_;
     const int n = H.n;
     const uint64_t actmask = (n >= 64) ? ~0ull : ((1ull << n) - 1ull);
-    const uint32_t ti = ((t < H.ntab) ? t : H.ntab) - 1u;
-    const uint32_t thrmax = H.thrmax[ti];
+    const uint32_t ti = table_index(t, H.ntab);
     // Every real dE is at most 2^31 - 2 (build-time bound), so capping the
     // offset and the largest threshold at 2^31 - 2 keeps all comparisons exact
     // while slots and lanes beyond n, which hold INT_MAX, never qualify.
@@ -530,13 +543,8 @@ __device__ __forceinline__ int anneal_step(Desc *Dp, const Hot &H, Replica<NS> &
 
     // 1. can any bit be accepted?
     int32_t mn = INT_MAX;
-    if (H.strict) {
 #pragma unroll
-        for (int i = 0; i < NS; ++i) mn = min(mn, max(S.e1[i], S.e2[i]));
-    } else {
-#pragma unroll
-        for (int i = 0; i < NS; ++i) mn = min(mn, min(S.e1[i], S.e2[i]));
-    }
+    for (int i = 0; i < NS; ++i) mn = min(mn, strict ? max(S.e1[i], S.e2[i]) : min(S.e1[i], S.e2[i]));
     const uint64_t cand = __ballot(mn <= X) & actmask;
 
     int j = -1;
@@ -556,10 +564,11 @@ __device__ __forceinline__ int anneal_step(Desc *Dp, const Hot &H, Replica<NS> &
 #pragma unroll
                 for (int f = 0; f < 8; ++f) {
                     const int i = g + f;
-                    const bool a1 = S.e1[i] <= EoC, a2 = S.e2[i] <= EoC;
-                    const bool b1 = S.e1[i] <= X, b2 = S.e2[i] <= X;
-                    const bool sure = H.strict ? (a1 && a2) : (a1 || a2);
-                    const bool near = H.strict ? (b1 && b2) : (b1 || b2);
+                    // the statistic S is 0 exactly when the combined difference is at
+                    // most the offset, and above every threshold when it exceeds X
+                    const int32_t v = strict ? max(S.e1[i], S.e2[i]) : min(S.e1[i], S.e2[i]);
+                    const bool sure = v <= EoC;
+                    const bool near = v <= X;
                     certain |= sure ? (1u << f) : 0u;
                     maybe |= (near && !sure) ? (1u << f) : 0u;
                 }
@@ -577,7 +586,7 @@ __device__ __forceinline__ int anneal_step(Desc *Dp, const Hot &H, Replica<NS> &
                             const uint32_t idx = (w >> (16 * (f & 1))) & 0xFFFu;
                             const uint64_t u1 = (uint32_t)(max(S.e1[i], EoC) - EoC);
                             const uint64_t u2 = (uint32_t)(max(S.e2[i], EoC) - EoC);
-                            const uint64_t Sx = H.strict ? (u1 + u2) : (u1 < u2 ? u1 : u2);
+                            const uint64_t Sx = strict ? (u1 + u2) : (u1 < u2 ? u1 : u2);
                             const uint64_t thr = ((uint64_t)T * (uint64_t)(uint32_t)lnt[idx]) >> 24;
                             if (Sx <= thr) certain |= (1u << f);
                         }
@@ -670,13 +679,20 @@ __device__ __forceinline__ void export_replica(Desc *Dp, const Replica<NS> &S, i
 // ---------------------------------------------------------------- kernels
 
 // All steps of one replica with its state in registers.
-template <int NS, int PV>
+template <int NS, int PV, int AM>
 __device__ __forceinline__ void run_replica(Desc *Dp, int r, int lane, const MDA_GLOBAL int32_t *lnt)
 {
     Replica<NS> S;
     init_replica<NS, PV>(Dp, S, r, lane);
     const Hot H = load_hot(Dp);
-    for (uint32_t t = 1; t <= H.steps; ++t) anneal_step<NS, PV>(Dp, H, S, r, t, lane, lnt);
+    // the next step's threshold is loaded one step ahead
+    uint32_t thr = H.thrmax[0];
+    for (uint32_t t = 1; t <= H.steps; ++t) {
+        // entry of step t + 1: min(t + 1, ntab) - 1 = min(t, ntab - 1), ntab >= 1
+        const uint32_t thr_next = H.thrmax[(t < H.ntab - 1u) ? t : H.ntab - 1u];
+        anneal_step<NS, PV, AM>(Dp, H, S, r, t, lane, lnt, thr);
+        thr = thr_next;
+    }
     export_replica<NS>(Dp, S, r, lane);
 }
 
@@ -684,6 +700,16 @@ __device__ __forceinline__ int path_variant(Desc *Dp)
 {
     return Dp->path == kPathDense ? kPvDense : (Dp->kform == kKronGen ? kPvKronGen : kPvKronSym);
 }
+
+// Update path and acceptance rule of a run, as one switch value.
+__device__ __forceinline__ int step_variant(Desc *Dp)
+{
+    return path_variant(Dp) * 2 + (Dp->accept != 0 ? kAmLenient : kAmStrict);
+}
+
+#define MDA_STEP_VARIANTS(X)                                                                          \
+    X(kPvDense, kAmStrict) X(kPvDense, kAmLenient) X(kPvKronSym, kAmStrict) X(kPvKronSym, kAmLenient) \
+    X(kPvKronGen, kAmStrict) X(kPvKronGen, kAmLenient)
 
 // Persistent form: wave w of the grid runs work items w, w + W, w + 2W, ...
 // (W waves in the grid; the host orders the items largest first), each for
@@ -701,10 +727,14 @@ __global__ void __launch_bounds__(256) k_persistent(const RunDesc *runs, const W
         const WorkItem w = {ro(work)[item].run, ro(work)[item].replica};
         Desc *Dp = ro(runs) + uni(w.run);
         const int r = uni(w.replica);
-        switch (path_variant(Dp)) {
-        case kPvDense: run_replica<NS, kPvDense>(Dp, r, lane, lnt); break;
-        case kPvKronSym: run_replica<NS, kPvKronSym>(Dp, r, lane, lnt); break;
-        default: run_replica<NS, kPvKronGen>(Dp, r, lane, lnt); break;
+        switch (step_variant(Dp)) {
+#define X(PV, AM)                                        \
+    case PV * 2 + AM:                                    \
+        run_replica<NS, PV, AM>(Dp, r, lane, lnt); \
+        break;
+            MDA_STEP_VARIANTS(X)
+#undef X
+        default: break;
         }
     }
 }
@@ -772,13 +802,13 @@ __global__ void __launch_bounds__(256) k_plain_init(const RunDesc *run)
     plain_store<NS>(Dp, S, r, lane);
 }
 
-template <int NS, int PV>
+template <int NS, int PV, int AM>
 __device__ __forceinline__ void plain_step_one(Desc *Dp, int r, uint32_t t, int lane, const MDA_GLOBAL int32_t *lnt)
 {
     Replica<NS> S;
     plain_load<NS>(Dp, S, r, lane);
     const Hot H = load_hot(Dp);
-    anneal_step<NS, PV>(Dp, H, S, r, t, lane, lnt);
+    anneal_step<NS, PV, AM>(Dp, H, S, r, t, lane, lnt, H.thrmax[table_index(t, H.ntab)]);
     plain_store<NS>(Dp, S, r, lane);
 }
 
@@ -790,10 +820,14 @@ __global__ void __launch_bounds__(256) k_plain_step(const RunDesc *run, uint32_t
     Desc *Dp = ro(run);
     if (r >= Dp->R) return;
     const MDA_GLOBAL int32_t *lnt = (const MDA_GLOBAL int32_t *)lnt_;
-    switch (path_variant(Dp)) {
-    case kPvDense: plain_step_one<NS, kPvDense>(Dp, r, t, lane, lnt); break;
-    case kPvKronSym: plain_step_one<NS, kPvKronSym>(Dp, r, t, lane, lnt); break;
-    default: plain_step_one<NS, kPvKronGen>(Dp, r, t, lane, lnt); break;
+    switch (step_variant(Dp)) {
+#define X(PV, AM)                                           \
+    case PV * 2 + AM:                                       \
+        plain_step_one<NS, PV, AM>(Dp, r, t, lane, lnt); \
+        break;
+        MDA_STEP_VARIANTS(X)
+#undef X
+    default: break;
     }
 }
 
@@ -824,6 +858,7 @@ __global__ void __launch_bounds__(256) k_nondominated(const RunDesc *runs, const
     asz = asz < 0 ? 0 : (asz > s ? s : asz);
     const MDA_GLOBAL int64_t *AE = rw(D.archE) + (size_t)r * s * 2;
     MDA_GLOBAL uint8_t *nd = rw(D.nd) + (size_t)r * s;
+    int count = 0;
     for (int b = 0; b < asz; b += 64) {
         const int e = b + lane;
         if (e < asz) {
@@ -831,7 +866,42 @@ __global__ void __launch_bounds__(256) k_nondominated(const RunDesc *runs, const
             bool dom = false;
             for (int f = 0; f < asz; ++f) dom |= dominates(AE[2 * f], AE[2 * f + 1], a1, a2);
             nd[e] = dom ? 0 : 1;
+            count += dom ? 0 : 1;
         }
+    }
+    count = wave_sum(count);
+    if (lane == 0) rw(D.st)[(size_t)r * kStWords + kStNd] = count;
+}
+
+// Gathers the flagged (non-dominated) entries of replicas [r0, r0 + nr) of one
+// run into out, replica k's entries at out[offs[k] ...] in slot order.  One
+// wave per replica; offs holds the exclusive prefix sum of the counts that
+// k_nondominated wrote.
+__global__ void __launch_bounds__(256) k_front_gather(const int64_t *archE, const uint8_t *ndf, const int64_t *st,
+                                                      int s, int r0, int nr, const int64_t *offs, FrontEntry *out)
+{
+    const int lane = __lane_id();
+    const int k = uni((int)((blockIdx.x * blockDim.x + threadIdx.x) >> 6));
+    if (k >= nr) return;
+    const int r = r0 + k;
+    int asz = uni((int)rw(st)[(size_t)r * kStWords + kStArch]);
+    asz = asz < 0 ? 0 : (asz > s ? s : asz);
+    const MDA_GLOBAL int64_t *AE = rw(archE) + (size_t)r * s * 2;
+    const MDA_GLOBAL uint8_t *nd = rw(ndf) + (size_t)r * s;
+    MDA_GLOBAL FrontEntry *o = rw(out) + rw(offs)[k];
+    int base = 0;
+    for (int b = 0; b < asz; b += 64) {
+        const int e = b + lane;
+        const bool keep = e < asz && nd[e] != 0;
+        const uint64_t mask = __ballot(keep);
+        if (keep) {
+            const int rank = base + __popcll(mask & ((lane == 0) ? 0ull : (~0ull >> (64 - lane))));
+            o[rank].e1 = AE[2 * e];
+            o[rank].e2 = AE[2 * e + 1];
+            o[rank].replica = r;
+            o[rank].slot = e;
+        }
+        base += __popcll(mask);
     }
 }
 
@@ -917,6 +987,15 @@ hipError_t launch_nondominated(const RunDesc *runs, const WorkItem *work, int nw
     const int block = 256;
     const int grid = (nwork * 64 + block - 1) / block;
     hipLaunchKernelGGL(k_nondominated, dim3(grid), dim3(block), 0, stream, runs, work, nwork);
+    return hipGetLastError();
+}
+
+hipError_t launch_front_gather(const int64_t *archE, const uint8_t *nd, const int64_t *st, int s, int r0, int nr,
+                               const int64_t *offs, FrontEntry *out, hipStream_t stream)
+{
+    const int block = 256;
+    const int grid = (nr * 64 + block - 1) / block;
+    hipLaunchKernelGGL(k_front_gather, dim3(grid), dim3(block), 0, stream, archE, nd, st, s, r0, nr, offs, out);
     return hipGetLastError();
 }
 

@@ -51,7 +51,7 @@ class Params(C.Structure):
                 ("beta", C.c_int64), ("accept", C.c_int32), ("archive", C.c_int32),
                 ("escape", C.c_int32), ("variant", C.c_int32), ("seed", C.c_uint64),
                 ("trace_replicas", C.c_int32), ("waves_per_block", C.c_int32),
-                ("stream", C.c_void_p)]
+                ("stream", C.c_void_p), ("graph", C.c_int32), ("reserved", C.c_int32)]
 
 
 class ArchiveOut(C.Structure):
@@ -234,7 +234,7 @@ def make_params(replicas: int, steps: int, seed: int, *, archive_size: int = 0,
                 delta0: float = 0.0, deltaf: float = 0.0, xi: float = 0.001, beta: int = -1,
                 accept: int = STRICT, archive: int = EXPLORE, escape: int = ESC_OFFSET,
                 variant: int = VARIANT_AUTO, trace_replicas: int = 0, waves_per_block: int = 0,
-                stream: Optional[int] = None) -> Params:
+                stream: Optional[int] = None, graph: bool = False) -> Params:
     p = Params()
     lib().mda_params_default(C.byref(p))
     p.replicas = int(replicas)
@@ -251,6 +251,7 @@ def make_params(replicas: int, steps: int, seed: int, *, archive_size: int = 0,
     p.seed = int(seed) & 0xFFFFFFFFFFFFFFFF
     p.trace_replicas = int(trace_replicas)
     p.waves_per_block = int(waves_per_block)
+    p.graph = 1 if graph else 0
     s = current_stream_handle() if stream is None else stream
     p.stream = C.c_void_p(s) if s else None
     return p
