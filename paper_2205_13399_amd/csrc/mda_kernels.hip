@@ -29,6 +29,7 @@
 
 #define MDA_CONST __attribute__((address_space(4)))
 #define MDA_GLOBAL __attribute__((address_space(1)))
+#define MDA_LDS __attribute__((address_space(3)))
 
 namespace mda {
 
@@ -431,18 +432,28 @@ __device__ __forceinline__ void archive_update(Desc *Dp, int n, Replica<NS> &S, 
     const int64_t E1 = S.E1, E2 = S.E2;
     int slot = -1;
     if (D.archive == 0) {
-        for (int b = 0; b < asz; b += 64) {
-            const int e = b + lane;
-            bool hit = false;
-            if (e < asz) hit = dominates(E1, E2, AE[2 * e], AE[2 * e + 1]);
-            const uint64_t M = __ballot(hit);
-            if (M) {
-                const int f = __ffsll((long long)M) - 1;
-                S.scanned += f + 1;
-                slot = b + f;
+        // first member that x dominates; four blocks of 64 members are read at
+        // once (indices clamped into the archive, so every read is in bounds)
+        for (int b = 0; b < asz; b += 256) {
+            uint64_t M[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int e = b + 64 * q + lane;
+                const int ec = e < asz ? e : asz - 1;
+                const int64_t a1 = AE[2 * ec], a2 = AE[2 * ec + 1];
+                M[q] = __ballot(e < asz && dominates(E1, E2, a1, a2));
+            }
+            int q = -1;
+#pragma unroll
+            for (int qq = 3; qq >= 0; --qq) q = M[qq] ? qq : q;
+            if (q >= 0) {
+                const uint64_t Mq = (q == 0) ? M[0] : (q == 1) ? M[1] : (q == 2) ? M[2] : M[3];
+                const int f = __ffsll((long long)Mq) - 1;
+                S.scanned += 64 * q + f + 1;
+                slot = b + 64 * q + f;
                 break;
             }
-            S.scanned += (asz - b < 64) ? (asz - b) : 64;
+            S.scanned += (asz - b < 256) ? (asz - b) : 256;
         }
     } else {
         // Algorithm 5: nothing may dominate x; then a random member of
@@ -525,9 +536,9 @@ __device__ __forceinline__ uint32_t table_index(uint32_t t, uint32_t ntab)
 
 // One annealing step t of replica r whose largest acceptance threshold
 // (T_t * LNT[0]) >> 24 is thrmax.  Returns the flipped bit or -1.
-template <int NS, int PV, int AM>
+template <int NS, int PV, int AM, class LP>
 __device__ __forceinline__ int anneal_step(Desc *Dp, const Hot &H, Replica<NS> &S, int r, uint32_t t, int lane_,
-                                           const MDA_GLOBAL int32_t *lnt, uint32_t thrmax)
+                                           LP lnt, uint32_t thrmax)
 {
     constexpr bool strict = AM == kAmStrict;
     const int lane = lane_;
@@ -551,8 +562,13 @@ __device__ __forceinline__ int anneal_step(Desc *Dp, const Hot &H, Replica<NS> &
     if (cand) {
         S.detailed++;
         const int lane = opaque_lane(lane_);
-        // 2. exact acceptance, 8 facilities per random block
+        // 2. exact acceptance, 8 facilities per random block.  The threshold
+        // (T * LNT[k]) >> 24 is formed exactly from 24-bit products: with
+        // T = Th 2^24 + Tl (T < 2^43, so Th < 2^19; LNT < 2^20) it equals
+        // Th LNT + ((Tl LNT) >> 24), and it is below 2^32 because the largest
+        // one, (T LNT[0]) >> 24, is (checked on the host).
         const int64_t T = H.T[ti];
+        const uint32_t Th = (uint32_t)((uint64_t)T >> 24), Tl = (uint32_t)T & 0xFFFFFFu;
         uint64_t acc = 0;
         const int ng = opaque(n);
 #pragma unroll
@@ -584,10 +600,14 @@ __device__ __forceinline__ int anneal_step(Desc *Dp, const Hot &H, Replica<NS> &
                             const int i = g + f;
                             const uint32_t w = (f < 2) ? o.x : (f < 4) ? o.y : (f < 6) ? o.z : o.w;
                             const uint32_t idx = (w >> (16 * (f & 1))) & 0xFFFu;
-                            const uint64_t u1 = (uint32_t)(max(S.e1[i], EoC) - EoC);
-                            const uint64_t u2 = (uint32_t)(max(S.e2[i], EoC) - EoC);
-                            const uint64_t Sx = strict ? (u1 + u2) : (u1 < u2 ? u1 : u2);
-                            const uint64_t thr = ((uint64_t)T * (uint64_t)(uint32_t)lnt[idx]) >> 24;
+                            // u_k = max(0, dE_k - E_offset) < 2^31 for a real bit, so the
+                            // strict sum stays below 2^32
+                            const uint32_t u1 = (uint32_t)(max(S.e1[i], EoC) - EoC);
+                            const uint32_t u2 = (uint32_t)(max(S.e2[i], EoC) - EoC);
+                            const uint32_t Sx = strict ? (u1 + u2) : (u1 < u2 ? u1 : u2);
+                            const uint32_t L = (uint32_t)lnt[idx] & 0xFFFFFu;
+                            const uint64_t low = (uint64_t)Tl * (uint64_t)L;   // 24 x 20 bits
+                            const uint32_t thr = __umul24(Th, L) + (uint32_t)(low >> 24);
                             if (Sx <= thr) certain |= (1u << f);
                         }
                     }
@@ -680,7 +700,7 @@ __device__ __forceinline__ void export_replica(Desc *Dp, const Replica<NS> &S, i
 
 // All steps of one replica with its state in registers.
 template <int NS, int PV, int AM>
-__device__ __forceinline__ void run_replica(Desc *Dp, int r, int lane, const MDA_GLOBAL int32_t *lnt)
+__device__ __forceinline__ void run_replica(Desc *Dp, int r, int lane, const MDA_LDS int32_t *lnt)
 {
     Replica<NS> S;
     init_replica<NS, PV>(Dp, S, r, lane);
@@ -718,8 +738,12 @@ template <int NS>
 __global__ void __launch_bounds__(256) k_persistent(const RunDesc *runs, const WorkItem *work, int nwork,
                                                     const int32_t *lnt_)
 {
+    // the -ln table, read at random by the exact acceptance test, lives in LDS
+    __shared__ int32_t lnt_lds[4096];
+    for (int k = (int)threadIdx.x; k < 4096; k += (int)blockDim.x) lnt_lds[k] = ((const MDA_GLOBAL int32_t *)lnt_)[k];
+    __syncthreads();
+    const MDA_LDS int32_t *lnt = (const MDA_LDS int32_t *)lnt_lds;
     const int lane = __lane_id();
-    const MDA_GLOBAL int32_t *lnt = (const MDA_GLOBAL int32_t *)lnt_;
     const int wpb = (int)(blockDim.x >> 6);
     const int wave = uni((int)(blockIdx.x * wpb + (threadIdx.x >> 6)));
     const int nwaves = (int)gridDim.x * wpb;
