@@ -64,7 +64,8 @@ OPS_PER_BIT_TRIAL = 2
 OPS_PER_MOVE_BIT = 6
 OPS_PER_PHILOX = 100
 
-KERNEL_SOURCES = ("paper_2205_13399_amd/csrc/mda_kernels.hip", "paper_2205_13399_amd/csrc/mda_desc.h")
+KERNEL_SOURCES = ("paper_2205_13399_amd/csrc/mda_kernels.hip", "paper_2205_13399_amd/csrc/mda_desc.h",
+                  "paper_2205_13399_amd/csrc/mda_device.h")
 
 
 def _log(msg):

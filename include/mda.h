@@ -120,7 +120,9 @@ typedef struct {
     int32_t graph;            /* 1: capture the launch sequence (one persistent launch per register tile, then the
                                  non-dominated flags) into a HIP graph and launch it; needs a created stream;
                                  da_kernel_ms then times the whole graph.  0: launch directly */
-    int32_t reserved;         /* 0 */
+    int32_t waves_per_replica;/* 0: one wave for n <= 64, else a workgroup of 2 * ceil(n / 64) waves;
+                                 1: one wave (n <= 64); 2..8: a workgroup of that many waves, split into
+                                 ceil(n / 64) location blocks and facility blocks of equal size */
 } mda_params;
 
 /* Fills p with the defaults of Table (param) and the benchmark settings. */

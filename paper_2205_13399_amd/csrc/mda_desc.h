@@ -71,6 +71,17 @@ struct RunDesc {
     int32_t *pe;               // [R][2][NS][64]
     int32_t ns_plain;          // NS of the plain state layout
     int32_t pad1;
+    // layout of the replica over waves: wr x wc waves (1 x 1 = one wave per
+    // replica, lane = location, slot = facility, n <= 64); in a workgroup run
+    // wave (p, c) holds facilities [p gns, p gns + gns) and locations
+    // [64 c, 64 c + 64), and solutions are stored as wr * wc * 64 words,
+    // word (p wc + c) 64 + (u mod 64), bit i - p gns
+    int32_t wr, wc, gns;
+    int32_t ldk;               // row stride of KA, KB, DA, DB and the diagonals
+    int32_t pld;               // dense P_k: entry (i, u) of row j at j * n * pld + i * pld + u
+    int32_t xw;                // words per archived solution (n, or wr * wc * 64)
+    int32_t xrw;               // words per replica in x (64, or wr * wc * 64)
+    int32_t pad2;
 };
 
 struct WorkItem {

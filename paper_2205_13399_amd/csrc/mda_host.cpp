@@ -18,6 +18,10 @@
 
 namespace mda {
 int ns_for(int n);
+int group_waves_limit(int ns);
+hipError_t launch_group(int ns, int wr, int wc, const RunDesc *runs, const WorkItem *work, int nwork,
+                        const int32_t *lnt, int grid, hipStream_t stream);
+hipError_t group_occupancy(int ns, int wr, int wc, int *blocks_per_cu);
 hipError_t launch_persistent(int ns, const RunDesc *runs, const WorkItem *work, int nwork,
                              const int32_t *lnt, int grid, int block, hipStream_t stream);
 hipError_t launch_plain(int ns, const RunDesc *run, int R, uint32_t steps, const int32_t *lnt, int block,
@@ -25,7 +29,7 @@ hipError_t launch_plain(int ns, const RunDesc *run, int R, uint32_t steps, const
 hipError_t launch_nondominated(const RunDesc *runs, const WorkItem *work, int nwork, hipStream_t stream);
 hipError_t launch_front_gather(const int64_t *archE, const uint8_t *nd, const int64_t *st, int s, int r0, int nr,
                                const int64_t *offs, FrontEntry *out, hipStream_t stream);
-hipError_t launch_build_dense(int n, const int32_t *F, const int32_t *Dm, int32_t two_alpha, int32_t *P,
+hipError_t launch_build_dense(int n, int ld, const int32_t *F, const int32_t *Dm, int32_t two_alpha, int32_t *P,
                               hipStream_t stream);
 hipError_t persistent_occupancy(int ns, int block, int *blocks_per_cu);
 }  // namespace mda
@@ -175,6 +179,8 @@ struct mda_qubo {
     std::vector<int32_t> F1, F2, D, diag1, diag2;
     int32_t *dKA1 = nullptr, *dKA2 = nullptr, *dKB1 = nullptr, *dKB2 = nullptr, *dDA = nullptr, *dDB = nullptr;
     int32_t *dP1 = nullptr, *dP2 = nullptr, *ddiag1 = nullptr, *ddiag2 = nullptr;
+    int32_t ldk = kLD;   // row stride of the per-lane operands and the diagonals
+    int32_t pld = kLD;   // dense P_k: entry (i, u) of row j at j * n * pld + i * pld + u
     DevPool pool;
     int refs = 1;   // the owner plus every run that uses it
 };
@@ -215,7 +221,6 @@ extern "C" int qubo_build_bqap(int32_t n, const int32_t *F1, const int32_t *F2, 
     if (opts) o = *opts;
     if (o.penalty != MDA_PEN_2MAX && o.penalty != MDA_PEN_VL) return fail(MDA_EINVAL, "unknown penalty %d", o.penalty);
     if (o.path < MDA_PATH_AUTO || o.path > MDA_PATH_KRON) return fail(MDA_EINVAL, "unknown path %d", o.path);
-    if (n > kMaxWaveN) return fail(MDA_EINVAL, "n = %d: this build anneals n <= %d", n, kMaxWaveN);
     const int64_t budget = o.dense_budget > 0 ? o.dense_budget : (int64_t)2 << 30;
     hipStream_t stream = (hipStream_t)stream_;
 
@@ -318,7 +323,12 @@ extern "C" int qubo_build_bqap(int32_t n, const int32_t *F1, const int32_t *F2, 
         track(DA);
     }
     const bool kron_ok = maxop < (1 << 23);   // 24-bit multiply-adds
-    const bool dense_fits = 8 * (int64_t)m * n * kLD <= budget;
+    // Operand layouts: up to 64 facilities every row is padded to 64 entries
+    // (one wave per replica reads them unmasked); beyond, rows of 128 entries
+    // and the dense rows unpadded (the workgroup form masks its reads).
+    q->ldk = n <= kMaxWaveN ? kLD : 2 * kLD;
+    q->pld = n <= kMaxWaveN ? kLD : n;
+    const bool dense_fits = 8 * (int64_t)m * n * q->pld <= budget;
     if (o.path == MDA_PATH_KRON) {
         if (!kron_ok) return fail(MDA_EOVERFLOW, "Kronecker operands exceed the 24-bit multiplier range");
         q->path = kPathKron;
@@ -328,7 +338,7 @@ extern "C" int qubo_build_bqap(int32_t n, const int32_t *F1, const int32_t *F2, 
         q->path = (dense_fits || !kron_ok) ? kPathDense : kPathKron;
     }
 
-    // Uploads.  Per-lane operands go up as n rows of kLD entries, zero padded.
+    // Uploads.  Per-lane operands go up as rows of ldk entries, zero padded.
     auto up = [&](const std::vector<int32_t> &h) -> int32_t * {
         int32_t *d = q->pool.alloc<int32_t>(h.size(), stream);
         if (d && hipMemcpyAsync(d, h.data(), h.size() * sizeof(int32_t), hipMemcpyHostToDevice, stream) != hipSuccess)
@@ -336,14 +346,16 @@ extern "C" int qubo_build_bqap(int32_t n, const int32_t *F1, const int32_t *F2, 
         return d;
     };
     auto pad = [&](const std::vector<int32_t> &h, int rows) {
-        std::vector<int32_t> o((size_t)rows * kLD, 0);
+        const int ld = q->ldk;
+        std::vector<int32_t> o((size_t)rows * ld, 0);
         for (int a = 0; a < n; ++a)
-            for (int b = 0; b < n; ++b) o[(size_t)a * kLD + b] = h[(size_t)a * n + b];
+            for (int b = 0; b < n; ++b) o[(size_t)a * ld + b] = h[(size_t)a * n + b];
         return o;
     };
-    // the diagonal is read for every register slot (up to kMaxWaveN rows)
-    q->ddiag1 = up(pad(q->diag1, kMaxWaveN));
-    q->ddiag2 = up(pad(q->diag2, kMaxWaveN));
+    // the one-wave form reads the diagonal for every register slot (up to
+    // kMaxWaveN rows)
+    q->ddiag1 = up(pad(q->diag1, std::max(n, kMaxWaveN)));
+    q->ddiag2 = up(pad(q->diag2, std::max(n, kMaxWaveN)));
     if (!q->ddiag1 || !q->ddiag2) return fail(MDA_ENOMEM, "device allocation failed");
     if (q->path == kPathKron) {
         q->dKA1 = up(pad(KA[0], n));
@@ -362,11 +374,11 @@ extern "C" int qubo_build_bqap(int32_t n, const int32_t *F1, const int32_t *F2, 
         }
     } else {
         int32_t *dF1 = up(q->F1), *dF2 = up(q->F2), *dD = up(q->D);
-        q->dP1 = q->pool.alloc<int32_t>((size_t)m * n * kLD, stream);
-        q->dP2 = q->pool.alloc<int32_t>((size_t)m * n * kLD, stream);
+        q->dP1 = q->pool.alloc<int32_t>((size_t)m * n * q->pld, stream);
+        q->dP2 = q->pool.alloc<int32_t>((size_t)m * n * q->pld, stream);
         if (!dF1 || !dF2 || !dD || !q->dP1 || !q->dP2) return fail(MDA_ENOMEM, "device allocation failed");
-        HIP_TRY(launch_build_dense(n, dF1, dD, (int32_t)(2 * q->alpha[0]), q->dP1, stream));
-        HIP_TRY(launch_build_dense(n, dF2, dD, (int32_t)(2 * q->alpha[1]), q->dP2, stream));
+        HIP_TRY(launch_build_dense(n, q->pld, dF1, dD, (int32_t)(2 * q->alpha[0]), q->dP1, stream));
+        HIP_TRY(launch_build_dense(n, q->pld, dF2, dD, (int32_t)(2 * q->alpha[1]), q->dP2, stream));
         q->dKA1 = q->dKA2 = q->dKB1 = q->dKB2 = q->dDA = q->dDB = dF1;   // unused on this path
     }
     HIP_TRY(hipStreamSynchronize(stream));
@@ -516,6 +528,36 @@ static int prepare_run(mda_qubo *q, const mda_params *pin, hipStream_t stream, m
     d.beta = p.beta;
     d.q1 = q->q[0];
     d.q2 = q->q[1];
+    // Layout of a replica over waves: one wave (n <= 64) or a workgroup of
+    // wr x wc waves, wc = ceil(n / 64) location blocks and wr facility blocks of
+    // gns = 8 ceil(ceil(n / wr) / 8) slots.
+    {
+        const int want = p.waves_per_replica;
+        const int wc = (n + 63) / 64;
+        if (want < 0 || want > 8) return fail(MDA_EINVAL, "waves_per_replica = %d outside [0, 8]", want);
+        if (want == 1 && n > kMaxWaveN) return fail(MDA_EINVAL, "n = %d needs more than one wave per replica", n);
+        if ((want == 0 && n <= kMaxWaveN) || want == 1) {
+            d.wr = d.wc = 1;
+            d.gns = ns_for(n);
+            d.xw = n;
+            d.xrw = 64;
+        } else {
+            const int wr = want == 0 ? 2 : std::max(1, want / wc);
+            const int per = (n + wr - 1) / wr;
+            const int gns = ((per + 7) / 8) * 8;
+            if (gns > 64 || wr * wc > group_waves_limit(gns) || wr * wc != (want == 0 ? 2 * wc : want))
+                return fail(MDA_EINVAL, "no workgroup layout of %d waves for n = %d (%d location blocks)",
+                            want == 0 ? 2 * wc : want, n, wc);
+            if (p.variant == MDA_VARIANT_PLAIN) return fail(MDA_EINVAL, "the plain form runs one wave per replica");
+            d.wr = wr;
+            d.wc = wc;
+            d.gns = gns;
+            d.xw = wr * wc * 64;
+            d.xrw = wr * wc * 64;
+        }
+    }
+    d.ldk = q->ldk;
+    d.pld = q->pld;
     d.KA1 = q->dKA1; d.KA2 = q->dKA2; d.KB1 = q->dKB1; d.KB2 = q->dKB2; d.DA = q->dDA; d.DB = q->dDB;
     d.P1 = q->dP1; d.P2 = q->dP2;
     d.diag1 = q->ddiag1; d.diag2 = q->ddiag2;
@@ -523,11 +565,11 @@ static int prepare_run(mda_qubo *q, const mda_params *pin, hipStream_t stream, m
     DevPool &pool = r->pool;
     int64_t *dT = pool.alloc<int64_t>(T.size(), stream);
     uint32_t *dthr = pool.alloc<uint32_t>(T.size(), stream);
-    d.x = pool.alloc<uint64_t>((size_t)R * 64, stream);
+    d.x = pool.alloc<uint64_t>((size_t)R * d.xrw, stream);
     d.h = pool.alloc<int32_t>((size_t)R * 2 * m, stream);
     d.st = pool.alloc<int64_t>((size_t)R * kStWords, stream);
     d.archE = pool.alloc<int64_t>((size_t)R * s * 2, stream);
-    d.archX = pool.alloc<uint64_t>((size_t)R * s * n, stream);
+    d.archX = pool.alloc<uint64_t>((size_t)R * s * d.xw, stream);
     d.nd = pool.alloc<uint8_t>((size_t)R * s, stream);
     d.trace = pool.alloc<int32_t>((size_t)std::max(1, p.trace_replicas) * (size_t)(p.trace_replicas ? p.steps : 1), stream);
     const int ns = ns_for(n);
@@ -585,10 +627,13 @@ extern "C" int da_run_batch(const mda_qubo *const *qs, const mda_params *ps, int
     const bool graph = ps[0].graph != 0;
     if (graph && !stream) return fail(MDA_EINVAL, "graph launches need a created stream, not the default one");
     std::vector<RunDesc> descs;
-    std::vector<int> tile(count);   // register tile (slots per lane) of each run
+    // launch key of each run: register tile (slots per lane) and waves per replica
+    std::vector<int> tile(count), wrk(count), wck(count);
     for (int i = 0; i < count; ++i) {
         descs.push_back(runs[i]->h);
-        tile[i] = ns_for(runs[i]->h.n);
+        tile[i] = runs[i]->h.gns;
+        wrk[i] = runs[i]->h.wr;
+        wck[i] = runs[i]->h.wc;
     }
     // Work list: runs grouped by register tile, largest tile first (one
     // persistent launch per tile, each with the occupancy of its own register
@@ -597,16 +642,19 @@ extern "C" int da_run_batch(const mda_qubo *const *qs, const mda_params *ps, int
     std::vector<int> order(count);
     for (int i = 0; i < count; ++i) order[i] = i;
     std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+        if (wrk[a] * wck[a] != wrk[b] * wck[b]) return wrk[a] * wck[a] > wrk[b] * wck[b];
+        if (wck[a] != wck[b]) return wck[a] > wck[b];
         if (tile[a] != tile[b]) return tile[a] > tile[b];
         return (int64_t)descs[a].m * descs[a].steps > (int64_t)descs[b].m * descs[b].steps;
     });
     struct Group {
-        int ns, off, cnt;
+        int ns, wr, wc, off, cnt;
     };
     std::vector<Group> groups;
     std::vector<WorkItem> work;
     for (int i : order) {
-        if (groups.empty() || groups.back().ns != tile[i]) groups.push_back(Group{tile[i], (int)work.size(), 0});
+        if (groups.empty() || groups.back().ns != tile[i] || groups.back().wr != wrk[i] || groups.back().wc != wck[i])
+            groups.push_back(Group{tile[i], wrk[i], wck[i], (int)work.size(), 0});
         for (int rr = 0; rr < descs[i].R; ++rr) work.push_back(WorkItem{i, rr});
         groups.back().cnt += descs[i].R;
     }
@@ -639,16 +687,30 @@ extern "C" int da_run_batch(const mda_qubo *const *qs, const mda_params *ps, int
         } else {
             for (const Group &g : groups) {
                 int per_cu = 0;
-                HIP_TRY(persistent_occupancy(g.ns, block, &per_cu));
-                if (per_cu < 1) per_cu = 1;
-                const int wpb = block / 64;
-                int grid = cus * per_cu;
-                const int need = (g.cnt + wpb - 1) / wpb;
-                if (grid > need) grid = need;
-                const hipError_t le = launch_persistent(g.ns, L->ddesc, L->dwork + g.off, g.cnt, L->dlnt, grid, block, stream);
-                if (le != hipSuccess)
-                    return fail(MDA_EDEVICE, "persistent launch (ns %d, grid %d, block %d, %d blocks/CU) failed: %s", g.ns,
-                                grid, block, per_cu, hipGetErrorString(le));
+                if (g.wr * g.wc == 1) {
+                    HIP_TRY(persistent_occupancy(g.ns, block, &per_cu));
+                    if (per_cu < 1) per_cu = 1;
+                    const int wpb = block / 64;
+                    int grid = cus * per_cu;
+                    const int need = (g.cnt + wpb - 1) / wpb;
+                    if (grid > need) grid = need;
+                    const hipError_t le =
+                        launch_persistent(g.ns, L->ddesc, L->dwork + g.off, g.cnt, L->dlnt, grid, block, stream);
+                    if (le != hipSuccess)
+                        return fail(MDA_EDEVICE, "persistent launch (ns %d, grid %d, block %d, %d blocks/CU) failed: %s",
+                                    g.ns, grid, block, per_cu, hipGetErrorString(le));
+                } else {
+                    // one replica per workgroup of wr x wc waves
+                    HIP_TRY(group_occupancy(g.ns, g.wr, g.wc, &per_cu));
+                    if (per_cu < 1) per_cu = 1;
+                    int grid = cus * per_cu;
+                    if (grid > g.cnt) grid = g.cnt;
+                    const hipError_t le =
+                        launch_group(g.ns, g.wr, g.wc, L->ddesc, L->dwork + g.off, g.cnt, L->dlnt, grid, stream);
+                    if (le != hipSuccess)
+                        return fail(MDA_EDEVICE, "workgroup launch (ns %d, %d x %d waves, grid %d, %d blocks/CU) failed: %s",
+                                    g.ns, g.wr, g.wc, grid, per_cu, hipGetErrorString(le));
+                }
             }
         }
         if (timed) HIP_TRY(hipEventRecord(L->evk1, stream));
@@ -725,6 +787,15 @@ extern "C" void da_run_free(mda_run *r)
 
 // ---------------------------------------------------------------- readout
 
+// Bit x_{i,u} of a stored solution (a row of x or an archive entry) in the run's
+// layout over waves.
+static inline bool sol_bit(const RunDesc &d, const uint64_t *words, int i, int u)
+{
+    if (d.wr * d.wc == 1) return (words[u] >> i) & 1ull;
+    const int p = i / d.gns, c = u / 64;
+    return (words[(size_t)(p * d.wc + c) * 64 + (u % 64)] >> (i - p * d.gns)) & 1ull;
+}
+
 static int copy_d2h(void *dst, const void *src, size_t bytes, hipStream_t s)
 {
     HIP_TRY(hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToHost, s));
@@ -770,11 +841,11 @@ extern "C" int da_state_get(mda_run *r, int32_t replica, mda_state *out)
     out->rng_blocks = st[kStRng];
     const int n = d.n, m = d.m;
     if (out->x) {
-        uint64_t cols[64];
-        rc = copy_d2h(cols, d.x + (size_t)replica * 64, sizeof cols, s);
+        std::vector<uint64_t> words((size_t)d.xrw);
+        rc = copy_d2h(words.data(), d.x + (size_t)replica * d.xrw, words.size() * 8, s);
         if (rc) return rc;
         for (int i = 0; i < n; ++i)
-            for (int u = 0; u < n; ++u) out->x[i * n + u] = (uint8_t)((cols[u] >> i) & 1ull);
+            for (int u = 0; u < n; ++u) out->x[i * n + u] = sol_bit(d, words.data(), i, u) ? 1 : 0;
     }
     if (out->h1 && (rc = copy_d2h(out->h1, d.h + (size_t)replica * 2 * m, (size_t)m * 4, s))) return rc;
     if (out->h2 && (rc = copy_d2h(out->h2, d.h + (size_t)replica * 2 * m + m, (size_t)m * 4, s))) return rc;
@@ -879,17 +950,18 @@ extern "C" int archive_get(mda_run *r, int32_t replica, int32_t raw, mda_archive
     if (!out) return MDA_OK;
     if (out->cap < (int64_t)ent.size()) return fail(MDA_ERANGE, "capacity %lld < %lld entries", (long long)out->cap, (long long)ent.size());
     const size_t k_n = ent.size();
+    const size_t xw = (size_t)d.xw;
     std::vector<uint64_t> cols;
     if (out->xbits || out->perm || out->feasible) {
-        // column masks of every returned entry: one contiguous copy for a raw
-        // archive, one copy per entry otherwise, then a single wait
-        cols.resize(k_n * (size_t)n);
+        // stored solutions of every returned entry: one contiguous copy for a
+        // raw archive, one copy per entry otherwise, then a single wait
+        cols.resize(k_n * xw);
         if (raw) {
-            if (k_n) HIP_TRY(hipMemcpyAsync(cols.data(), d.archX + (size_t)replica * S * n, cols.size() * 8, hipMemcpyDeviceToHost, s));
+            if (k_n) HIP_TRY(hipMemcpyAsync(cols.data(), d.archX + (size_t)replica * S * xw, cols.size() * 8, hipMemcpyDeviceToHost, s));
         } else {
             for (size_t k = 0; k < k_n; ++k)
-                HIP_TRY(hipMemcpyAsync(cols.data() + k * n, d.archX + ((size_t)ent[k].replica * S + ent[k].slot) * n,
-                                       (size_t)n * 8, hipMemcpyDeviceToHost, s));
+                HIP_TRY(hipMemcpyAsync(cols.data() + k * xw, d.archX + ((size_t)ent[k].replica * S + ent[k].slot) * xw,
+                                       xw * 8, hipMemcpyDeviceToHost, s));
         }
         HIP_TRY(hipStreamSynchronize(s));
     }
@@ -902,14 +974,14 @@ extern "C" int archive_get(mda_run *r, int32_t replica, int32_t raw, mda_archive
         if (out->replica) out->replica[k] = e.replica;
         if (out->slot) out->slot[k] = e.slot;
         if (cols.empty()) continue;
-        const uint64_t *c = cols.data() + k * n;
+        const uint64_t *c = cols.data() + k * xw;
         bool feas = true;
         std::fill(perm.begin(), perm.end(), -1);
         std::fill(colsum.begin(), colsum.end(), 0);
         for (int i = 0; i < n; ++i) {
             int cnt = 0;
             for (int u = 0; u < n; ++u) {
-                if ((c[u] >> i) & 1ull) {
+                if (sol_bit(d, c, i, u)) {
                     ++cnt;
                     ++colsum[u];
                     perm[i] = u;
@@ -927,7 +999,7 @@ extern "C" int archive_get(mda_run *r, int32_t replica, int32_t raw, mda_archive
             std::memset(w, 0, (size_t)words * 4);
             for (int i = 0; i < n; ++i)
                 for (int u = 0; u < n; ++u)
-                    if ((c[u] >> i) & 1ull) {
+                    if (sol_bit(d, c, i, u)) {
                         const int a = i * n + u;
                         w[a >> 5] |= 1u << (a & 31);
                     }

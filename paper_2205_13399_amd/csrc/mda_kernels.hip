@@ -21,197 +21,9 @@
 //  5. archive update (Algorithm 4 or 5) against the archive in HBM.
 // The random stream is counter-based on (seed, step, replica, bit group), so
 // the result does not depend on the launch shape or on which draws are skipped.
-#include <hip/hip_runtime.h>
-
-#include <climits>
-
-#include "mda_desc.h"
-
-#define MDA_CONST __attribute__((address_space(4)))
-#define MDA_GLOBAL __attribute__((address_space(1)))
-#define MDA_LDS __attribute__((address_space(3)))
+#include "mda_device.h"
 
 namespace mda {
-
-// Read-only operands are read through the constant address space (scalar
-// loads when the address is wave-uniform); buffers the kernels write go
-// through the global address space.
-using Desc = const MDA_CONST RunDesc;
-
-template <class T>
-__device__ __forceinline__ const MDA_CONST T *ro(const T *p)
-{
-    return (const MDA_CONST T *)p;
-}
-
-template <class T>
-__device__ __forceinline__ MDA_GLOBAL T *rw(T *p)
-{
-    return (MDA_GLOBAL T *)p;
-}
-
-// ---------------------------------------------------------------- utilities
-
-struct U4 {
-    uint32_t x, y, z, w;
-};
-
-// Philox4x32-10 block function (Salmon, Moraes, Dror, Shaw, SC'11): ten
-// rounds, each multiplying words 0 and 2 by the round multipliers and mixing
-// the high halves with words 1, 3 and the key; the key advances by the two
-// Weyl increments between rounds.
-__device__ __forceinline__ U4 philox10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
-                                       uint32_t k0, uint32_t k1)
-{
-    // the round keys are derived here, at each call, instead of being hoisted
-    // out of the annealing loop into twenty long-lived scalar registers
-    asm volatile("" : "+s"(k0), "+s"(k1));
-#pragma unroll
-    for (int round = 0; round < 10; ++round) {
-        if (round) {
-            k0 += 0x9E3779B9u;
-            k1 += 0xBB67AE85u;
-        }
-        const uint64_t a = (uint64_t)c0 * 0xD2511F53u;
-        const uint64_t b = (uint64_t)c2 * 0xCD9E8D57u;
-        const uint32_t y0 = (uint32_t)(b >> 32) ^ c1 ^ k0;
-        const uint32_t y2 = (uint32_t)(a >> 32) ^ c3 ^ k1;
-        c1 = (uint32_t)b;
-        c3 = (uint32_t)a;
-        c0 = y0;
-        c2 = y2;
-    }
-    return U4{c0, c1, c2, c3};
-}
-
-__device__ __forceinline__ uint32_t scale32(uint32_t w, uint32_t c)
-{
-    return (uint32_t)(((uint64_t)w * c) >> 32);   // floor(w * c / 2^32), uniform in [0, c)
-}
-
-__device__ __forceinline__ int32_t rl(int32_t v, int lane)
-{
-    return __builtin_amdgcn_readlane(v, lane);
-}
-
-__device__ __forceinline__ uint64_t rl64(uint64_t v, int lane)
-{
-    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, lane);
-    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), lane);
-    return ((uint64_t)hi << 32) | lo;
-}
-
-__device__ __forceinline__ int uni(int v)
-{
-    return __builtin_amdgcn_readfirstlane(v);
-}
-
-__device__ __forceinline__ int64_t uni64(int64_t v)
-{
-    const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)v);
-    const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)((uint64_t)v >> 32));
-    return (int64_t)(((uint64_t)hi << 32) | lo);
-}
-
-// Lane of the k-th (0-based) set bit of a wave-uniform mask.
-__device__ __forceinline__ int kth_lane(uint64_t M, int k, int lane)
-{
-    const uint64_t below = M & ((lane == 0) ? 0ull : (~0ull >> (64 - lane)));
-    const bool hit = ((M >> lane) & 1ull) && (__popcll(below) == k);
-    return uni(__ffsll((long long)__ballot(hit)) - 1);
-}
-
-__device__ __forceinline__ bool dominates(int64_t p1, int64_t p2, int64_t q1, int64_t q2)
-{
-    return p1 <= q1 && p2 <= q2 && !(p1 == q1 && p2 == q2);
-}
-
-// Returns p unchanged but hides its value from the optimiser, so loads made
-// through it stay on the (rare) path that uses them instead of being hoisted
-// into registers for the whole annealing loop.
-__device__ __forceinline__ Desc *cold(Desc *p)
-{
-    uint64_t v = (uint64_t)p;
-    uint32_t lo = (uint32_t)v, hi = (uint32_t)(v >> 32);
-    asm volatile("" : "+v"(lo), "+v"(hi));
-    lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)lo);
-    hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)hi);
-    return (Desc *)(((uint64_t)hi << 32) | lo);
-}
-
-// Same for a wave-uniform integer: conditions derived from the result are
-// evaluated where they are used instead of being kept live across the loop.
-__device__ __forceinline__ int opaque(int v)
-{
-    asm volatile("" : "+v"(v));
-    return __builtin_amdgcn_readfirstlane(v);
-}
-
-// Per-lane value hidden from the optimiser: cold code that starts from it
-// cannot be hoisted out of the annealing loop into long-lived registers.
-__device__ __forceinline__ int opaque_lane(int v)
-{
-    asm volatile("" : "+v"(v));
-    return v;
-}
-
-// Wave-wide sum of a per-lane integer.
-__device__ __forceinline__ int wave_sum(int v)
-{
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
-    return uni(v);
-}
-
-// Fields read on every step, kept in scalar registers.
-struct Hot {
-    int n;
-    int escape;
-    int trace_R;
-    uint32_t steps, ntab, key0, key1;
-    int64_t beta;
-    const MDA_CONST uint32_t *thrmax;
-    const MDA_CONST int64_t *T;
-};
-
-__device__ __forceinline__ Hot load_hot(Desc *Dp)
-{
-    Hot h;
-    h.n = Dp->n;
-    h.escape = Dp->escape;
-    h.trace_R = Dp->trace_R;
-    h.steps = Dp->steps;
-    h.ntab = Dp->ntab;
-    h.key0 = Dp->key0;
-    h.key1 = Dp->key1;
-    h.beta = Dp->beta;
-    h.thrmax = ro(Dp->thrmax);
-    h.T = ro(Dp->T);
-    return h;
-}
-
-// ---------------------------------------------------------------- replica state
-
-template <int NS>
-struct Replica {
-    int32_t e1[NS], e2[NS];   // dE_k of bit (slot i, this lane)
-    uint64_t xm;              // bit i = x_{i, lane}
-    int64_t E1, E2, Eoff;
-    int64_t moves, scanned, rngb, detailed;
-    int32_t asize;
-};
-
-// Update paths (template argument PV): dense rows of P_k, or the Kronecker
-// column with one product per objective (D or F symmetric) or two.
-enum : int { kPvDense = 0, kPvKronSym = 1, kPvKronGen = 2 };
-
-// Value held by slots beyond n (facilities that do not exist).  Such a slot
-// only ever receives the +-2 alpha_k penalty of flips in its own column, whose
-// sum is 2 alpha_k times the change of that column's occupation, so it stays
-// within [kDead - 2 alpha n, kDead + 2 alpha n] (the host checks 2 alpha n <
-// 2^29); the exact acceptance test masks these slots out, and they are large
-// enough never to pass the cheap "can anything be accepted" test.
-constexpr int32_t kDead = 1 << 30;
 
 // Flips bit (js, jl) whose current differences are d1, d2: E_k += dE_k(j);
 // for every other bit a, dE_k[a] += (x_a == x_j ? +1 : -1) * P_k[a][j];
@@ -298,18 +110,6 @@ __device__ __forceinline__ void flip(Desc *Dp, int n_, Replica<NS> &S, int js, i
         }
     }
     S.xm ^= (lane == jl) ? (1ull << js) : 0ull;
-}
-
-// Wave-wide sum of a per-lane int64.
-__device__ __forceinline__ int64_t wave_sum64(int64_t v)
-{
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) {
-        const int lo = __shfl_xor((int)(uint32_t)v, off);
-        const int hi = __shfl_xor((int)(uint32_t)((uint64_t)v >> 32), off);
-        v += (int64_t)(((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
-    }
-    return uni64(v);
 }
 
 // Fields and energies of the solution in S.xm computed from scratch:
@@ -523,17 +323,6 @@ __device__ __forceinline__ void init_replica(Desc *Dp, Replica<NS> &S, int r, in
     fields_from_scratch<NS, PV>(Dp, S, lane);
 }
 
-// Acceptance rule (template argument AM): strict (Eq. pacceptms) or lenient
-// (Eq. pacceptml).
-enum : int { kAmStrict = 0, kAmLenient = 1 };
-
-// Index into the temperature tables for step t (the schedule is constant after
-// its last entry).
-__device__ __forceinline__ uint32_t table_index(uint32_t t, uint32_t ntab)
-{
-    return ((t < ntab) ? t : ntab) - 1u;
-}
-
 // One annealing step t of replica r whose largest acceptance threshold
 // (T_t * LNT[0]) >> 24 is thrmax.  Returns the flipped bit or -1.
 template <int NS, int PV, int AM, class LP>
@@ -714,17 +503,6 @@ __device__ __forceinline__ void run_replica(Desc *Dp, int r, int lane, const MDA
         thr = thr_next;
     }
     export_replica<NS>(Dp, S, r, lane);
-}
-
-__device__ __forceinline__ int path_variant(Desc *Dp)
-{
-    return Dp->path == kPathDense ? kPvDense : (Dp->kform == kKronGen ? kPvKronGen : kPvKronSym);
-}
-
-// Update path and acceptance rule of a run, as one switch value.
-__device__ __forceinline__ int step_variant(Desc *Dp)
-{
-    return path_variant(Dp) * 2 + (Dp->accept != 0 ? kAmLenient : kAmStrict);
 }
 
 #define MDA_STEP_VARIANTS(X)                                                                          \
@@ -930,18 +708,19 @@ __global__ void __launch_bounds__(256) k_front_gather(const int64_t *archE, cons
 }
 
 // Dense P_k of the bQAP QUBO built on the device.  Row a = (i, u) is stored
-// as n blocks of kLD entries, P[a][(j, v)] at j * kLD + v, zero for v >= n:
+// as n blocks of ld entries, P[a][(j, v)] at j * ld + v, zero for v >= n
+// (ld = n: the plain m x m layout):
 // P[a][b] = F[i][j] D[u][v] + F[j][i] D[v][u] + 2 alpha [(i == j) != (u == v)]
 // off the diagonal, F[i][i] D[u][u] - 2 alpha on it.
-__global__ void k_build_dense(int n, const int32_t *__restrict__ F, const int32_t *__restrict__ Dm,
+__global__ void k_build_dense(int n, int ld, const int32_t *__restrict__ F, const int32_t *__restrict__ Dm,
                               int32_t two_alpha, int32_t *__restrict__ P)
 {
     const int m = n * n;
-    const size_t row = (size_t)n * kLD;
+    const size_t row = (size_t)n * ld;
     const size_t total = (size_t)m * row;
     for (size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x; k < total; k += (size_t)gridDim.x * blockDim.x) {
         const int a = (int)(k / row);
-        const int j = (int)((k % row) / kLD), v = (int)(k % kLD);
+        const int j = (int)((k % row) / ld), v = (int)(k % ld);
         if (v >= n) {
             P[k] = 0;
             continue;
@@ -1023,13 +802,13 @@ hipError_t launch_front_gather(const int64_t *archE, const uint8_t *nd, const in
     return hipGetLastError();
 }
 
-hipError_t launch_build_dense(int n, const int32_t *F, const int32_t *Dm, int32_t two_alpha, int32_t *P,
+hipError_t launch_build_dense(int n, int ld, const int32_t *F, const int32_t *Dm, int32_t two_alpha, int32_t *P,
                               hipStream_t stream)
 {
-    const size_t total = (size_t)n * n * n * kLD;
+    const size_t total = (size_t)n * n * n * ld;
     size_t blocks = (total + 255) / 256;
     if (blocks > 65536) blocks = 65536;
-    hipLaunchKernelGGL(k_build_dense, dim3((unsigned)blocks), dim3(256), 0, stream, n, F, Dm, two_alpha, P);
+    hipLaunchKernelGGL(k_build_dense, dim3((unsigned)blocks), dim3(256), 0, stream, n, ld, F, Dm, two_alpha, P);
     return hipGetLastError();
 }
 

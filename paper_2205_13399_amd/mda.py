@@ -51,7 +51,7 @@ class Params(C.Structure):
                 ("beta", C.c_int64), ("accept", C.c_int32), ("archive", C.c_int32),
                 ("escape", C.c_int32), ("variant", C.c_int32), ("seed", C.c_uint64),
                 ("trace_replicas", C.c_int32), ("waves_per_block", C.c_int32),
-                ("stream", C.c_void_p), ("graph", C.c_int32), ("reserved", C.c_int32)]
+                ("stream", C.c_void_p), ("graph", C.c_int32), ("waves_per_replica", C.c_int32)]
 
 
 class ArchiveOut(C.Structure):
@@ -135,16 +135,28 @@ def _ptr(a: np.ndarray):
 
 # ---------------------------------------------------------------- allocator
 
+# Callbacks handed to the library stay alive for the life of the process: every
+# device buffer keeps the release function it was allocated with, so a buffer
+# allocated under one allocator is released through it even after another one
+# has been installed.
 _alloc_keep = []
+_torch_installed = None
 
 
 def use_torch_allocator():
-    """Routes the library's device allocations through PyTorch's caching allocator."""
+    """Routes the library's device allocations through PyTorch's caching
+    allocator, on the stream the library names (idempotent)."""
+    global _torch_installed
     import torch
+
+    if _torch_installed is not None:
+        _check(lib().mda_set_allocator(_torch_installed[0], _torch_installed[1], None))
+        return
 
     def _alloc(nbytes, stream, ctx):
         try:
-            return int(torch.cuda.caching_allocator_alloc(int(nbytes), stream=torch.cuda.current_stream()))
+            s = torch.cuda.ExternalStream(stream) if stream else torch.cuda.current_stream()
+            return int(torch.cuda.caching_allocator_alloc(int(nbytes), stream=s))
         except Exception:
             return None
 
@@ -155,13 +167,13 @@ def use_torch_allocator():
             pass
 
     fa, ff = ALLOC_FN(_alloc), FREE_FN(_free)
-    _alloc_keep[:] = [fa, ff]
+    _alloc_keep.extend([fa, ff])
+    _torch_installed = (fa, ff)
     _check(lib().mda_set_allocator(fa, ff, None))
 
 
 def use_hip_allocator():
     _check(lib().mda_set_allocator(ALLOC_FN(), FREE_FN(), None))
-    _alloc_keep.clear()
 
 
 def current_stream_handle() -> Optional[int]:
@@ -234,7 +246,7 @@ def make_params(replicas: int, steps: int, seed: int, *, archive_size: int = 0,
                 delta0: float = 0.0, deltaf: float = 0.0, xi: float = 0.001, beta: int = -1,
                 accept: int = STRICT, archive: int = EXPLORE, escape: int = ESC_OFFSET,
                 variant: int = VARIANT_AUTO, trace_replicas: int = 0, waves_per_block: int = 0,
-                stream: Optional[int] = None, graph: bool = False) -> Params:
+                stream: Optional[int] = None, graph: bool = False, waves_per_replica: int = 0) -> Params:
     p = Params()
     lib().mda_params_default(C.byref(p))
     p.replicas = int(replicas)
@@ -252,6 +264,7 @@ def make_params(replicas: int, steps: int, seed: int, *, archive_size: int = 0,
     p.trace_replicas = int(trace_replicas)
     p.waves_per_block = int(waves_per_block)
     p.graph = 1 if graph else 0
+    p.waves_per_replica = int(waves_per_replica)
     s = current_stream_handle() if stream is None else stream
     p.stream = C.c_void_p(s) if s else None
     return p

@@ -65,3 +65,16 @@ def test_errors_without_device(mda):
     assert mda.lib().archive_get(None, 0, 0, None, None) == mda.MDA_EINVAL
     mda.lib().da_run_free(None)
     mda.lib().qubo_free(None)
+
+
+def test_torch_allocator_installed_once(mda):
+    """Every device buffer keeps the release callback it was allocated with, so
+    installing the allocator again must not drop the callbacks already handed out."""
+    pytest.importorskip("torch")
+    mda.use_torch_allocator()
+    first = mda._torch_installed
+    kept = len(mda._alloc_keep)
+    mda.use_hip_allocator()
+    mda.use_torch_allocator()
+    assert mda._torch_installed is first
+    assert len(mda._alloc_keep) == kept and all(f in mda._alloc_keep for f in first)

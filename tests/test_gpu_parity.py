@@ -138,3 +138,15 @@ def test_merged_archive(mda):
     for k in range(len(got)):
         x = np.array([(got.xbits[k, a >> 5] >> (a & 31)) & 1 for a in range(64)], np.uint8)
         assert got.feasible[k] == (oracle.constraint_direct(8, x) == 0)
+
+
+def test_free_after_allocator_reinstalled(mda):
+    """A run allocated before the allocator is installed again is released
+    through the callbacks it was allocated with."""
+    import gc
+    inst = synth.make_instance(5, 0.0, seed=1)
+    q, run = _run(mda, inst, 2, 50, 1, trace=0)
+    mda.use_hip_allocator()
+    mda.use_torch_allocator()
+    del run, q
+    gc.collect()

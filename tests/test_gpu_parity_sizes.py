@@ -73,8 +73,16 @@ def test_n64_largest(mda):
     _check(mda, inst, 3, 2000, 64, 2)
 
 
-def test_n65_rejected(mda):
-    inst = synth.make_instance(65, 0.0, seed=65)
+def test_n101_rejected(mda):
+    inst = synth.make_instance(101, 0.0, seed=101)
     with pytest.raises(mda.MdaError) as e:
         mda.Qubo(inst.F1, inst.F2, inst.D)
+    assert e.value.code == mda.MDA_EINVAL
+
+
+def test_one_wave_beyond_64_rejected(mda):
+    inst = synth.make_instance(65, 0.0, seed=65)
+    q = mda.Qubo(inst.F1, inst.F2, inst.D, path=2)
+    with pytest.raises(mda.MdaError) as e:
+        mda.da_run(q, mda.make_params(2, 10, 1, waves_per_replica=1))
     assert e.value.code == mda.MDA_EINVAL
