@@ -206,6 +206,67 @@ int mda_set_allocator(mda_alloc_fn alloc, mda_free_fn release, void *ctx);
 
 const char *mda_last_error(void);
 
+/*
+ * Device bytes a run of an n-facility instance with parameters p (and the QUBO
+ * built with opts) holds: replica state, archives (Table param size s = m by
+ * default), tables and operands.  Host only.  Negative MDA_E* on bad input.
+ */
+int64_t mda_footprint(int32_t n, const mda_params *p, const mda_build_opts *opts);
+
+/* ---------------- serving engine ----------------
+ *
+ * Clients submit bQAP solves (the problem statement of Sec. 2.1: F1, F2, D)
+ * at any time.  A scheduler thread admits pending requests in arrival order
+ * while their footprint (mda_footprint) fits the memory budget, and packs
+ * every admitted request -- any mix of n -- into one batched launch on one of
+ * max_inflight streams, so requests arriving while others run are launched
+ * beside them.  A result stays on the device until collected with
+ * mda_server_wait; it is identical to da_run of the same instance,
+ * parameters and seed.  The server allocates stream-ordered device memory of
+ * its own (not through mda_set_allocator).  Runs handed to the client may be
+ * freed before or after mda_server_destroy: the server's streams stay valid
+ * for the life of the process.
+ */
+typedef struct mda_server mda_server;
+
+typedef struct {
+    int64_t hbm_budget;      /* device bytes admitted requests may hold; <= 0: half the free memory */
+    int32_t max_inflight;    /* launches (streams) in flight, 1..8; 0 = 4 */
+    int32_t max_batch;       /* requests per launch; 0 = 64 */
+    int32_t device;          /* HIP device; < 0 = the current one */
+    int32_t reserved;        /* 0 */
+} mda_server_opts;
+
+typedef struct {
+    int64_t ticket;
+    int32_t n;
+    int32_t status;          /* 2 = done, negative MDA_E* = failed */
+    double t_submit, t_admit, t_launch, t_done;   /* seconds since the server started */
+    int64_t bit_trials;      /* replicas * n^2 * steps */
+    int64_t footprint;       /* device bytes accounted to the request */
+    int32_t batch;           /* requests in its launch */
+    int32_t reserved;
+} mda_request_info;
+
+typedef struct {
+    int64_t launches, completed, bit_trials;
+    int64_t pending, in_flight;
+    int64_t hbm_used, hbm_budget;
+    double now, first_launch, last_done;   /* seconds since the server started */
+} mda_server_counters;
+
+int mda_server_create(const mda_server_opts *opts, mda_server **out);
+/* Copies the instance; p->stream and p->graph are ignored; steps and replicas must be set. */
+int mda_server_submit(mda_server *s, int32_t n, const int32_t *F1, const int32_t *F2, const int32_t *D,
+                      const mda_build_opts *opts, const mda_params *p, int64_t *ticket);
+/* Waits up to timeout_s (< 0: no limit) for the request; on success hands its run to the caller
+ * (NULL run: freed at once) and fills info.  MDA_EBUSY on timeout (the ticket stays valid); the
+ * request's own error code if it failed.  A ticket is collected once. */
+int mda_server_wait(mda_server *s, int64_t ticket, double timeout_s, mda_run **run, mda_request_info *info);
+int mda_server_stats(mda_server *s, mda_server_counters *st);
+/* Fails requests not yet admitted, waits for launched ones, frees uncollected results. */
+void mda_server_destroy(mda_server *s);
+
 /* Debug/verification exports: the library's own host tables. */
 int mda_threshold_table(int32_t *lnt4096);
 int mda_temperature_table(double delta0, double deltaf, double xi, int64_t steps, int64_t *T);

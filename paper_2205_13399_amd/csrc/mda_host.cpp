@@ -15,6 +15,7 @@
 
 #include "mda.h"
 #include "mda_desc.h"
+#include "mda_internal.h"
 
 namespace mda {
 int ns_for(int n);
@@ -80,12 +81,18 @@ extern "C" int mda_set_allocator(mda_alloc_fn alloc, mda_free_fn release, void *
 
 namespace {
 
+// Allocation mode of the calling thread: the serving engine's scheduler
+// allocates stream-ordered (hipMallocAsync), so that releasing one request's
+// memory never waits for the other requests' work on the device.
+static thread_local bool tl_stream_ordered = false;
+
 struct DevBuf {
     void *p = nullptr;
     size_t bytes = 0;
     hipStream_t stream = nullptr;
     mda_free_fn release = nullptr;
     void *ctx = nullptr;
+    bool async = false;
 };
 
 struct DevPool {
@@ -100,7 +107,10 @@ struct DevPool {
         bytes = (bytes + 255) & ~(size_t)255;
         void *p = nullptr;
         DevBuf b;
-        if (g_alloc) {
+        if (tl_stream_ordered) {
+            if (hipMallocAsync(&p, bytes, stream) != hipSuccess) p = nullptr;
+            b.async = true;
+        } else if (g_alloc) {
             p = g_alloc(bytes, (void *)stream, g_ctx);
             b.release = g_release;
             b.ctx = g_ctx;
@@ -119,7 +129,8 @@ struct DevPool {
     void release_all()
     {
         for (auto &b : bufs) {
-            if (b.release) b.release(b.p, b.bytes, (void *)b.stream, b.ctx);
+            if (b.async) (void)hipFreeAsync(b.p, b.stream);
+            else if (b.release) b.release(b.p, b.bytes, (void *)b.stream, b.ctx);
             else (void)hipFree(b.p);
         }
         bufs.clear();
@@ -187,8 +198,9 @@ struct mda_qubo {
 
 static void qubo_release(mda_qubo *q)
 {
+    // every run synchronises its stream before it drops its reference, and the
+    // build waits for its uploads, so nothing on the device still reads q here
     if (--q->refs == 0) {
-        (void)hipDeviceSynchronize();
         q->pool.release_all();
         delete q;
     }
@@ -425,7 +437,9 @@ struct Launch {
     hipGraphExec_t graph_exec = nullptr;
     ~Launch()
     {
-        if (stream || ev0) (void)hipStreamSynchronize(stream);
+        // wait for this launch only (its last event), not for later work on the stream
+        if (ev1) (void)hipEventSynchronize(ev1);
+        else if (stream || ev0) (void)hipStreamSynchronize(stream);
         if (graph_exec) (void)hipGraphExecDestroy(graph_exec);
         if (graph) (void)hipGraphDestroy(graph);
         if (ev0) (void)hipEventDestroy(ev0);
@@ -448,7 +462,10 @@ struct mda_run {
     bool merged_ok = false;
     ~mda_run()
     {
-        if (launch) (void)hipStreamSynchronize(launch->stream);
+        if (launch) {
+            if (launch->ev1) (void)hipEventSynchronize(launch->ev1);
+            else (void)hipStreamSynchronize(launch->stream);
+        }
         pool.release_all();
         launch.reset();
         if (q) qubo_release(q);
@@ -1006,4 +1023,59 @@ extern "C" int archive_get(mda_run *r, int32_t replica, int32_t raw, mda_archive
         }
     }
     return MDA_OK;
+}
+
+// ---------------------------------------------------------------- internal (serving engine)
+
+namespace mda {
+
+void set_stream_ordered_alloc(bool on)
+{
+    tl_stream_ordered = on;
+}
+
+int run_finished(mda_run *r)
+{
+    if (!r || !r->launch || !r->launch->ev1) return -1;
+    const hipError_t e = hipEventQuery(r->launch->ev1);
+    if (e == hipSuccess) return 1;
+    if (e == hipErrorNotReady) return 0;
+    return -1;
+}
+
+int set_error(int code, const char *msg)
+{
+    return fail(code, "%s", msg);
+}
+
+int64_t qubo_device_bytes(const mda_qubo *q)
+{
+    return q->pool.total;
+}
+
+}  // namespace mda
+
+extern "C" int64_t mda_footprint(int32_t n, const mda_params *p, const mda_build_opts *bo)
+{
+    if (n < 2 || n > 100 || !p) return fail(MDA_EINVAL, "bad footprint query");
+    const int64_t m = (int64_t)n * n;
+    const int64_t R = p->replicas > 0 ? p->replicas : 1;
+    const int64_t s = p->archive_size > 0 ? p->archive_size : m;
+    const int64_t steps = p->steps > 0 ? p->steps : (int64_t)std::llround(0.25 * (double)m * (double)m);
+    const int wc = (n + 63) / 64;
+    const bool group = p->waves_per_replica > 1 || (p->waves_per_replica == 0 && n > kMaxWaveN);
+    const int G = group ? (p->waves_per_replica > 1 ? p->waves_per_replica : 2 * wc) : 1;
+    const int64_t xw = group ? (int64_t)G * 64 : n, xrw = group ? (int64_t)G * 64 : 64;
+    // run: x, fields, statistics, archive energies, solutions and flags, tables, trace
+    int64_t b = R * (xrw * 8 + 2 * m * 4 + kStWords * 8) + R * s * (16 + xw * 8 + 1);
+    b += steps * 12 + 65536;
+    if (p->trace_replicas > 0) b += (int64_t)p->trace_replicas * steps * 4;
+    // QUBO: dense rows when the build will pick them, the per-lane operands
+    const mda_build_opts o = bo ? *bo : mda_build_opts{MDA_PEN_2MAX, MDA_PATH_AUTO, 0};
+    const int64_t budget = o.dense_budget > 0 ? o.dense_budget : (int64_t)2 << 30;
+    const int64_t pld = n <= kMaxWaveN ? kLD : n, ldk = n <= kMaxWaveN ? kLD : 2 * kLD;
+    const int64_t dense = 8 * m * n * pld;
+    const bool use_dense = o.path == MDA_PATH_DENSE || (o.path == MDA_PATH_AUTO && dense <= budget);
+    b += (use_dense ? dense + 3 * m * 4 : 0) + 6 * (int64_t)n * ldk * 4 + 2 * std::max<int64_t>(n, kMaxWaveN) * ldk * 4;
+    return b;
 }

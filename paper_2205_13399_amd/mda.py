@@ -66,6 +66,25 @@ class State(C.Structure):
                 ("scanned", C.c_int64), ("rng_blocks", C.c_int64), ("trace", C.c_void_p)]
 
 
+class ServerOpts(C.Structure):
+    _fields_ = [("hbm_budget", C.c_int64), ("max_inflight", C.c_int32), ("max_batch", C.c_int32),
+                ("device", C.c_int32), ("reserved", C.c_int32)]
+
+
+class RequestInfo(C.Structure):
+    _fields_ = [("ticket", C.c_int64), ("n", C.c_int32), ("status", C.c_int32),
+                ("t_submit", C.c_double), ("t_admit", C.c_double), ("t_launch", C.c_double),
+                ("t_done", C.c_double), ("bit_trials", C.c_int64), ("footprint", C.c_int64),
+                ("batch", C.c_int32), ("reserved", C.c_int32)]
+
+
+class ServerCounters(C.Structure):
+    _fields_ = [("launches", C.c_int64), ("completed", C.c_int64), ("bit_trials", C.c_int64),
+                ("pending", C.c_int64), ("in_flight", C.c_int64), ("hbm_used", C.c_int64),
+                ("hbm_budget", C.c_int64), ("now", C.c_double), ("first_launch", C.c_double),
+                ("last_done", C.c_double)]
+
+
 ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p)
 FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p)
 
@@ -115,13 +134,27 @@ def lib():
     L.mda_threshold_table.restype = C.c_int
     L.mda_temperature_table.argtypes = [C.c_double, C.c_double, C.c_double, i64, vp]
     L.mda_temperature_table.restype = C.c_int
+    L.mda_footprint.argtypes = [i32, C.POINTER(Params), C.POINTER(BuildOpts)]
+    L.mda_footprint.restype = C.c_int64
+    L.mda_server_create.argtypes = [C.POINTER(ServerOpts), C.POINTER(vp)]
+    L.mda_server_create.restype = C.c_int
+    L.mda_server_submit.argtypes = [vp, i32, vp, vp, vp, C.POINTER(BuildOpts), C.POINTER(Params), C.POINTER(i64)]
+    L.mda_server_submit.restype = C.c_int
+    L.mda_server_wait.argtypes = [vp, i64, C.c_double, C.POINTER(vp), C.POINTER(RequestInfo)]
+    L.mda_server_wait.restype = C.c_int
+    L.mda_server_stats.argtypes = [vp, C.POINTER(ServerCounters)]
+    L.mda_server_stats.restype = C.c_int
+    L.mda_server_destroy.argtypes = [vp]
+    L.mda_server_destroy.restype = None
     _lib = L
     return L
 
 
 EXPORTED = ["qubo_build_bqap", "qubo_info", "qubo_free", "mda_params_default", "da_run", "da_run_batch",
             "da_sync", "da_elapsed_ms", "da_kernel_ms", "archive_get", "da_state_get", "da_stats", "da_run_free",
-            "mda_set_allocator", "mda_last_error", "mda_threshold_table", "mda_temperature_table"]
+            "mda_set_allocator", "mda_last_error", "mda_threshold_table", "mda_temperature_table",
+            "mda_footprint", "mda_server_create", "mda_server_submit", "mda_server_wait", "mda_server_stats",
+            "mda_server_destroy"]
 
 
 def _check(rc: int):
@@ -372,3 +405,70 @@ def da_run_batch(qs: Sequence[Qubo], params: Sequence[Params]) -> list:
     outs = (C.c_void_p * k)()
     _check(lib().da_run_batch(harr, parr, k, outs))
     return [Run(C.c_void_p(outs[i]), qs[i], params[i]) for i in range(k)]
+
+
+# ---------------------------------------------------------------- footprint and serving
+
+def footprint(n: int, params: Params, path: int = PATH_AUTO, penalty: int = PEN_2MAX, dense_budget: int = 0) -> int:
+    """mda_footprint: device bytes a run of an n-facility instance holds."""
+    v = int(lib().mda_footprint(int(n), C.byref(params), C.byref(BuildOpts(int(penalty), int(path), int(dense_budget)))))
+    if v < 0:
+        _check(v)
+    return v
+
+
+class _Shape:
+    def __init__(self, n):
+        self.n = n
+        self.m = n * n
+
+
+class Server:
+    """The serving engine: submit solves at any time, collect their runs."""
+
+    def __init__(self, hbm_budget: int = 0, max_inflight: int = 0, max_batch: int = 0, device: int = -1):
+        self._h = C.c_void_p()
+        opts = ServerOpts(int(hbm_budget), int(max_inflight), int(max_batch), int(device), 0)
+        _check(lib().mda_server_create(C.byref(opts), C.byref(self._h)))
+        self._params = {}
+
+    def submit(self, F1, F2, D, params: Params, path: int = PATH_AUTO, penalty: int = PEN_2MAX,
+               dense_budget: int = 0) -> int:
+        F1 = np.ascontiguousarray(F1, np.int32)
+        F2 = np.ascontiguousarray(F2, np.int32)
+        D = np.ascontiguousarray(D, np.int32)
+        n = int(D.shape[0])
+        t = C.c_int64()
+        bo = BuildOpts(int(penalty), int(path), int(dense_budget))
+        _check(lib().mda_server_submit(self._h, n, _ptr(F1), _ptr(F2), _ptr(D), C.byref(bo), C.byref(params),
+                                       C.byref(t)))
+        self._params[int(t.value)] = (n, params)
+        return int(t.value)
+
+    def wait(self, ticket: int, timeout: float = -1.0, keep: bool = True):
+        """Returns (Run or None, info dict); raises MdaError on failure or timeout."""
+        h = C.c_void_p()
+        info = RequestInfo()
+        rc = lib().mda_server_wait(self._h, int(ticket), float(timeout), C.byref(h) if keep else None,
+                                   C.byref(info))
+        _check(rc)
+        n, params = self._params.pop(int(ticket))
+        d = {k: getattr(info, k) for k, _ in RequestInfo._fields_ if k != "reserved"}
+        run = Run(h, _Shape(n), params) if keep else None
+        return run, d
+
+    def stats(self) -> dict:
+        c = ServerCounters()
+        _check(lib().mda_server_stats(self._h, C.byref(c)))
+        return {k: getattr(c, k) for k, _ in ServerCounters._fields_}
+
+    def close(self):
+        if self._h:
+            lib().mda_server_destroy(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -78,3 +78,29 @@ def test_torch_allocator_installed_once(mda):
     mda.use_torch_allocator()
     assert mda._torch_installed is first
     assert len(mda._alloc_keep) == kept and all(f in mda._alloc_keep for f in first)
+
+
+def test_footprint_counts_archives_and_operands(mda):
+    """mda_footprint: replicas x archive slots x (energies + stored solution)
+    dominate; the dense rows are counted only when the build would pick them."""
+    p = mda.make_params(4096, 100000, 1)
+    kron = mda.footprint(50, p, path=mda.PATH_KRON)
+    m = 2500
+    assert kron >= 4096 * m * (16 + 50 * 8)          # archives of every replica
+    assert kron < 4096 * m * (16 + 50 * 8) * 1.2
+    dense = mda.footprint(50, p, path=mda.PATH_DENSE)
+    assert dense - kron >= 8 * m * 50 * 64            # two padded objectives
+    # beyond 64 facilities a solution is stored as 2 x 2 wave blocks of 64 words
+    p100 = mda.make_params(256, 50000, 1)
+    assert mda.footprint(100, p100, path=mda.PATH_KRON) >= 256 * 10000 * (16 + 256 * 8)
+    with pytest.raises(mda.MdaError):
+        mda.footprint(101, p100)
+
+
+def test_server_needs_device(mda):
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("device present")
+    with pytest.raises(mda.MdaError) as e:
+        mda.Server()
+    assert e.value.code == mda.MDA_EDEVICE

@@ -1,0 +1,116 @@
+"""The serving engine: requests of different n submitted at once, staggered,
+or under a memory budget that admits one at a time.  Each served result must
+equal a da_run of the same instance, parameters and seed (trajectories, final
+states, fronts), and one is checked against the oracle directly."""
+import time
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from tests.gpu_common import compare_replica, oracle_kwargs
+from tests.oracle_jobs import run_replicas
+
+pytestmark = pytest.mark.gpu
+
+R, STEPS = 8, 3000
+
+
+@pytest.fixture(scope="module")
+def mda():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2205_13399_amd import mda as m
+    m.use_torch_allocator()
+    return m
+
+
+def _requests():
+    out = []
+    for k, n in enumerate((12, 40, 70, 25, 90, 8)):
+        inst = synth.make_instance(n, 0.5 - 0.2 * k, seed=4_000_000 + k)
+        out.append((inst, 0 if k % 2 == 0 else 2))   # automatic (dense up to the budget) or Kronecker path
+    return out
+
+
+def _same_as_alone(mda, inst, path, run):
+    q = mda.Qubo(inst.F1, inst.F2, inst.D, path=path)
+    alone = mda.da_run(q, mda.make_params(R, STEPS, inst.seed, trace_replicas=R))
+    for r in range(R):
+        a, b = alone.state(r, trace=True), run.state(r, trace=True)
+        assert np.array_equal(a["trace"], b["trace"]), (inst.n, r)
+        assert (a["E1"], a["E2"], a["moves"]) == (b["E1"], b["E2"], b["moves"]), (inst.n, r)
+    fa, fb = alone.archive(-1), run.archive(-1)
+    assert np.array_equal(fa.e1, fb.e1) and np.array_equal(fa.e2, fb.e2) and np.array_equal(fa.xbits, fb.xbits)
+
+
+def _serve(mda, srv, reqs, gap=0.0):
+    tickets = []
+    for inst, path in reqs:
+        tickets.append(srv.submit(inst.F1, inst.F2, inst.D, mda.make_params(R, STEPS, inst.seed, trace_replicas=R),
+                                  path=path))
+        if gap:
+            time.sleep(gap)
+    return [srv.wait(t, timeout=120.0) for t in tickets]
+
+
+def test_mix_at_once(mda):
+    srv = mda.Server()
+    reqs = _requests()
+    got = _serve(mda, srv, reqs)
+    for (inst, path), (run, info) in zip(reqs, got):
+        assert info["status"] == 2 and info["t_done"] >= info["t_launch"] >= info["t_admit"] >= info["t_submit"]
+        _same_as_alone(mda, inst, path, run)
+    st = srv.stats()
+    assert st["completed"] == len(reqs) and st["pending"] == 0
+    srv.close()
+
+
+def test_staggered_arrivals_overlap(mda):
+    srv = mda.Server(max_inflight=4)
+    reqs = _requests()
+    got = _serve(mda, srv, reqs, gap=0.002)
+    for (inst, path), (run, info) in zip(reqs, got):
+        _same_as_alone(mda, inst, path, run)
+    assert srv.stats()["launches"] >= 2
+    srv.close()
+
+
+def test_budget_limits_admission(mda):
+    """With room for the largest request only, it cannot share a launch with
+    the requests admitted before it; memory returns as results are collected."""
+    reqs = _requests()
+    sizes = [mda.footprint(i.n, mda.make_params(R, STEPS, 1, trace_replicas=R), path=p) for i, p in reqs]
+    big = int(np.argmax(sizes))
+    srv = mda.Server(hbm_budget=max(sizes) + 1, max_inflight=4)
+    got = _serve(mda, srv, reqs)
+    for k, ((inst, path), (run, info)) in enumerate(zip(reqs, got)):
+        assert info["footprint"] == sizes[k]
+        _same_as_alone(mda, inst, path, run)
+    assert got[big][1]["batch"] == 1
+    assert srv.stats()["launches"] >= 2 and srv.stats()["hbm_used"] == 0
+    srv.close()
+
+
+def test_oversized_request_fails(mda):
+    inst = synth.make_instance(30, 0.0, seed=30)
+    srv = mda.Server(hbm_budget=1 << 20)
+    t = srv.submit(inst.F1, inst.F2, inst.D, mda.make_params(R, STEPS, 1))
+    with pytest.raises(mda.MdaError) as e:
+        srv.wait(t, timeout=30.0)
+    assert e.value.code == mda.MDA_ENOMEM
+    srv.close()
+
+
+def test_served_request_against_oracle(mda):
+    inst = synth.make_instance(70, -0.3, seed=70)
+    srv = mda.Server()
+    t = srv.submit(inst.F1, inst.F2, inst.D, mda.make_params(3, 2000, inst.seed, trace_replicas=3), path=2)
+    run, info = srv.wait(t, timeout=120.0)
+    oq = oracle.Qubo(inst.F1, inst.F2, inst.D)
+    res = run_replicas(inst.F1, inst.F2, inst.D, range(3), workers=3, **oracle_kwargs(oq, 2000, inst.seed))
+    for r in range(3):
+        compare_replica(run, res[r], r, label="served n=70")
+    srv.close()
