@@ -138,6 +138,84 @@ def cpu_baseline(inst, steps, replicas, cores):
     return wall, {r: (dt, out) for r, dt, out in res}
 
 
+# ---------------------------------------------------------------- serving
+
+SERVE = dict(count=48, n_lo=10, n_hi=100, replicas=256, steps=50_000, config=4)
+
+
+def serve_bench(args, mda):
+    """Poisson stream of bQAP solves through the serving engine: the saturated
+    rate first (everything submitted at once), then arrivals at 0.5, 0.9 and
+    1.2 times it; per-request latency (submission to results on the device)
+    and throughput."""
+    import threading
+    w = dict(SERVE)
+    if args.anneal_steps:
+        w["steps"] = args.anneal_steps
+    if args.replicas:
+        w["replicas"] = args.replicas
+    if args.serve_requests:
+        w["count"] = args.serve_requests
+    insts = synth.mixed_batch(count=w["count"], n_lo=w["n_lo"], n_hi=w["n_hi"], config=w["config"])
+    params = [mda.make_params(w["replicas"], w["steps"], i.seed) for i in insts]
+    srv = mda.Server(max_inflight=4)
+
+    def run_stream(gaps):
+        infos = [None] * len(insts)
+        tickets = [None] * len(insts)
+        ready = threading.Semaphore(0)
+
+        def collect():
+            for k in range(len(insts)):
+                ready.acquire()
+                _, infos[k] = srv.wait(tickets[k], keep=False)
+        th = threading.Thread(target=collect)
+        th.start()
+        start = time.perf_counter()
+        due = 0.0
+        for k, inst in enumerate(insts):
+            due += gaps[k]
+            delay = start + due - time.perf_counter()
+            if delay > 0:
+                time.sleep(delay)
+            tickets[k] = srv.submit(inst.F1, inst.F2, inst.D, params[k])
+            ready.release()
+        th.join()
+        lat = np.array([i["t_done"] - i["t_submit"] for i in infos])
+        span = max(i["t_done"] for i in infos) - min(i["t_submit"] for i in infos)
+        bt = sum(i["bit_trials"] for i in infos)
+        return dict(p50_s=float(np.percentile(lat, 50)), p99_s=float(np.percentile(lat, 99)),
+                    mean_s=float(lat.mean()), span_s=span, bit_trials_per_s=bt / span,
+                    requests_per_s=len(insts) / span,
+                    mean_batch=float(np.mean([i["batch"] for i in infos]))), bt
+
+    # warm-up: compile paths and fill the memory pool
+    _log("serving: warm-up")
+    t = srv.submit(insts[0].F1, insts[0].F2, insts[0].D, mda.make_params(8, 1000, 1))
+    srv.wait(t, keep=False)
+    _log("serving: saturated (%d requests at once)" % len(insts))
+    sat, bt = run_stream(np.zeros(len(insts)))
+    rates = {"saturated": sat}
+    rng = np.random.default_rng(w["config"])
+    for f in (0.5, 0.9, 1.2):
+        lam = f * sat["requests_per_s"]
+        _log("serving: Poisson arrivals at %.2f requests/s (%.1f x saturated)" % (lam, f))
+        res, _ = run_stream(rng.exponential(1.0 / lam, len(insts)))
+        res["arrival_rate"] = lam
+        rates["%.1fx" % f] = res
+    srv.close()
+    out = {
+        "metric": "bit-trials/s", "value": sat["bit_trials_per_s"], "unit": "bit-trials/s", "n_gpus": 1,
+        "steps": 1, "warmup": 1, "ms_per_step": round(sat["span_s"] * 1e3, 3), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "int32", "data": "synthetic",
+        "config": {"workload": "bqap-serve-n10-100", "requests": len(insts), "n": [w["n_lo"], w["n_hi"]],
+                   "replicas": w["replicas"], "anneal_steps": w["steps"], "path": "automatic (dense up to 2 GB)",
+                   "server": "admission by device footprint, up to 4 launches in flight"},
+        "latency": rates,
+    }
+    print(json.dumps(out), flush=True)
+
+
 # ---------------------------------------------------------------- main
 
 def main():
@@ -145,7 +223,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=2, help="timed bench steps")
     ap.add_argument("--warmup", type=int, default=1, help="untimed bench steps")
-    ap.add_argument("--workload", default="bqap-n50-x3-kron", choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default="bqap-n50-x3-kron", choices=sorted(WORKLOADS) + ["bqap-serve-n10-100"])
     ap.add_argument("--anneal-steps", type=int, default=0, help="override the workload's annealing steps")
     ap.add_argument("--replicas", type=int, default=0, help="override the workload's replicas")
     ap.add_argument("--plain", type=int, default=1, help="plain-form comparison runs (0 = none)")
@@ -154,6 +232,7 @@ def main():
     ap.add_argument("--waves-per-block", type=int, default=0)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain device copy of 1 GiB (counter calibration)")
+    ap.add_argument("--serve-requests", type=int, default=0, help="requests of the serving workload")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -167,6 +246,12 @@ def main():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
     from paper_2205_13399_amd import mda
+
+    if args.workload == "bqap-serve-n10-100":
+        torch.cuda.set_device(0)
+        mda.use_torch_allocator()
+        serve_bench(args, mda)
+        return
 
     w = dict(WORKLOADS[args.workload])
     if args.anneal_steps:

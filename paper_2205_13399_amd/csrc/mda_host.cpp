@@ -248,46 +248,121 @@ extern "C" int qubo_build_bqap(int32_t n, const int32_t *F1, const int32_t *F2, 
     const int32_t *Dm = q->D.data();
 
     // Penalty weights (Eq. wqubom): 2 max|C_k|, or Eq. (vermap)/(wvermaa) on the
-    // symmetric form of C_k.
+    // symmetric form of C_k; then the int32 bound on every bit's interactions.
+    // Off the diagonal, entry (a, b) = ((i, u), (j, v)) of the symmetric form is
+    // F[i][j] D[u][v] + F[j][i] D[v][u] (the same for (b, a)), so the scans run
+    // over (i, j, u, v) without divisions; with non-negative F and D the row
+    // sums have closed forms.
+    std::vector<int32_t> DT(nn);
+    for (int u = 0; u < n; ++u)
+        for (int v = 0; v < n; ++v) DT[(size_t)v * n + u] = Dm[(size_t)u * n + v];
+    bool nonneg = true;
+    for (size_t e = 0; e < nn; ++e) nonneg &= q->D[e] >= 0 && q->F1[e] >= 0 && q->F2[e] >= 0;
+    const bool dsym_ = is_symmetric(q->D, n);
     for (int k = 0; k < 2; ++k) {
+        const int32_t *F = Fk[k];
         int64_t mx = 0;
-        for (int a = 0; a < m; ++a)
-            for (int b = a; b < m; ++b) mx = std::max<int64_t>(mx, std::llabs(cost_upper(Fk[k], Dm, n, a, b)));
+        for (int i = 0; i < n; ++i)
+            for (int u = 0; u < n; ++u) mx = std::max<int64_t>(mx, std::llabs((int64_t)F[i * n + i] * Dm[u * n + u]));
+        if (nonneg && dsym_ && is_symmetric(k == 0 ? q->F1 : q->F2, n)) {
+            // off-diagonal entries are 2 F[i][j] D[u][v] over (i, u) != (j, v)
+            int64_t fo = 0, fd = 0, da = 0, dof = 0;
+            for (int i = 0; i < n; ++i)
+                for (int j = 0; j < n; ++j) {
+                    (i == j ? fd : fo) = std::max<int64_t>(i == j ? fd : fo, F[i * n + j]);
+                    da = std::max<int64_t>(da, Dm[i * n + j]);
+                    if (i != j) dof = std::max<int64_t>(dof, Dm[i * n + j]);
+                }
+            mx = std::max(mx, 2 * std::max(fo * da, fd * dof));
+        } else {
+        for (int i = 0; i < n; ++i)
+            for (int j = 0; j < n; ++j) {
+                const int64_t fij = F[i * n + j], fji = F[j * n + i];
+                for (int u = 0; u < n; ++u) {
+                    const int32_t *dr = Dm + (size_t)u * n, *dc = DT.data() + (size_t)u * n;
+                    for (int v = 0; v < n; ++v) {
+                        if (i == j && u == v) continue;
+                        mx = std::max<int64_t>(mx, std::llabs(fij * dr[v] + fji * dc[v]));
+                    }
+                }
+            }
+        }
         q->maxabs = std::max(q->maxabs, mx);
+        // per-bit sums over b != a of the positive and negative parts of C_ab
+        std::vector<int64_t> pos(m, 0), neg(m, 0);
+        std::vector<int64_t> rowF(n, 0), colF(n, 0), rowD(n, 0), colD(n, 0);
+        for (int i = 0; i < n; ++i)
+            for (int j = 0; j < n; ++j) {
+                rowF[i] += F[i * n + j];
+                colF[j] += F[i * n + j];
+                rowD[i] += Dm[i * n + j];
+                colD[j] += Dm[i * n + j];
+            }
+        for (int i = 0; i < n; ++i)
+            for (int u = 0; u < n; ++u) {
+                const int a = i * n + u;
+                const int64_t self = (int64_t)F[i * n + i] * Dm[u * n + u];
+                if (nonneg) {
+                    pos[a] = rowF[i] * rowD[u] + colF[i] * colD[u] - 2 * self;
+                    continue;
+                }
+                int64_t pp = 0, nq = 0;
+                for (int j = 0; j < n; ++j) {
+                    const int64_t fij = F[i * n + j], fji = F[j * n + i];
+                    const int32_t *dr = Dm + (size_t)u * n, *dc = DT.data() + (size_t)u * n;
+                    for (int v = 0; v < n; ++v) {
+                        if (j == i && v == u) continue;
+                        const int64_t c = fij * dr[v] + fji * dc[v];
+                        if (c > 0) pp += c;
+                        else nq -= c;
+                    }
+                }
+                pos[a] = pp;
+                neg[a] = nq;
+            }
         int64_t alpha = 2 * mx;
         if (o.penalty == MDA_PEN_VL) {
             int64_t w = INT64_MIN;
-            for (int a = 0; a < m; ++a) {
-                const int64_t caa = cost_upper(Fk[k], Dm, n, a, a);
-                int64_t neg = -caa, pos = caa;
-                for (int b = 0; b < m; ++b) {
-                    if (b == a) continue;
-                    const int64_t v = cost_upper(Fk[k], Dm, n, std::min(a, b), std::max(a, b));
-                    if (v < 0) neg -= v;
-                    if (v > 0) pos += v;
+            for (int i = 0; i < n; ++i)
+                for (int u = 0; u < n; ++u) {
+                    const int a = i * n + u;
+                    const int64_t caa = (int64_t)F[i * n + i] * Dm[u * n + u];
+                    w = std::max(w, std::max(-caa + neg[a], caa + pos[a]));
                 }
-                w = std::max(w, std::max(neg, pos));
-            }
             alpha = (w + 1) / 2;
         }
         q->alpha[k] = alpha;
         q->q[k] = alpha * 2 * n;
         if (2 * alpha * n >= (int64_t)1 << 29)
             return fail(MDA_EOVERFLOW, "penalty 2*alpha_%d*n = %lld exceeds 2^29", k + 1, (long long)(2 * alpha * n));
-        // Every local field |P_aa + sum_b P_ab x_b| must fit int32.
-        for (int a = 0; a < m; ++a) {
-            const int i = a / n, u = a % n;
-            int64_t s = std::llabs(cost_upper(Fk[k], Dm, n, a, a) - 2 * alpha);
-            for (int b = 0; b < m; ++b) {
-                if (b == a) continue;
-                const int j = b / n, v = b % n;
-                int64_t p = cost_upper(Fk[k], Dm, n, std::min(a, b), std::max(a, b));
-                if ((i == j) != (u == v)) p += 2 * alpha;
-                s += std::llabs(p);
+        // Every local field |P_aa + sum_b P_ab x_b| must fit int32: with the
+        // penalty 2 alpha on the 2 (n - 1) bits sharing a's row or column,
+        // sum_b |P_ab| <= |P_aa| + sum |C_ab| + 4 alpha (n - 1), exact when
+        // no C_ab of those bits is below -2 alpha (always for non-negative
+        // inputs); otherwise the exact sum is taken.
+        for (int i = 0; i < n; ++i)
+            for (int u = 0; u < n; ++u) {
+                const int a = i * n + u;
+                const int64_t self = (int64_t)F[i * n + i] * Dm[u * n + u];
+                int64_t sum = std::llabs(self - 2 * alpha);
+                if (nonneg) {
+                    sum += pos[a] + 4 * alpha * (n - 1);
+                } else {
+                    for (int j = 0; j < n; ++j) {
+                        const int64_t fij = F[i * n + j], fji = F[j * n + i];
+                        const int32_t *dr = Dm + (size_t)u * n, *dc = DT.data() + (size_t)u * n;
+                        for (int v = 0; v < n; ++v) {
+                            if (j == i && v == u) continue;
+                            int64_t c = fij * dr[v] + fji * dc[v];
+                            if ((i == j) != (u == v)) c += 2 * alpha;
+                            sum += std::llabs(c);
+                        }
+                    }
+                }
+                if (sum > INT32_MAX - 1)
+                    return fail(MDA_EOVERFLOW, "objective %d: bit %d has sum |P_ab| = %lld > 2^31-2", k + 1, a,
+                                (long long)sum);
             }
-            if (s > INT32_MAX - 1)
-                return fail(MDA_EOVERFLOW, "objective %d: bit %d has sum |P_ab| = %lld > 2^31-2", k + 1, a, (long long)s);
-        }
     }
     q->diag1.resize(m);
     q->diag2.resize(m);

@@ -79,6 +79,22 @@ def test_vl_penalty(mda):
     _check_all(mda, inst, 4, 2000, 11, path=2, penalty=1)
 
 
+@pytest.mark.parametrize("penalty", [0, 1])
+def test_negative_entries(mda, penalty):
+    """Flows and distances of both signs: the builder's general scans (penalty
+    weight and field bound) against the oracle's, on both update paths."""
+    rng = np.random.default_rng(60 + penalty)
+    n = 7
+    F1 = rng.integers(-40, 60, size=(n, n)).astype(np.int32)
+    F2 = rng.integers(-50, 50, size=(n, n)).astype(np.int32)
+    D = rng.integers(-20, 90, size=(n, n)).astype(np.int32)
+    inst = synth.Instance(n, F1, F2, D, 0.0, 0)
+    for path in (1, 2):
+        q, run, _ = _check_all(mda, inst, 4, 2000, 5 + penalty, path=path, penalty=penalty)
+        oq = oracle.Qubo(F1, F2, D, penalty)
+        assert (q.info().alpha1, q.info().alpha2) == (oq.alpha[0], oq.alpha[1])
+
+
 def test_plain_form_equals_persistent(mda):
     inst = synth.make_instance(9, 0.0, seed=5)
     steps, R = 1200, 5
