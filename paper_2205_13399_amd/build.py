@@ -13,7 +13,7 @@ INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libmda.so")
 BUILD_DIR = os.path.join(HERE, "_build")
 
-SOURCES = ["mda_kernels.hip", "mda_group.hip", "mda_host.cpp", "mda_server.cpp"]
+SOURCES = ["mda_kernels.hip", "mda_group.hip", "mda_front.hip", "mda_host.cpp", "mda_server.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "hipcc")
 ARCH = os.environ.get("MDA_OFFLOAD_ARCH", "gfx950")

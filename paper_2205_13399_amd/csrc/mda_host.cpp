@@ -28,6 +28,9 @@ hipError_t launch_persistent(int ns, const RunDesc *runs, const WorkItem *work, 
 hipError_t launch_plain(int ns, const RunDesc *run, int R, uint32_t steps, const int32_t *lnt, int block,
                         hipStream_t stream);
 hipError_t launch_nondominated(const RunDesc *runs, const WorkItem *work, int nwork, hipStream_t stream);
+size_t front_filter_scratch();
+hipError_t launch_front_filter(const FrontEntry *ent, int64_t count, void *scratch, FrontEntry *out,
+                               unsigned long long *nout, hipStream_t stream);
 hipError_t launch_front_gather(const int64_t *archE, const uint8_t *nd, const int64_t *st, int s, int r0, int nr,
                                const int64_t *offs, FrontEntry *out, hipStream_t stream);
 hipError_t launch_build_dense(int n, int ld, const int32_t *F, const int32_t *Dm, int32_t two_alpha, int32_t *P,
@@ -979,8 +982,24 @@ static int gather_flagged(mda_run *r, int r0, int nr, const std::vector<int64_t>
     if (!doffs || !dout) return fail(MDA_ENOMEM, "device allocation failed for %lld front entries", (long long)total);
     HIP_TRY(hipMemcpyAsync(doffs, offs.data(), offs.size() * sizeof(int64_t), hipMemcpyHostToDevice, s));
     HIP_TRY(launch_front_gather(d.archE, d.nd, d.st, d.s, r0, nr, doffs, dout, s));
-    ent.resize((size_t)total);
-    return copy_d2h(ent.data(), dout, ent.size() * sizeof(FrontEntry), s);
+    if (total < 4096) {
+        ent.resize((size_t)total);
+        return copy_d2h(ent.data(), dout, ent.size() * sizeof(FrontEntry), s);
+    }
+    // many candidates: drop on the device those that an entry of strictly
+    // smaller E1 dominates, copy the rest
+    void *scratch = tmp.pool.alloc<char>(front_filter_scratch(), s);
+    FrontEntry *dkeep = tmp.pool.alloc<FrontEntry>((size_t)total, s);
+    unsigned long long *dn = tmp.pool.alloc<unsigned long long>(1, s);
+    if (!scratch || !dkeep || !dn) return fail(MDA_ENOMEM, "device allocation failed for the front filter");
+    HIP_TRY(launch_front_filter(dout, total, scratch, dkeep, dn, s));
+    unsigned long long kept = 0;
+    int rc = copy_d2h(&kept, dn, sizeof kept, s);
+    if (rc) return rc;
+    if ((int64_t)kept > total) return fail(MDA_EDEVICE, "front filter kept %llu of %lld", kept, (long long)total);
+    ent.resize((size_t)kept);
+    if (kept == 0) return MDA_OK;
+    return copy_d2h(ent.data(), dkeep, ent.size() * sizeof(FrontEntry), s);
 }
 
 extern "C" int archive_get(mda_run *r, int32_t replica, int32_t raw, mda_archive_out *out, int64_t *count)

@@ -72,6 +72,30 @@ def test_n25_dense_equals_kronecker(n25):
     assert np.array_equal(fa.xbits, fb.xbits)
 
 
+def test_n25_front_equals_union_of_archives(n25):
+    """The merged front (filtered on the device, merged on the host) equals the
+    non-dominated set of the union of every replica's raw archive."""
+    inst, R, runs, res = n25
+    e1, e2, rep, slot = [], [], [], []
+    for r in range(R):
+        a = runs[2].archive(r, raw=True, bits=False)
+        e1.append(a.e1)
+        e2.append(a.e2)
+        rep.append(np.full(len(a), r, np.int64))
+        slot.append(np.arange(len(a), dtype=np.int64))
+    e1, e2, rep, slot = map(np.concatenate, (e1, e2, rep, slot))
+    order = np.lexsort((slot, rep, e2, e1))
+    best = np.iinfo(np.int64).max
+    keep = []
+    for k in order:
+        if e2[k] < best:
+            keep.append(k)
+            best = e2[k]
+    f = runs[2].archive(-1, bits=False)
+    assert np.array_equal(f.e1, e1[keep]) and np.array_equal(f.e2, e2[keep])
+    assert np.array_equal(f.replica, rep[keep]) and np.array_equal(f.slot, slot[keep])
+
+
 # ---------------------------------------------------------------- n = 50
 
 @pytest.fixture(scope="module")
