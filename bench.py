@@ -216,6 +216,78 @@ def serve_bench(args, mda):
     print(json.dumps(out), flush=True)
 
 
+# ---------------------------------------------------------------- SB-DA vs MDA
+
+def sbda_vs_mda(args, mda):
+    """The paper's comparison on synthetic instances: MDA (strict, explore) and
+    SB-DA (11 weights), 20 runs each at I_max = 0.25 m^2 steps, Verma-Lewis
+    penalty for both; per run the non-dominated feasible set in (f1, f2),
+    normalised together, its hypervolume and size; and each method's
+    throughput."""
+    import torch
+    from paper_2205_13399_amd import quality, sbda
+    runs = args.replicas or 20
+    n = 20   # the largest size at which the Verma-Lewis weight keeps every field in int32 here
+    m = n * n
+    steps = args.anneal_steps or int(round(0.25 * m * m))
+    insts = [synth.make_instance(n, rho, seed=synth.instance_seed(5, k)) for k, rho in enumerate((-0.75, 0.0, 0.75))]
+    per_inst = []
+    tot = {"mda": [0, 0.0], "sbda": [0, 0.0]}
+    for inst in insts:
+        q = mda.Qubo(inst.F1, inst.F2, inst.D, penalty=mda.PEN_VL, path=mda.PATH_KRON)
+
+        def mda_runs(escape):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            run = mda.da_run(q, mda.make_params(runs, steps, inst.seed, escape=escape))
+            run.sync()
+            dt = time.perf_counter() - t0
+            sets = []
+            for r in range(runs):
+                a = run.archive(r, raw=True, bits=False)
+                pts = (np.stack([a.e1[a.feasible == 1], a.e2[a.feasible == 1]], axis=1) if len(a)
+                       else np.zeros((0, 2)))
+                sets.append(pts[quality.nondominated(pts)] if len(pts) else pts)
+            return sets, dt
+
+        mda_sets, t_mda = mda_runs(mda.ESC_OFFSET)
+        rst_sets, t_rst = mda_runs(mda.ESC_ARCHIVE)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        res = sbda.sbda(inst.F1, inst.F2, inst.D, runs, steps, inst.seed)
+        t_sb = time.perf_counter() - t0
+        sets = mda_sets + rst_sets + res.points
+        qual = quality.compare([s for s in sets if len(s)] or [np.zeros((1, 2))])
+        norm = quality.normaliser([s for s in sets if len(s)])
+        hv = lambda ss: [quality.hypervolume_2d(norm(s)) if len(s) else 0.0 for s in ss]
+        hv_m, hv_r, hv_s = hv(mda_sets), hv(rst_sets), hv(res.points)
+        per_inst.append({"rho": inst.rho,
+                         "mda": {"hv_mean": float(np.mean(hv_m)), "nondominated_mean": float(np.mean([len(s) for s in mda_sets])),
+                                 "seconds": t_mda},
+                         "mda_restart": {"hv_mean": float(np.mean(hv_r)),
+                                         "nondominated_mean": float(np.mean([len(s) for s in rst_sets])), "seconds": t_rst},
+                         "sbda": {"hv_mean": float(np.mean(hv_s)), "nondominated_mean": float(np.mean([len(s) for s in res.points])),
+                                  "seconds": t_sb}})
+        tot["mda"][0] += runs * m * steps
+        tot["mda"][1] += t_mda
+        tot["sbda"][0] += len(res.weights) * runs * m * steps
+        tot["sbda"][1] += t_sb
+        _log("rho %+.2f: MDA hv %.4f (%.1f points/run, %.2f s), MDA restarting from the archive hv %.4f (%.1f), "
+             "SB-DA hv %.4f (%.1f points/run, %.2f s)"
+             % (inst.rho, per_inst[-1]["mda"]["hv_mean"], per_inst[-1]["mda"]["nondominated_mean"], t_mda,
+                per_inst[-1]["mda_restart"]["hv_mean"], per_inst[-1]["mda_restart"]["nondominated_mean"],
+                per_inst[-1]["sbda"]["hv_mean"], per_inst[-1]["sbda"]["nondominated_mean"], t_sb))
+        del qual
+    out = {"metric": "bit-trials/s", "value": tot["sbda"][0] / tot["sbda"][1], "unit": "bit-trials/s", "n_gpus": 1,
+           "steps": 1, "warmup": 0, "ms_per_step": round(tot["sbda"][1] * 1e3, 3), "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "int32", "data": "synthetic",
+           "config": {"workload": "sbda-vs-mda-n20", "n": n, "instances": 3, "runs": runs, "anneal_steps": steps,
+                      "weights": 11, "penalty": "Verma-Lewis"},
+           "mda_bit_trials_per_s": tot["mda"][0] / tot["mda"][1],
+           "quality": per_inst}
+    print(json.dumps(out), flush=True)
+
+
 # ---------------------------------------------------------------- main
 
 def main():
@@ -223,7 +295,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=2, help="timed bench steps")
     ap.add_argument("--warmup", type=int, default=1, help="untimed bench steps")
-    ap.add_argument("--workload", default="bqap-n50-x3-kron", choices=sorted(WORKLOADS) + ["bqap-serve-n10-100"])
+    ap.add_argument("--workload", default="bqap-n50-x3-kron",
+                    choices=sorted(WORKLOADS) + ["bqap-serve-n10-100", "sbda-vs-mda-n20"])
     ap.add_argument("--anneal-steps", type=int, default=0, help="override the workload's annealing steps")
     ap.add_argument("--replicas", type=int, default=0, help="override the workload's replicas")
     ap.add_argument("--plain", type=int, default=1, help="plain-form comparison runs (0 = none)")
@@ -251,6 +324,11 @@ def main():
         torch.cuda.set_device(0)
         mda.use_torch_allocator()
         serve_bench(args, mda)
+        return
+    if args.workload == "sbda-vs-mda-n20":
+        torch.cuda.set_device(0)
+        mda.use_torch_allocator()
+        sbda_vs_mda(args, mda)
         return
 
     w = dict(WORKLOADS[args.workload])

@@ -95,7 +95,7 @@ typedef struct {
  * Errors: MDA_EINVAL (n outside [2, 64] in this build -- the interface admits
  * n <= 100 -- or a NULL array), MDA_EOVERFLOW (some bit's |P_aa| + sum_b |P_ab|
  * exceeds 2^31-2, so its energy difference would not fit int32, or
- * 2 * alpha_k * n >= 2^29), MDA_ENOMEM, MDA_EDEVICE.
+ * 2 * alpha_k * n >= 2^30), MDA_ENOMEM, MDA_EDEVICE.
  */
 int qubo_build_bqap(int32_t n, const int32_t *F1, const int32_t *F2, const int32_t *D,
                     const mda_build_opts *opts, void *stream, mda_qubo **out);

@@ -191,9 +191,10 @@ enum : int { kPvDense = 0, kPvKronSym = 1, kPvKronGen = 2 };
 // Value held by slots beyond n (facilities that do not exist).  Such a slot
 // only ever receives the +-2 alpha_k penalty of flips in its own column, whose
 // sum is 2 alpha_k times the change of that column's occupation, so it stays
-// within [kDead - 2 alpha n, kDead + 2 alpha n] (the host checks 2 alpha n <
-// 2^29); the exact acceptance test masks these slots out, and they are large
-// enough never to pass the cheap "can anything be accepted" test.
+// within [kDead - 2 alpha n, kDead + 2 alpha n], inside (0, 2^31) because the
+// host checks 2 alpha n < 2^30.  The exact acceptance test masks these slots
+// out; their value only decides whether the cheap "can anything be accepted"
+// test passes.
 constexpr int32_t kDead = 1 << 30;
 
 // Wave-wide sum of a per-lane int64.

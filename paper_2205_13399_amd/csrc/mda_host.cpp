@@ -336,8 +336,10 @@ extern "C" int qubo_build_bqap(int32_t n, const int32_t *F1, const int32_t *F2, 
         }
         q->alpha[k] = alpha;
         q->q[k] = alpha * 2 * n;
-        if (2 * alpha * n >= (int64_t)1 << 29)
-            return fail(MDA_EOVERFLOW, "penalty 2*alpha_%d*n = %lld exceeds 2^29", k + 1, (long long)(2 * alpha * n));
+        // slots beyond n hold 2^30 and drift by at most 2 alpha n; below 2^30 the
+        // drift keeps them positive and inside int32
+        if (2 * alpha * n >= (int64_t)1 << 30)
+            return fail(MDA_EOVERFLOW, "penalty 2*alpha_%d*n = %lld exceeds 2^30", k + 1, (long long)(2 * alpha * n));
         // Every local field |P_aa + sum_b P_ab x_b| must fit int32: with the
         // penalty 2 alpha on the 2 (n - 1) bits sharing a's row or column,
         // sum_b |P_ab| <= |P_aa| + sum |C_ab| + 4 alpha (n - 1), exact when

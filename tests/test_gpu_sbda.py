@@ -1,0 +1,52 @@
+"""SB-DA (the scalarisation-based DA) on the same kernels, against the oracle:
+every weight's run bit-exact on the scalarised instance (second objective
+zero, Verma-Lewis penalty), each replica's best solution the oracle archive's
+least-energy entry, and the reported objective values the oracle's QAP costs."""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from tests.gpu_common import compare_replica, oracle_kwargs
+from tests.oracle_jobs import run_replicas
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def mods():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2205_13399_amd import mda, sbda
+    mda.use_torch_allocator()
+    return mda, sbda
+
+
+def test_sbda_against_oracle(mods):
+    mda, sbda = mods
+    inst = synth.make_instance(8, -0.5, seed=88)
+    R, steps, seed = 4, 3000, 123
+    res = sbda.sbda(inst.F1, inst.F2, inst.D, R, steps, seed)
+    zero = np.zeros_like(inst.F1)
+    for w, g in enumerate(res.weights):
+        Fg = sbda.scalarised_flows(inst.F1, inst.F2, g)
+        oq = oracle.Qubo(Fg, zero, inst.D, 1)
+        assert oq.alpha[1] == 0
+        out = run_replicas(Fg, zero, inst.D, range(R), penalty=1, workers=4,
+                           **oracle_kwargs(oq, steps, seed + g, trace=False))
+        for r in range(R):
+            compare_replica(res.runs[w], out[r], r, trace=False, label="SB-DA weight %d" % g)
+            assert np.all(out[r]["arch_e2"] == 0)
+            assert res.best[w, r, 0] == out[r]["arch_e1"].min()
+    for r in range(R):
+        assert len(res.points[r]) >= 1
+        for (f1, f2), perm in zip(res.points[r], res.perms[r]):
+            assert f1 == oracle.qap_cost(inst.F1, inst.D, perm)
+            assert f2 == oracle.qap_cost(inst.F2, inst.D, perm)
+        # mutually non-dominated
+        p = res.points[r]
+        for a in range(len(p)):
+            for b in range(len(p)):
+                if a != b:
+                    assert not (p[b][0] <= p[a][0] and p[b][1] <= p[a][1])
