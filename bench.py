@@ -348,6 +348,14 @@ def main():
          % (args.workload, len(insts), n, R, steps, w["path"]))
     qs = [mda.Qubo(i.F1, i.F2, i.D, path=path) for i in insts]
     params = [mda.make_params(R, steps, i.seed, waves_per_block=args.waves_per_block) for i in insts]
+    tuning = None
+    if not args.waves_per_block:
+        # launch shape from the autotuner (probe runs, outside the timed region)
+        tuning = mda.autotune(qs[0], params[0], probe_steps=2000)
+        params = [mda.tuned(p, tuning) for p in params]
+        _log("autotuner: %d waves per replica, %d waves per block (%s)"
+             % (tuning["waves_per_replica"], tuning["waves_per_block"],
+                ", ".join("%d/%d: %.1f ms" % c for c in tuning["candidates"])))
     torch.cuda.synchronize()
 
     bit_trials_step = len(insts) * R * m * steps
@@ -404,7 +412,10 @@ def main():
         "config": {"workload": args.workload, "n": n, "m": m, "instances": len(insts),
                    "rho": list(w["rhos"]), "replicas": R, "anneal_steps": steps,
                    "path": w["path"], "launch": "persistent, all instances in one launch",
-                   "bit_trials_per_step": bit_trials_step},
+                   "bit_trials_per_step": bit_trials_step,
+                   "launch_shape": ({"waves_per_replica": tuning["waves_per_replica"],
+                                     "waves_per_block": tuning["waves_per_block"], "autotuned": True}
+                                    if tuning else {"waves_per_block": args.waves_per_block})},
         "roofline": roofline,
         "run_stats": {"moves_per_replica": moves / (len(insts) * R),
                       "p_move": moves / (len(insts) * R * steps),

@@ -213,6 +213,32 @@ const char *mda_last_error(void);
  */
 int64_t mda_footprint(int32_t n, const mda_params *p, const mda_build_opts *opts);
 
+/*
+ * Launch-shape autotuner.  Times probe runs (probe_steps steps of at most
+ * probe_replicas replicas, q's update path and p's acceptance rule) for each
+ * shape: one wave per replica (n <= 64) with 1, 2 or 4 waves per block, and
+ * workgroups of 2 or 4 waves per replica where a layout exists; returns the
+ * fastest.  Results are remembered per (n, update path, acceptance rule,
+ * replica count rounded down to a power of two) for the life of the process
+ * (cached = 1 when answered from there).  Launch shapes never change results.
+ * probe_steps < 1: 2000; probe_replicas < 1: all of p->replicas.
+ */
+typedef struct {
+    int32_t waves_per_block;     /* chosen: set in mda_params */
+    int32_t waves_per_replica;   /* chosen: set in mda_params */
+    int32_t candidates;          /* shapes timed */
+    int32_t cached;
+    double best_ms;
+    int64_t probe_steps;
+    int32_t probe_replicas;
+    int32_t reserved;
+    int32_t cand_wpb[16], cand_wpr[16];
+    double probe_ms[16];         /* persistent-kernel time of each candidate */
+} mda_tuning;
+
+int mda_autotune(const mda_qubo *q, const mda_params *p, int64_t probe_steps, int32_t probe_replicas,
+                 mda_tuning *out);
+
 /* ---------------- serving engine ----------------
  *
  * Clients submit bQAP solves (the problem statement of Sec. 2.1: F1, F2, D)

@@ -9,7 +9,9 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <map>
 #include <memory>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -1174,4 +1176,100 @@ extern "C" int64_t mda_footprint(int32_t n, const mda_params *p, const mda_build
     const bool use_dense = o.path == MDA_PATH_DENSE || (o.path == MDA_PATH_AUTO && dense <= budget);
     b += (use_dense ? dense + 3 * m * 4 : 0) + 6 * (int64_t)n * ldk * 4 + 2 * std::max<int64_t>(n, kMaxWaveN) * ldk * 4;
     return b;
+}
+
+// ---------------------------------------------------------------- autotuner
+
+namespace {
+
+struct TuneKey {
+    int32_t n, path, kform, accept, rbucket;
+    bool operator<(const TuneKey &o) const
+    {
+        if (n != o.n) return n < o.n;
+        if (path != o.path) return path < o.path;
+        if (kform != o.kform) return kform < o.kform;
+        if (accept != o.accept) return accept < o.accept;
+        return rbucket < o.rbucket;
+    }
+};
+
+std::mutex g_tune_mu;
+std::map<TuneKey, mda_tuning> g_tune_cache;
+
+}  // namespace
+
+extern "C" int mda_autotune(const mda_qubo *q, const mda_params *pin, int64_t probe_steps, int32_t probe_replicas,
+                            mda_tuning *out)
+{
+    if (!q || !pin || !out) return fail(MDA_EINVAL, "NULL argument");
+    if (probe_steps < 1) probe_steps = 2000;
+    const int n = q->n;
+    int32_t R = pin->replicas;
+    if (probe_replicas > 0 && probe_replicas < R) R = probe_replicas;
+    int rb = 0;
+    while ((1 << (rb + 1)) <= pin->replicas && rb < 30) ++rb;
+    const TuneKey key{n, q->path, q->kform, pin->accept, rb};
+    {
+        std::lock_guard<std::mutex> g(g_tune_mu);
+        auto it = g_tune_cache.find(key);
+        if (it != g_tune_cache.end()) {
+            *out = it->second;
+            out->cached = 1;
+            return MDA_OK;
+        }
+    }
+    std::memset(out, 0, sizeof *out);
+    // candidates: one wave per replica (n <= 64) with 1, 2, 4 waves per block;
+    // workgroups of 2 and 4 waves where a layout exists
+    std::vector<std::pair<int, int>> cand;   // (waves per replica, waves per block)
+    if (n <= kMaxWaveN)
+        for (int wpb : {1, 2, 4}) cand.push_back({1, wpb});
+    const int wc = (n + 63) / 64;
+    for (int g : {2, 4}) {
+        const int wr = std::max(1, g / wc);
+        if (wr * wc != g) continue;
+        const int gns = (((n + wr - 1) / wr + 7) / 8) * 8;
+        if (gns > 64 || g > group_waves_limit(gns)) continue;
+        cand.push_back({g, 0});
+    }
+    if (cand.size() > 16) cand.resize(16);
+    mda_params p = *pin;
+    p.replicas = R;
+    p.steps = probe_steps;
+    p.trace_replicas = 0;
+    p.graph = 0;
+    p.variant = MDA_VARIANT_PERSISTENT;
+    // a first launch loads the code objects; it is not timed
+    for (int pass = 0; pass < 2; ++pass) {
+        for (size_t c = 0; c < cand.size(); ++c) {
+            p.waves_per_replica = cand[c].first;
+            p.waves_per_block = cand[c].second;
+            mda_run *r = nullptr;
+            int rc = da_run(q, &p, &r);
+            if (rc) return rc;
+            double ms = 0;
+            rc = da_kernel_ms(r, &ms);
+            da_run_free(r);
+            if (rc) return rc;
+            if (pass == 1) {
+                out->cand_wpr[c] = cand[c].first;
+                out->cand_wpb[c] = cand[c].second;
+                out->probe_ms[c] = ms;
+            }
+            if (pass == 0) break;   // one warm-up launch is enough
+        }
+    }
+    out->candidates = (int32_t)cand.size();
+    int best = 0;
+    for (int c = 1; c < out->candidates; ++c)
+        if (out->probe_ms[c] < out->probe_ms[best]) best = c;
+    out->waves_per_replica = out->cand_wpr[best];
+    out->waves_per_block = out->cand_wpb[best];
+    out->best_ms = out->probe_ms[best];
+    out->probe_steps = probe_steps;
+    out->probe_replicas = R;
+    std::lock_guard<std::mutex> g(g_tune_mu);
+    g_tune_cache[key] = *out;
+    return MDA_OK;
 }

@@ -66,6 +66,13 @@ class State(C.Structure):
                 ("scanned", C.c_int64), ("rng_blocks", C.c_int64), ("trace", C.c_void_p)]
 
 
+class Tuning(C.Structure):
+    _fields_ = [("waves_per_block", C.c_int32), ("waves_per_replica", C.c_int32), ("candidates", C.c_int32),
+                ("cached", C.c_int32), ("best_ms", C.c_double), ("probe_steps", C.c_int64),
+                ("probe_replicas", C.c_int32), ("reserved", C.c_int32), ("cand_wpb", C.c_int32 * 16),
+                ("cand_wpr", C.c_int32 * 16), ("probe_ms", C.c_double * 16)]
+
+
 class ServerOpts(C.Structure):
     _fields_ = [("hbm_budget", C.c_int64), ("max_inflight", C.c_int32), ("max_batch", C.c_int32),
                 ("device", C.c_int32), ("reserved", C.c_int32)]
@@ -134,6 +141,8 @@ def lib():
     L.mda_threshold_table.restype = C.c_int
     L.mda_temperature_table.argtypes = [C.c_double, C.c_double, C.c_double, i64, vp]
     L.mda_temperature_table.restype = C.c_int
+    L.mda_autotune.argtypes = [vp, C.POINTER(Params), i64, i32, C.POINTER(Tuning)]
+    L.mda_autotune.restype = C.c_int
     L.mda_footprint.argtypes = [i32, C.POINTER(Params), C.POINTER(BuildOpts)]
     L.mda_footprint.restype = C.c_int64
     L.mda_server_create.argtypes = [C.POINTER(ServerOpts), C.POINTER(vp)]
@@ -153,7 +162,7 @@ def lib():
 EXPORTED = ["qubo_build_bqap", "qubo_info", "qubo_free", "mda_params_default", "da_run", "da_run_batch",
             "da_sync", "da_elapsed_ms", "da_kernel_ms", "archive_get", "da_state_get", "da_stats", "da_run_free",
             "mda_set_allocator", "mda_last_error", "mda_threshold_table", "mda_temperature_table",
-            "mda_footprint", "mda_server_create", "mda_server_submit", "mda_server_wait", "mda_server_stats",
+            "mda_autotune", "mda_footprint", "mda_server_create", "mda_server_submit", "mda_server_wait", "mda_server_stats",
             "mda_server_destroy"]
 
 
@@ -472,3 +481,21 @@ class Server:
             self.close()
         except Exception:
             pass
+
+
+def autotune(q: Qubo, params: Params, probe_steps: int = 2000, probe_replicas: int = 0) -> dict:
+    """mda_autotune: the fastest launch shape for q and params (see mda.h)."""
+    t = Tuning()
+    _check(lib().mda_autotune(q.handle, C.byref(params), int(probe_steps), int(probe_replicas), C.byref(t)))
+    k = int(t.candidates)
+    return {"waves_per_block": int(t.waves_per_block), "waves_per_replica": int(t.waves_per_replica),
+            "cached": bool(t.cached), "best_ms": float(t.best_ms),
+            "candidates": [(int(t.cand_wpr[i]), int(t.cand_wpb[i]), float(t.probe_ms[i])) for i in range(k)]}
+
+
+def tuned(params: Params, tuning: dict) -> Params:
+    """A copy of params with the tuned launch shape."""
+    p = Params.from_buffer_copy(params)
+    p.waves_per_block = tuning["waves_per_block"]
+    p.waves_per_replica = tuning["waves_per_replica"]
+    return p
