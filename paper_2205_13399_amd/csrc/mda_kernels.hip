@@ -511,9 +511,13 @@ __device__ __forceinline__ void run_replica(Desc *Dp, int r, int lane, const MDA
 
 // Persistent form: wave w of the grid runs work items w, w + W, w + 2W, ...
 // (W waves in the grid; the host orders the items largest first), each for
-// all of its steps with the replica state in registers.
+// all of its steps with the replica state in registers.  From 40 slots up the
+// kernel would hold one wave per SIMD; it is built for two, which moves part
+// of the cold-path state (initial fields, restarts, archive scans) to scratch
+// and lets a second wave hide the latency of the first (n = 50: 2.45 s ->
+// 1.69 s for the benchmark launch; three waves spill the step's own state).
 template <int NS>
-__global__ void __launch_bounds__(256) k_persistent(const RunDesc *runs, const WorkItem *work, int nwork,
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(NS >= 40 ? 2 : 1))) k_persistent(const RunDesc *runs, const WorkItem *work, int nwork,
                                                     const int32_t *lnt_)
 {
     // the -ln table, read at random by the exact acceptance test, lives in LDS
