@@ -561,8 +561,12 @@ constexpr int group_max_waves()
     return NS <= 16 ? kMaxGroupWaves : 4;
 }
 
-template <int NS>
-__global__ void __launch_bounds__(64 * group_max_waves<NS>()) k_group(const RunDesc *runs, const WorkItem *work, int nwork,
+// OCC = 2 builds (from 24 slots up) keep cold-path state in scratch so that two
+// workgroups share a CU; the host takes them when a launch has more replicas
+// than one workgroup per CU can hold at once (n = 100, 2048 replicas: about a
+// quarter faster; a single round of replicas is faster with OCC = 1).
+template <int NS, int OCC>
+__global__ void __launch_bounds__(64 * group_max_waves<NS>()) __attribute__((amdgpu_waves_per_eu(OCC))) k_group(const RunDesc *runs, const WorkItem *work, int nwork,
                                                const int32_t *lnt_, int WR, int WC)
 {
     __shared__ GroupLds L;
@@ -602,15 +606,24 @@ int group_waves_limit(int ns)
     return ns <= 16 ? kMaxGroupWaves : 4;
 }
 
-hipError_t launch_group(int ns, int wr, int wc, const RunDesc *runs, const WorkItem *work, int nwork,
+static bool group_two(int ns, int occ)
+{
+    return ns >= 24 && occ >= 2;
+}
+
+hipError_t launch_group(int ns, int occ, int wr, int wc, const RunDesc *runs, const WorkItem *work, int nwork,
                         const int32_t *lnt, int grid, hipStream_t stream)
 {
     if (wr < 1 || wc < 1 || wr * wc > group_waves_limit(ns)) return hipErrorInvalidValue;
     const dim3 block(64 * wr * wc);
+    const bool two = group_two(ns, occ);
     switch (ns) {
-#define X(N)                                                                                          \
-    case N:                                                                                           \
-        hipLaunchKernelGGL(k_group<N>, dim3(grid), block, 0, stream, runs, work, nwork, lnt, wr, wc); \
+#define X(N)                                                                                                       \
+    case N:                                                                                                        \
+        if (two)                                                                                                   \
+            hipLaunchKernelGGL((k_group<N, (N >= 24 ? 2 : 1)>), dim3(grid), block, 0, stream, runs, work, nwork, lnt, wr, wc); \
+        else                                                                                                       \
+            hipLaunchKernelGGL((k_group<N, 1>), dim3(grid), block, 0, stream, runs, work, nwork, lnt, wr, wc);     \
         break;
         MDA_GNS_LIST(X)
 #undef X
@@ -620,13 +633,15 @@ hipError_t launch_group(int ns, int wr, int wc, const RunDesc *runs, const WorkI
     return hipGetLastError();
 }
 
-hipError_t group_occupancy(int ns, int wr, int wc, int *blocks_per_cu)
+hipError_t group_occupancy(int ns, int occ, int wr, int wc, int *blocks_per_cu)
 {
     const int threads = 64 * wr * wc;
+    const bool two = group_two(ns, occ);
     switch (ns) {
-#define X(N) \
-    case N:  \
-        return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_group<N>, threads, 0);
+#define X(N)                                                                                                  \
+    case N:                                                                                                   \
+        return two ? hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_group<N, (N >= 24 ? 2 : 1)>, threads, 0) \
+                   : hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_group<N, 1>, threads, 0);
         MDA_GNS_LIST(X)
 #undef X
     default:

@@ -22,10 +22,10 @@
 namespace mda {
 int ns_for(int n);
 int group_waves_limit(int ns);
-hipError_t launch_group(int ns, int wr, int wc, const RunDesc *runs, const WorkItem *work, int nwork,
+hipError_t launch_group(int ns, int occ, int wr, int wc, const RunDesc *runs, const WorkItem *work, int nwork,
                         const int32_t *lnt, int grid, hipStream_t stream);
-hipError_t group_occupancy(int ns, int wr, int wc, int *blocks_per_cu);
-hipError_t launch_persistent(int ns, const RunDesc *runs, const WorkItem *work, int nwork,
+hipError_t group_occupancy(int ns, int occ, int wr, int wc, int *blocks_per_cu);
+hipError_t launch_persistent(int ns, int occ, const RunDesc *runs, const WorkItem *work, int nwork,
                              const int32_t *lnt, int grid, int block, hipStream_t stream);
 hipError_t launch_plain(int ns, const RunDesc *run, int R, uint32_t steps, const int32_t *lnt, int block,
                         hipStream_t stream);
@@ -37,7 +37,7 @@ hipError_t launch_front_gather(const int64_t *archE, const uint8_t *nd, const in
                                const int64_t *offs, FrontEntry *out, hipStream_t stream);
 hipError_t launch_build_dense(int n, int ld, const int32_t *F, const int32_t *Dm, int32_t two_alpha, int32_t *P,
                               hipStream_t stream);
-hipError_t persistent_occupancy(int ns, int block, int *blocks_per_cu);
+hipError_t persistent_occupancy(int ns, int occ, int block, int *blocks_per_cu);
 }  // namespace mda
 
 using namespace mda;
@@ -787,25 +787,38 @@ extern "C" int da_run_batch(const mda_qubo *const *qs, const mda_params *ps, int
             for (const Group &g : groups) {
                 int per_cu = 0;
                 if (g.wr * g.wc == 1) {
-                    HIP_TRY(persistent_occupancy(g.ns, block, &per_cu));
-                    if (per_cu < 1) per_cu = 1;
+                    // one wave per SIMD when that holds every replica of the launch
+                    // at once, the two-wave build when more are waiting
                     const int wpb = block / 64;
+                    HIP_TRY(persistent_occupancy(g.ns, 1, block, &per_cu));
+                    if (per_cu < 1) per_cu = 1;
+                    const int occ = (int64_t)g.cnt > (int64_t)cus * per_cu * wpb ? 2 : 1;
+                    if (occ == 2) {
+                        HIP_TRY(persistent_occupancy(g.ns, 2, block, &per_cu));
+                        if (per_cu < 1) per_cu = 1;
+                    }
                     int grid = cus * per_cu;
                     const int need = (g.cnt + wpb - 1) / wpb;
                     if (grid > need) grid = need;
                     const hipError_t le =
-                        launch_persistent(g.ns, L->ddesc, L->dwork + g.off, g.cnt, L->dlnt, grid, block, stream);
+                        launch_persistent(g.ns, occ, L->ddesc, L->dwork + g.off, g.cnt, L->dlnt, grid, block, stream);
                     if (le != hipSuccess)
                         return fail(MDA_EDEVICE, "persistent launch (ns %d, grid %d, block %d, %d blocks/CU) failed: %s",
                                     g.ns, grid, block, per_cu, hipGetErrorString(le));
                 } else {
-                    // one replica per workgroup of wr x wc waves
-                    HIP_TRY(group_occupancy(g.ns, g.wr, g.wc, &per_cu));
+                    // one replica per workgroup of wr x wc waves; the two-workgroups-per-CU
+                    // build when one per CU cannot hold every replica at once
+                    HIP_TRY(group_occupancy(g.ns, 1, g.wr, g.wc, &per_cu));
                     if (per_cu < 1) per_cu = 1;
+                    const int occ = (int64_t)g.cnt > (int64_t)cus * per_cu ? 2 : 1;
+                    if (occ == 2) {
+                        HIP_TRY(group_occupancy(g.ns, 2, g.wr, g.wc, &per_cu));
+                        if (per_cu < 1) per_cu = 1;
+                    }
                     int grid = cus * per_cu;
                     if (grid > g.cnt) grid = g.cnt;
                     const hipError_t le =
-                        launch_group(g.ns, g.wr, g.wc, L->ddesc, L->dwork + g.off, g.cnt, L->dlnt, grid, stream);
+                        launch_group(g.ns, occ, g.wr, g.wc, L->ddesc, L->dwork + g.off, g.cnt, L->dlnt, grid, stream);
                     if (le != hipSuccess)
                         return fail(MDA_EDEVICE, "workgroup launch (ns %d, %d x %d waves, grid %d, %d blocks/CU) failed: %s",
                                     g.ns, g.wr, g.wc, grid, per_cu, hipGetErrorString(le));

@@ -512,12 +512,14 @@ __device__ __forceinline__ void run_replica(Desc *Dp, int r, int lane, const MDA
 // Persistent form: wave w of the grid runs work items w, w + W, w + 2W, ...
 // (W waves in the grid; the host orders the items largest first), each for
 // all of its steps with the replica state in registers.  From 40 slots up the
-// kernel would hold one wave per SIMD; it is built for two, which moves part
-// of the cold-path state (initial fields, restarts, archive scans) to scratch
-// and lets a second wave hide the latency of the first (n = 50: 2.45 s ->
-// 1.69 s for the benchmark launch; three waves spill the step's own state).
-template <int NS>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(NS >= 40 ? 2 : 1))) k_persistent(const RunDesc *runs, const WorkItem *work, int nwork,
+// kernel holds one wave per SIMD (OCC = 1); the OCC = 2 build keeps part of the
+// cold-path state (initial fields, restarts, archive scans) in scratch so that
+// a second wave per SIMD hides the latency of the first.  The host takes it
+// when a launch has more replicas than one wave per SIMD can hold at once
+// (n = 50 benchmark launch: 2.45 s -> 1.69 s; three waves spill the step's
+// own state and are slower).
+template <int NS, int OCC>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(OCC))) k_persistent(const RunDesc *runs, const WorkItem *work, int nwork,
                                                     const int32_t *lnt_)
 {
     // the -ln table, read at random by the exact acceptance test, lives in LDS
@@ -746,19 +748,30 @@ __global__ void k_build_dense(int n, int ld, const int32_t *__restrict__ F, cons
 
 #define MDA_NS_LIST(X) X(8) X(16) X(24) X(32) X(40) X(48) X(56) X(64)
 
+// Tiles with a two-waves-per-SIMD build (below 40 slots the kernel holds two
+// or more waves per SIMD by itself).
+static int occ_for(int ns, int occ)
+{
+    return (ns >= 40 && occ >= 2) ? 2 : 1;
+}
+
 int ns_for(int n)
 {
     const int ns = ((n + 7) / 8) * 8;
     return ns < 8 ? 8 : ns;
 }
 
-hipError_t launch_persistent(int ns, const RunDesc *runs, const WorkItem *work, int nwork, const int32_t *lnt,
-                             int grid, int block, hipStream_t stream)
+hipError_t launch_persistent(int ns, int occ, const RunDesc *runs, const WorkItem *work, int nwork,
+                             const int32_t *lnt, int grid, int block, hipStream_t stream)
 {
+    const bool two = occ_for(ns, occ) == 2;
     switch (ns) {
-#define X(N)                                                                                          \
-    case N:                                                                                           \
-        hipLaunchKernelGGL(k_persistent<N>, dim3(grid), dim3(block), 0, stream, runs, work, nwork, lnt); \
+#define X(N)                                                                                                  \
+    case N:                                                                                                   \
+        if (two)                                                                                              \
+            hipLaunchKernelGGL((k_persistent<N, (N >= 40 ? 2 : 1)>), dim3(grid), dim3(block), 0, stream, runs, work, nwork, lnt); \
+        else                                                                                                  \
+            hipLaunchKernelGGL((k_persistent<N, 1>), dim3(grid), dim3(block), 0, stream, runs, work, nwork, lnt); \
         break;
         MDA_NS_LIST(X)
 #undef X
@@ -816,12 +829,14 @@ hipError_t launch_build_dense(int n, int ld, const int32_t *F, const int32_t *Dm
     return hipGetLastError();
 }
 
-hipError_t persistent_occupancy(int ns, int block, int *blocks_per_cu)
+hipError_t persistent_occupancy(int ns, int occ, int block, int *blocks_per_cu)
 {
+    const bool two = occ_for(ns, occ) == 2;
     switch (ns) {
-#define X(N) \
-    case N:  \
-        return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_persistent<N>, block, 0);
+#define X(N)                                                                                                   \
+    case N:                                                                                                    \
+        return two ? hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_persistent<N, (N >= 40 ? 2 : 1)>, block, 0) \
+                   : hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_persistent<N, 1>, block, 0);
         MDA_NS_LIST(X)
 #undef X
     default:
