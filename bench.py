@@ -64,8 +64,9 @@ OPS_PER_BIT_TRIAL = 2
 OPS_PER_MOVE_BIT = 6
 OPS_PER_PHILOX = 100
 
-KERNEL_SOURCES = ("paper_2205_13399_amd/csrc/mda_kernels.hip", "paper_2205_13399_amd/csrc/mda_desc.h",
-                  "paper_2205_13399_amd/csrc/mda_device.h")
+# sources of the persistent kernel (the per-tile translation units only name a tile)
+KERNEL_SOURCES = ("paper_2205_13399_amd/csrc/mda_wave.h", "paper_2205_13399_amd/csrc/mda_wave_tile.h",
+                  "paper_2205_13399_amd/csrc/mda_device.h", "paper_2205_13399_amd/csrc/mda_desc.h")
 
 
 def _log(msg):

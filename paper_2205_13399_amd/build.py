@@ -13,7 +13,9 @@ INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libmda.so")
 BUILD_DIR = os.path.join(HERE, "_build")
 
-SOURCES = ["mda_kernels.hip", "mda_group.hip", "mda_front.hip", "mda_host.cpp", "mda_server.cpp"]
+SOURCES = (["mda_wave_ns%d.hip" % t for t in (64, 56, 48, 40)] + ["mda_group_ns%d.hip" % t for t in (64, 56, 48, 40)]
+           + ["mda_wave_ns%d.hip" % t for t in (32, 24, 16, 8)] + ["mda_group_ns%d.hip" % t for t in (32, 24, 16, 8)]
+           + ["mda_kernels.hip", "mda_group.hip", "mda_front.hip", "mda_host.cpp", "mda_server.cpp"])
 
 HIPCC = os.environ.get("HIPCC", "hipcc")
 ARCH = os.environ.get("MDA_OFFLOAD_ARCH", "gfx950")
@@ -39,7 +41,8 @@ def _compile(src: str) -> str:
 def build(verbose: bool = False) -> str:
     """Compiles every source and links ``libmda.so`` (always rebuilds)."""
     os.makedirs(BUILD_DIR, exist_ok=True)
-    with ThreadPoolExecutor(max_workers=len(SOURCES)) as ex:
+    workers = max(1, min(len(SOURCES), int(os.environ.get("MAX_JOBS", os.cpu_count() or 4))))
+    with ThreadPoolExecutor(max_workers=workers) as ex:
         objs = list(ex.map(_compile, SOURCES))
     tmp = LIB + ".tmp%d" % os.getpid()
     cmd = [HIPCC, "-shared", "-fPIC", "--offload-arch=" + ARCH, "-o", tmp, *objs]

@@ -1,0 +1,656 @@
+// mda_wave.h -- one-wave-per-replica kernels of the multi-objective Digital Annealer
+// (Ayodele et al., GECCO 2022, arXiv:2205.13399) on the bi-objective QAP.
+//
+// Layout: one replica per wave64.  Lane u holds location u; register slot i
+// holds facility i, so bit a = i*n + u lives in slot i of lane u (n <= 64).
+// Each lane keeps the two energy differences dE_1[a], dE_2[a] of its bits
+// (Eq. cale with the sign (1 - 2 x_a) folded in) and its column of x as a
+// 64-bit mask.  All arithmetic is integer: int32 differences (bounded by the
+// build-time row check), int64 energies, offset and thresholds.
+//
+// One annealing step (Algorithm 3, with the offset of Algorithm 1):
+//  1. per lane: min over its slots of max(dE_1, dE_2) (strict) or
+//     min(dE_1, dE_2) (lenient); one ballot tells whether any bit can be
+//     accepted at all (dE <= E_offset + the largest threshold of this step);
+//  2. only then: exact acceptance per bit, drawing the Philox block of a group
+//     of eight facilities only when some bit of it is neither certainly
+//     accepted (S = 0) nor certainly rejected (S > largest threshold);
+//  3. uniform choice of one accepted bit in ascending bit order (scalar);
+//  4. field update: dense rows of P_k from HBM, or the Kronecker column
+//     rebuilt from F_k, D and alpha_k with 24-bit multiply-adds;
+//  5. archive update (Algorithm 4 or 5) against the archive in HBM.
+// The random stream is counter-based on (seed, step, replica, bit group), so
+// the result does not depend on the launch shape or on which draws are skipped.
+#pragma once
+
+#include "mda_device.h"
+
+namespace mda {
+
+// Flips bit (js, jl) whose current differences are d1, d2: E_k += dE_k(j);
+// for every other bit a, dE_k[a] += (x_a == x_j ? +1 : -1) * P_k[a][j];
+// dE_k(j) = -dE_k(j).  The per-slot code has no branch: the own-row penalty
+// of slot js and the new value of bit j enter through a per-slot select.
+template <int NS, int PV>
+__device__ __forceinline__ void flip(Desc *Dp, int n_, Replica<NS> &S, int js, int jl, int32_t d1, int32_t d2,
+                                     int lane_)
+{
+    const int n = opaque(n_);
+    const int lane = opaque_lane(lane_);
+    const bool live = lane < n;
+    const uint64_t xj = (rl64(S.xm, jl) >> js) & 1ull;
+    const uint64_t xmx = S.xm ^ (0ull - xj);   // bit i set where x_{i,lane} != x_j
+    S.E1 += d1;
+    S.E2 += d2;
+    Desc &D = *cold(Dp);
+    if (PV == kPvDense) {
+        // Row j of P_k holds every column entry, penalty and diagonal included;
+        // bit j itself gets -2 d - P_jj on top of P_jj.
+        const int j = js * n + jl;
+        const uint32_t c1 = (lane == jl) ? (uint32_t)(-2 * d1) - (uint32_t)ro(D.diag1)[js * kLD + jl] : 0u;
+        const uint32_t c2 = (lane == jl) ? (uint32_t)(-2 * d2) - (uint32_t)ro(D.diag2)[js * kLD + jl] : 0u;
+        const MDA_CONST int32_t *r1 = ro(D.P1) + (size_t)j * (size_t)(n * kLD);
+        const MDA_CONST int32_t *r2 = ro(D.P2) + (size_t)j * (size_t)(n * kLD);
+#pragma unroll
+        for (int g = 0; g < NS; g += 8) {
+            // at most 16 row loads in flight (keeps the register budget)
+            asm volatile("" : "+v"(r1), "+v"(r2));
+            uint32_t t1[8], t2[8];
+#pragma unroll
+            for (int f = 0; f < 8; ++f) {
+                const int i = g + f;
+                t1[f] = (i < n) ? (uint32_t)r1[i * kLD + lane] : 0u;   // padded rows: 0 beyond n
+                t2[f] = (i < n) ? (uint32_t)r2[i * kLD + lane] : 0u;
+            }
+#pragma unroll
+            for (int f = 0; f < 8; ++f) {
+                const int i = g + f;
+                const uint32_t b = (uint32_t)(xmx >> i) & 1u;
+                const uint32_t m = 0u - b;
+                const uint32_t u1 = t1[f] + ((i == js) ? c1 : 0u);
+                const uint32_t u2 = t2[f] + ((i == js) ? c2 : 0u);
+                S.e1[i] = (int32_t)((uint32_t)S.e1[i] + (u1 ^ m) + b);
+                S.e2[i] = (int32_t)((uint32_t)S.e2[i] + (u2 ^ m) + b);
+            }
+        }
+    } else {
+        // P_k[(i,u)][(js,jl)] = KA_k[js][i] DA[jl][u] (+ KB_k[js][i] DB[jl][u])
+        //                       + 2 alpha_k [(i == js) != (u == jl)]
+        // Slot i != js adds the penalty vector q_k = 2 alpha_k [u == jl]; slot js
+        // adds r_k = 2 alpha_k [u != jl] instead, except at lane jl where the
+        // term is chosen so that dE_k(j) becomes -d_k.
+        // operand rows are padded to kLD entries with zeros, so lanes beyond n load 0
+        const int32_t dv = ro(D.DA)[jl * kLD + lane];
+        const int32_t dw = (PV == kPvKronGen) ? ro(D.DB)[jl * kLD + lane] : 0;
+        const int32_t fa1 = ro(D.KA1)[js * kLD + lane];
+        const int32_t fa2 = ro(D.KA2)[js * kLD + lane];
+        const int32_t fb1 = (PV == kPvKronGen) ? ro(D.KB1)[js * kLD + lane] : 0;
+        const int32_t fb2 = (PV == kPvKronGen) ? ro(D.KB2)[js * kLD + lane] : 0;
+        const uint32_t ta1 = (uint32_t)D.two_alpha1, ta2 = (uint32_t)D.two_alpha2;
+        const bool atj = lane == jl;
+        const uint32_t q1 = atj ? ta1 : 0u, q2 = atj ? ta2 : 0u;
+        uint32_t own1 = (uint32_t)__mul24(rl(fa1, js), dv), own2 = (uint32_t)__mul24(rl(fa2, js), dv);
+        if (PV == kPvKronGen) {
+            own1 += (uint32_t)__mul24(rl(fb1, js), dw);
+            own2 += (uint32_t)__mul24(rl(fb2, js), dw);
+        }
+        const uint32_t r1 = atj ? (uint32_t)(-2 * d1) - own1 : (live ? ta1 : 0u);
+        const uint32_t r2 = atj ? (uint32_t)(-2 * d2) - own2 : (live ? ta2 : 0u);
+#pragma unroll
+        for (int i = 0; i < NS; ++i) {
+            // wrapping 32-bit arithmetic: the column entry itself fits int32
+            uint32_t t1 = (uint32_t)__mul24(rl(fa1, i), dv) + ((i == js) ? r1 : q1);
+            uint32_t t2 = (uint32_t)__mul24(rl(fa2, i), dv) + ((i == js) ? r2 : q2);
+            if (PV == kPvKronGen) {
+                t1 += (uint32_t)__mul24(rl(fb1, i), dw);
+                t2 += (uint32_t)__mul24(rl(fb2, i), dw);
+            }
+            const uint32_t b = (uint32_t)(xmx >> i) & 1u;
+            const uint32_t m = 0u - b;
+            S.e1[i] = (int32_t)((uint32_t)S.e1[i] + (t1 ^ m) + b);
+            S.e2[i] = (int32_t)((uint32_t)S.e2[i] + (t2 ^ m) + b);
+        }
+    }
+    S.xm ^= (lane == jl) ? (1ull << js) : 0ull;
+}
+
+// Fields and energies of the solution in S.xm computed from scratch:
+// g_k[a] = d_k[a] + sum_{b in x, b != a} P_k[a][b], dE_k[a] = (1 - 2 x_a) g_k[a],
+// E_k = q_k + sum_{a in x} (d_k[a] + g_k[a]) / 2 (Eq. qubo).  The column sums
+// run over the set bits; the penalty part 2 alpha_k [(i == i') != (u == u')]
+// is counted from the row and column occupation of x.
+template <int NS, int PV>
+__device__ __forceinline__ void fields_from_scratch(Desc *Dp, Replica<NS> &S, int lane_)
+{
+    const int lane = opaque_lane(lane_);
+    Desc &D = *cold(Dp);
+    const int n = opaque(D.n);
+    const bool live = lane < n;
+#pragma unroll
+    for (int i = 0; i < NS; ++i) {
+        S.e1[i] = 0;
+        S.e2[i] = 0;
+    }
+    // sum over set bits b = (bi, bu) of the cost part of column b
+    uint64_t todo = live ? S.xm : 0ull;
+    for (;;) {
+        const uint64_t bb = __ballot(todo != 0ull);
+        if (bb == 0ull) break;
+        const int bu = __ffsll((long long)bb) - 1;
+        const int bi = uni(__ffsll((long long)rl64(todo, bu)) - 1);
+        if (PV == kPvDense) {
+            const MDA_CONST int32_t *r1 = ro(D.P1) + (size_t)(bi * n + bu) * (size_t)(n * kLD);
+            const MDA_CONST int32_t *r2 = ro(D.P2) + (size_t)(bi * n + bu) * (size_t)(n * kLD);
+#pragma unroll
+            for (int g = 0; g < NS; g += 8) {
+                asm volatile("" : "+v"(r1), "+v"(r2));
+#pragma unroll
+                for (int f = 0; f < 8; ++f) {
+                    const int i = g + f;
+                    S.e1[i] = (int32_t)((uint32_t)S.e1[i] + ((i < n) ? (uint32_t)r1[i * kLD + lane] : 0u));
+                    S.e2[i] = (int32_t)((uint32_t)S.e2[i] + ((i < n) ? (uint32_t)r2[i * kLD + lane] : 0u));
+                }
+            }
+        } else {
+            const int32_t dv = ro(D.DA)[bu * kLD + lane];
+            const int32_t dw = (PV == kPvKronGen) ? ro(D.DB)[bu * kLD + lane] : 0;
+            const int32_t fa1 = ro(D.KA1)[bi * kLD + lane];
+            const int32_t fa2 = ro(D.KA2)[bi * kLD + lane];
+            const int32_t fb1 = (PV == kPvKronGen) ? ro(D.KB1)[bi * kLD + lane] : 0;
+            const int32_t fb2 = (PV == kPvKronGen) ? ro(D.KB2)[bi * kLD + lane] : 0;
+#pragma unroll
+            for (int i = 0; i < NS; ++i) {
+                uint32_t t1 = (uint32_t)__mul24(rl(fa1, i), dv);
+                uint32_t t2 = (uint32_t)__mul24(rl(fa2, i), dv);
+                if (PV == kPvKronGen) {
+                    t1 += (uint32_t)__mul24(rl(fb1, i), dw);
+                    t2 += (uint32_t)__mul24(rl(fb2, i), dw);
+                }
+                S.e1[i] = (int32_t)((uint32_t)S.e1[i] + t1);
+                S.e2[i] = (int32_t)((uint32_t)S.e2[i] + t2);
+            }
+        }
+        todo ^= (lane == bu) ? (1ull << bi) : 0ull;
+    }
+    // Self term, penalty counts, diagonal, sign; energies.
+    const uint64_t xl = live ? S.xm : 0ull;
+    const uint32_t cu = (uint32_t)__popcll(xl);   // bits set in this lane's column
+    const uint32_t ta1 = (uint32_t)D.two_alpha1, ta2 = (uint32_t)D.two_alpha2;
+    const int32_t lslot = live ? 0 : 1;            // lanes beyond n
+    int64_t acc1 = 0, acc2 = 0;
+#pragma unroll
+    for (int i = 0; i < NS; ++i) {
+        const bool on = (xl >> i) & 1ull;
+        const bool ok = live && i < n;
+        const uint32_t ri = (uint32_t)__popcll(__ballot(on));   // bits set in row i
+        const uint32_t dg1 = (uint32_t)ro(D.diag1)[i * kLD + lane];   // padded: 0 beyond n
+        const uint32_t dg2 = (uint32_t)ro(D.diag2)[i * kLD + lane];
+        uint32_t g1 = (uint32_t)S.e1[i] + dg1, g2 = (uint32_t)S.e2[i] + dg2;
+        if (PV == kPvDense) {
+            // the row of b = a added P_aa = d_a
+            g1 -= on ? dg1 : 0u;
+            g2 -= on ? dg2 : 0u;
+        } else {
+            // the Kronecker column of b = a added twice its cost part
+            // C_aa = d_a + 2 alpha (both products of the off-diagonal form)
+            g1 -= on ? 2u * (dg1 + ta1) : 0u;
+            g2 -= on ? 2u * (dg2 + ta2) : 0u;
+            const uint32_t cnt = ri + cu - (on ? 2u : 0u);
+            g1 += cnt * ta1;
+            g2 += cnt * ta2;
+        }
+        acc1 += on ? (int64_t)(int32_t)g1 + (int32_t)dg1 : 0;
+        acc2 += on ? (int64_t)(int32_t)g2 + (int32_t)dg2 : 0;
+        const int32_t s1 = on ? -(int32_t)g1 : (int32_t)g1;
+        const int32_t s2 = on ? -(int32_t)g2 : (int32_t)g2;
+        S.e1[i] = ok ? s1 : (lslot ? INT_MAX : kDead);
+        S.e2[i] = ok ? s2 : (lslot ? INT_MAX : kDead);
+    }
+    S.E1 = D.q1 + wave_sum64(acc1) / 2;
+    S.E2 = D.q2 + wave_sum64(acc2) / 2;
+}
+
+// Continue from archive member p (Algorithm 3, escape by restart).
+template <int NS, int PV>
+__device__ __forceinline__ void restart_from(Desc *Dp, int n, Replica<NS> &S, int r, int p, int lane)
+{
+    Desc &D = *cold(Dp);
+    const MDA_GLOBAL uint64_t *ax = rw(D.archX) + ((size_t)r * D.s + p) * (size_t)n;
+    S.xm = (lane < n) ? ax[lane] : 0ull;
+    fields_from_scratch<NS, PV>(Dp, S, lane);
+}
+
+// Archive update after a move: Algorithm 4 (explore) or 5 (exploit).
+template <int NS>
+__device__ __forceinline__ void archive_update(Desc *Dp, int n, Replica<NS> &S, int r, uint32_t t, int lane_,
+                                               uint32_t key0, uint32_t key1)
+{
+    const int lane = opaque_lane(lane_);
+    Desc &D = *cold(Dp);
+    const int s = D.s;
+    MDA_GLOBAL int64_t *AE = rw(D.archE) + (size_t)r * s * 2;
+    MDA_GLOBAL uint64_t *AX = rw(D.archX) + (size_t)r * s * (size_t)n;
+    const int asz = S.asize;
+    const int64_t E1 = S.E1, E2 = S.E2;
+    int slot = -1;
+    if (D.archive == 0) {
+        // first member that x dominates; four blocks of 64 members are read at
+        // once (indices clamped into the archive, so every read is in bounds)
+        for (int b = 0; b < asz; b += 256) {
+            uint64_t M[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int e = b + 64 * q + lane;
+                const int ec = e < asz ? e : asz - 1;
+                const int64_t a1 = AE[2 * ec], a2 = AE[2 * ec + 1];
+                M[q] = __ballot(e < asz && dominates(E1, E2, a1, a2));
+            }
+            int q = -1;
+#pragma unroll
+            for (int qq = 3; qq >= 0; --qq) q = M[qq] ? qq : q;
+            if (q >= 0) {
+                const uint64_t Mq = (q == 0) ? M[0] : (q == 1) ? M[1] : (q == 2) ? M[2] : M[3];
+                const int f = __ffsll((long long)Mq) - 1;
+                S.scanned += 64 * q + f + 1;
+                slot = b + 64 * q + f;
+                break;
+            }
+            S.scanned += (asz - b < 256) ? (asz - b) : 256;
+        }
+    } else {
+        // Algorithm 5: nothing may dominate x; then a random member of
+        // B = {y : x dominates y} is replaced, or x is appended.
+        int nb = 0;
+        bool rejected = false;
+        for (int b = 0; b < asz; b += 64) {
+            const int e = b + lane;
+            bool z = false, y = false;
+            if (e < asz) {
+                const int64_t a1 = AE[2 * e], a2 = AE[2 * e + 1];
+                z = dominates(a1, a2, E1, E2);
+                y = dominates(E1, E2, a1, a2);
+            }
+            S.scanned += (asz - b < 64) ? (asz - b) : 64;
+            if (__ballot(z)) {
+                rejected = true;
+                break;
+            }
+            nb += __popcll(__ballot(y));
+        }
+        if (rejected) return;
+        if (nb > 0) {
+            const U4 o = philox10(0u, t, (uint32_t)r, kTagArc, key0, key1);
+            int k = (int)scale32((uint32_t)uni((int)o.x), (uint32_t)nb);
+            for (int b = 0; b < asz; b += 64) {
+                const int e = b + lane;
+                bool y = false;
+                if (e < asz) y = dominates(E1, E2, AE[2 * e], AE[2 * e + 1]);
+                const uint64_t M = __ballot(y);
+                const int pc = __popcll(M);
+                if (k < pc) {
+                    slot = b + kth_lane(M, k, lane);
+                    break;
+                }
+                k -= pc;
+            }
+        }
+    }
+    if (slot < 0 && asz < s) {
+        slot = asz;
+        S.asize = asz + 1;
+    }
+    slot = uni(slot);
+    if (slot >= 0) {
+        if (lane == 0) {
+            AE[2 * slot] = E1;
+            AE[2 * slot + 1] = E2;
+        }
+        if (lane < n) AX[(size_t)slot * n + lane] = S.xm;
+    }
+}
+
+// Random start (Algorithm 3, line 2): bit (i, u) is bit i of the 64-bit word
+// (o.x, o.y) of Philox block (0, u); fields and energies from scratch.
+template <int NS, int PV>
+__device__ __forceinline__ void init_replica(Desc *Dp, Replica<NS> &S, int r, int lane)
+{
+    Desc &D = *cold(Dp);
+    const int n = opaque(D.n);
+    const U4 o = philox10((uint32_t)lane, 0u, (uint32_t)r, kTagInit, D.key0, D.key1);
+    const uint64_t nmask = (n >= 64) ? ~0ull : ((1ull << n) - 1ull);
+    S.xm = (lane < n) ? ((((uint64_t)o.y << 32) | o.x) & nmask) : 0ull;
+    S.Eoff = 0;
+    S.moves = S.scanned = S.rngb = S.detailed = 0;
+    S.asize = 0;
+    fields_from_scratch<NS, PV>(Dp, S, lane);
+}
+
+// One annealing step t of replica r whose largest acceptance threshold
+// (T_t * LNT[0]) >> 24 is thrmax.  Returns the flipped bit or -1.
+template <int NS, int PV, int AM, class LP>
+__device__ __forceinline__ int anneal_step(Desc *Dp, const Hot &H, Replica<NS> &S, int r, uint32_t t, int lane_,
+                                           LP lnt, uint32_t thrmax)
+{
+    constexpr bool strict = AM == kAmStrict;
+    const int lane = lane_;
+    const int n = H.n;
+    const uint64_t actmask = (n >= 64) ? ~0ull : ((1ull << n) - 1ull);
+    const uint32_t ti = table_index(t, H.ntab);
+    // Every real dE is at most 2^31 - 2 (build-time bound), so capping the
+    // offset and the largest threshold at 2^31 - 2 keeps all comparisons exact
+    // while slots and lanes beyond n, which hold INT_MAX, never qualify.
+    const int32_t EoC = (int32_t)(S.Eoff < (int64_t)(INT_MAX - 1) ? S.Eoff : (int64_t)(INT_MAX - 1));
+    const int64_t Xl = (int64_t)EoC + (int64_t)thrmax;
+    const int32_t X = (int32_t)(Xl < (int64_t)(INT_MAX - 1) ? Xl : (int64_t)(INT_MAX - 1));
+
+    // 1. can any bit be accepted?
+    int32_t mn = INT_MAX;
+#pragma unroll
+    for (int i = 0; i < NS; ++i) mn = min(mn, strict ? max(S.e1[i], S.e2[i]) : min(S.e1[i], S.e2[i]));
+    const uint64_t cand = __ballot(mn <= X) & actmask;
+
+    int j = -1;
+    if (cand) {
+        S.detailed++;
+        const int lane = opaque_lane(lane_);
+        // 2. exact acceptance, 8 facilities per random block.  The threshold
+        // (T * LNT[k]) >> 24 is formed exactly from 24-bit products: with
+        // T = Th 2^24 + Tl (T < 2^43, so Th < 2^19; LNT < 2^20) it equals
+        // Th LNT + ((Tl LNT) >> 24), and it is below 2^32 because the largest
+        // one, (T LNT[0]) >> 24, is (checked on the host).
+        const int64_t T = H.T[ti];
+        const uint32_t Th = (uint32_t)((uint64_t)T >> 24), Tl = (uint32_t)T & 0xFFFFFFu;
+        uint64_t acc = 0;
+        const int ng = opaque(n);
+#pragma unroll
+        for (int g = 0; g < NS; g += 8) {
+            if (g < ng) {
+                // slots g .. g+7 that are facilities (< n)
+                const uint32_t slots = (ng - g >= 8) ? 0xFFu : ((1u << (ng - g)) - 1u);
+                uint32_t certain = 0, maybe = 0;
+#pragma unroll
+                for (int f = 0; f < 8; ++f) {
+                    const int i = g + f;
+                    // the statistic S is 0 exactly when the combined difference is at
+                    // most the offset, and above every threshold when it exceeds X
+                    const int32_t v = strict ? max(S.e1[i], S.e2[i]) : min(S.e1[i], S.e2[i]);
+                    const bool sure = v <= EoC;
+                    const bool near = v <= X;
+                    certain |= sure ? (1u << f) : 0u;
+                    maybe |= (near && !sure) ? (1u << f) : 0u;
+                }
+                certain &= slots;
+                maybe &= slots;
+                if (__ballot(maybe != 0u)) {
+                    S.rngb++;
+                    const U4 o = philox10(((uint32_t)(g >> 3) << 16) | (uint32_t)lane, t, (uint32_t)r,
+                                          kTagAcc, H.key0, H.key1);
+#pragma unroll
+                    for (int f = 0; f < 8; ++f) {
+                        if ((maybe >> f) & 1u) {
+                            const int i = g + f;
+                            const uint32_t w = (f < 2) ? o.x : (f < 4) ? o.y : (f < 6) ? o.z : o.w;
+                            const uint32_t idx = (w >> (16 * (f & 1))) & 0xFFFu;
+                            // u_k = max(0, dE_k - E_offset) < 2^31 for a real bit, so the
+                            // strict sum stays below 2^32
+                            const uint32_t u1 = (uint32_t)(max(S.e1[i], EoC) - EoC);
+                            const uint32_t u2 = (uint32_t)(max(S.e2[i], EoC) - EoC);
+                            const uint32_t Sx = strict ? (u1 + u2) : (u1 < u2 ? u1 : u2);
+                            const uint32_t L = (uint32_t)lnt[idx] & 0xFFFFFu;
+                            const uint64_t low = (uint64_t)Tl * (uint64_t)L;   // 24 x 20 bits
+                            const uint32_t thr = __umul24(Th, L) + (uint32_t)(low >> 24);
+                            if (Sx <= thr) certain |= (1u << f);
+                        }
+                    }
+                }
+                acc |= (uint64_t)certain << g;
+            }
+        }
+        // 3. uniform choice in ascending bit order a = i*n + u
+        const int cnt = wave_sum(__popcll(acc));
+        if (cnt > 0) {
+            const U4 o = philox10(0u, t, (uint32_t)r, kTagSel, H.key0, H.key1);
+            int k = (int)scale32((uint32_t)uni((int)o.x), (uint32_t)cnt);
+            // (slot, lane) of the k-th accepted bit, slot-major: binary search for
+            // the slot over prefix counts, then the lane within the slot.
+            int lo = 0, hi = NS;
+            while (hi - lo > 1) {
+                const int mid = (lo + hi) >> 1;
+                const int below = wave_sum(__popcll(acc & ((1ull << mid) - 1ull)));
+                if (below <= k) lo = mid;
+                else hi = mid;
+            }
+            const int js = uni(lo);
+            k -= (js == 0) ? 0 : wave_sum(__popcll(acc & ((1ull << js) - 1ull)));
+            const int jl = kth_lane(__ballot((acc >> js) & 1ull), k, lane);
+            int32_t v1 = 0, v2 = 0;
+#pragma unroll
+            for (int i = 0; i < NS; ++i) {
+                v1 = (i == js) ? S.e1[i] : v1;
+                v2 = (i == js) ? S.e2[i] : v2;
+            }
+            const int32_t d1 = rl(v1, jl), d2 = rl(v2, jl);
+            // 4. move, 5. archive
+            flip<NS, PV>(Dp, n, S, js, jl, d1, d2, lane);
+            S.moves++;
+            archive_update<NS>(Dp, n, S, r, t, lane, H.key0, H.key1);
+            j = js * n + jl;
+        }
+    }
+    // No accepted flip: raise the offset (Algorithm 1) or restart from the archive
+    // (Algorithm 3).  Written as straight-line selects and an if-then so that the
+    // replica state never merges at an if/else.
+    const bool moved = j >= 0;
+    S.Eoff = moved ? 0 : ((H.escape == 0) ? S.Eoff + H.beta : S.Eoff);
+    if (!moved && H.escape != 0 && S.asize > 0) {
+        const U4 o = philox10(0u, t, (uint32_t)r, kTagArc, H.key0, H.key1);
+        const int p = (int)scale32((uint32_t)uni((int)o.y), (uint32_t)S.asize);
+        restart_from<NS, PV>(Dp, n, S, r, p, lane);
+    }
+    if (r < H.trace_R && lane == 0) rw(cold(Dp)->trace)[(size_t)r * H.steps + (t - 1u)] = j;
+    return j;
+}
+
+// Final state of replica r: x, canonical local fields h_k = sign * dE_k - d_k, scalars.
+template <int NS>
+__device__ __forceinline__ void export_replica(Desc *Dp, const Replica<NS> &S, int r, int lane)
+{
+    Desc &D = *cold(Dp);
+    const int n = opaque(D.n);
+    const int m = D.m;
+    rw(D.x)[(size_t)r * 64 + lane] = (lane < n) ? S.xm : 0ull;
+    if (lane < n) {
+        MDA_GLOBAL int32_t *h1 = rw(D.h) + (size_t)r * 2 * m;
+        MDA_GLOBAL int32_t *h2 = h1 + m;
+#pragma unroll
+        for (int i = 0; i < NS; ++i) {
+            if (i < n) {
+                const int a = i * n + lane;
+                const bool on = (S.xm >> i) & 1ull;
+                const int32_t g1 = on ? -S.e1[i] : S.e1[i];
+                const int32_t g2 = on ? -S.e2[i] : S.e2[i];
+                h1[a] = g1 - ro(D.diag1)[i * kLD + lane];
+                h2[a] = g2 - ro(D.diag2)[i * kLD + lane];
+            }
+        }
+    }
+    if (lane == 0) {
+        MDA_GLOBAL int64_t *st = rw(D.st) + (size_t)r * kStWords;
+        st[kStE1] = S.E1;
+        st[kStE2] = S.E2;
+        st[kStEoff] = S.Eoff;
+        st[kStMoves] = S.moves;
+        st[kStScanned] = S.scanned;
+        st[kStRng] = S.rngb;
+        st[kStArch] = S.asize;
+        st[kStDetailed] = S.detailed;
+    }
+}
+
+// ---------------------------------------------------------------- kernels
+
+// All steps of one replica with its state in registers.
+template <int NS, int PV, int AM>
+__device__ __forceinline__ void run_replica(Desc *Dp, int r, int lane, const MDA_LDS int32_t *lnt)
+{
+    Replica<NS> S;
+    init_replica<NS, PV>(Dp, S, r, lane);
+    const Hot H = load_hot(Dp);
+    // the next step's threshold is loaded one step ahead
+    uint32_t thr = H.thrmax[0];
+    for (uint32_t t = 1; t <= H.steps; ++t) {
+        // entry of step t + 1: min(t + 1, ntab) - 1 = min(t, ntab - 1), ntab >= 1
+        const uint32_t thr_next = H.thrmax[(t < H.ntab - 1u) ? t : H.ntab - 1u];
+        anneal_step<NS, PV, AM>(Dp, H, S, r, t, lane, lnt, thr);
+        thr = thr_next;
+    }
+    export_replica<NS>(Dp, S, r, lane);
+}
+
+#define MDA_STEP_VARIANTS(X)                                                                          \
+    X(kPvDense, kAmStrict) X(kPvDense, kAmLenient) X(kPvKronSym, kAmStrict) X(kPvKronSym, kAmLenient) \
+    X(kPvKronGen, kAmStrict) X(kPvKronGen, kAmLenient)
+
+// Persistent form: wave w of the grid runs work items w, w + W, w + 2W, ...
+// (W waves in the grid; the host orders the items largest first), each for
+// all of its steps with the replica state in registers.  From 40 slots up the
+// kernel holds one wave per SIMD (OCC = 1); the OCC = 2 build keeps part of the
+// cold-path state (initial fields, restarts, archive scans) in scratch so that
+// a second wave per SIMD hides the latency of the first.  The host takes it
+// when a launch has more replicas than one wave per SIMD can hold at once
+// (n = 50 benchmark launch: 2.45 s -> 1.69 s; three waves spill the step's
+// own state and are slower).
+template <int NS, int OCC>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(OCC))) k_persistent(const RunDesc *runs, const WorkItem *work, int nwork,
+                                                    const int32_t *lnt_)
+{
+    // the -ln table, read at random by the exact acceptance test, lives in LDS
+    __shared__ int32_t lnt_lds[4096];
+    for (int k = (int)threadIdx.x; k < 4096; k += (int)blockDim.x) lnt_lds[k] = ((const MDA_GLOBAL int32_t *)lnt_)[k];
+    __syncthreads();
+    const MDA_LDS int32_t *lnt = (const MDA_LDS int32_t *)lnt_lds;
+    const int lane = __lane_id();
+    const int wpb = (int)(blockDim.x >> 6);
+    const int wave = uni((int)(blockIdx.x * wpb + (threadIdx.x >> 6)));
+    const int nwaves = (int)gridDim.x * wpb;
+    for (int item = wave; item < nwork; item += nwaves) {
+        const WorkItem w = {ro(work)[item].run, ro(work)[item].replica};
+        Desc *Dp = ro(runs) + uni(w.run);
+        const int r = uni(w.replica);
+        switch (step_variant(Dp)) {
+#define X(PV, AM)                                        \
+    case PV * 2 + AM:                                    \
+        run_replica<NS, PV, AM>(Dp, r, lane, lnt); \
+        break;
+            MDA_STEP_VARIANTS(X)
+#undef X
+        default: break;
+        }
+    }
+}
+
+// Plain form: state lives in HBM between launches (one launch per step).
+template <int NS>
+__device__ __forceinline__ void plain_load(Desc *Dp, Replica<NS> &S, int r, int lane)
+{
+    Desc &D = *Dp;
+    const MDA_GLOBAL int32_t *pe = rw(D.pe) + (size_t)r * 2 * NS * 64;
+#pragma unroll
+    for (int i = 0; i < NS; ++i) {
+        S.e1[i] = pe[i * 64 + lane];
+        S.e2[i] = pe[(NS + i) * 64 + lane];
+    }
+    S.xm = rw(D.x)[(size_t)r * 64 + lane];
+    const MDA_GLOBAL int64_t *st = rw(D.st) + (size_t)r * kStWords;
+    S.E1 = uni64(st[kStE1]);
+    S.E2 = uni64(st[kStE2]);
+    S.Eoff = uni64(st[kStEoff]);
+    S.moves = uni64(st[kStMoves]);
+    S.scanned = uni64(st[kStScanned]);
+    S.rngb = uni64(st[kStRng]);
+    S.asize = uni((int)st[kStArch]);
+    S.detailed = uni64(st[kStDetailed]);
+}
+
+template <int NS>
+__device__ __forceinline__ void plain_store(Desc *Dp, const Replica<NS> &S, int r, int lane)
+{
+    Desc &D = *cold(Dp);
+    MDA_GLOBAL int32_t *pe = rw(D.pe) + (size_t)r * 2 * NS * 64;
+#pragma unroll
+    for (int i = 0; i < NS; ++i) {
+        pe[i * 64 + lane] = S.e1[i];
+        pe[(NS + i) * 64 + lane] = S.e2[i];
+    }
+    rw(D.x)[(size_t)r * 64 + lane] = S.xm;
+    if (lane == 0) {
+        MDA_GLOBAL int64_t *st = rw(D.st) + (size_t)r * kStWords;
+        st[kStE1] = S.E1;
+        st[kStE2] = S.E2;
+        st[kStEoff] = S.Eoff;
+        st[kStMoves] = S.moves;
+        st[kStScanned] = S.scanned;
+        st[kStRng] = S.rngb;
+        st[kStArch] = S.asize;
+        st[kStDetailed] = S.detailed;
+    }
+}
+
+template <int NS>
+__global__ void __launch_bounds__(256) k_plain_init(const RunDesc *run)
+{
+    const int lane = __lane_id();
+    const int r = uni((int)((blockIdx.x * blockDim.x + threadIdx.x) >> 6));
+    Desc *Dp = ro(run);
+    if (r >= Dp->R) return;
+    Replica<NS> S;
+    switch (path_variant(Dp)) {
+    case kPvDense: init_replica<NS, kPvDense>(Dp, S, r, lane); break;
+    case kPvKronSym: init_replica<NS, kPvKronSym>(Dp, S, r, lane); break;
+    default: init_replica<NS, kPvKronGen>(Dp, S, r, lane); break;
+    }
+    plain_store<NS>(Dp, S, r, lane);
+}
+
+template <int NS, int PV, int AM>
+__device__ __forceinline__ void plain_step_one(Desc *Dp, int r, uint32_t t, int lane, const MDA_GLOBAL int32_t *lnt)
+{
+    Replica<NS> S;
+    plain_load<NS>(Dp, S, r, lane);
+    const Hot H = load_hot(Dp);
+    anneal_step<NS, PV, AM>(Dp, H, S, r, t, lane, lnt, H.thrmax[table_index(t, H.ntab)]);
+    plain_store<NS>(Dp, S, r, lane);
+}
+
+template <int NS>
+__global__ void __launch_bounds__(256) k_plain_step(const RunDesc *run, uint32_t t, const int32_t *lnt_)
+{
+    const int lane = __lane_id();
+    const int r = uni((int)((blockIdx.x * blockDim.x + threadIdx.x) >> 6));
+    Desc *Dp = ro(run);
+    if (r >= Dp->R) return;
+    const MDA_GLOBAL int32_t *lnt = (const MDA_GLOBAL int32_t *)lnt_;
+    switch (step_variant(Dp)) {
+#define X(PV, AM)                                           \
+    case PV * 2 + AM:                                       \
+        plain_step_one<NS, PV, AM>(Dp, r, t, lane, lnt); \
+        break;
+        MDA_STEP_VARIANTS(X)
+#undef X
+    default: break;
+    }
+}
+
+template <int NS>
+__global__ void __launch_bounds__(256) k_plain_final(const RunDesc *run)
+{
+    const int lane = __lane_id();
+    const int r = uni((int)((blockIdx.x * blockDim.x + threadIdx.x) >> 6));
+    Desc *Dp = ro(run);
+    if (r >= Dp->R) return;
+    Replica<NS> S;
+    plain_load<NS>(Dp, S, r, lane);
+    export_replica<NS>(Dp, S, r, lane);
+}
+
+}  // namespace mda

@@ -1,0 +1,44 @@
+// mda_wave_tile.h -- launchers of one register tile of the one-wave kernels;
+// included by the translation unit of that tile (MDA_TILE).
+#pragma once
+
+#include "mda_wave.h"
+
+namespace mda {
+
+#define MDA_CAT2(a, b) a##b
+#define MDA_CAT(a, b) MDA_CAT2(a, b)
+
+// From 40 slots up a second build holds two waves per SIMD (see k_persistent).
+constexpr int kTileOcc2 = MDA_TILE >= 40 ? 2 : 1;
+
+hipError_t MDA_CAT(launch_persistent_ns, MDA_TILE)(int occ, const RunDesc *runs, const WorkItem *work, int nwork,
+                                                  const int32_t *lnt, int grid, int block, hipStream_t stream)
+{
+    if (occ >= 2 && kTileOcc2 == 2)
+        hipLaunchKernelGGL((k_persistent<MDA_TILE, kTileOcc2>), dim3(grid), dim3(block), 0, stream, runs, work, nwork, lnt);
+    else
+        hipLaunchKernelGGL((k_persistent<MDA_TILE, 1>), dim3(grid), dim3(block), 0, stream, runs, work, nwork, lnt);
+    return hipGetLastError();
+}
+
+hipError_t MDA_CAT(persistent_occupancy_ns, MDA_TILE)(int occ, int block, int *blocks_per_cu)
+{
+    if (occ >= 2 && kTileOcc2 == 2)
+        return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_persistent<MDA_TILE, kTileOcc2>, block, 0);
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_persistent<MDA_TILE, 1>, block, 0);
+}
+
+hipError_t MDA_CAT(launch_plain_ns, MDA_TILE)(const RunDesc *run, int R, uint32_t steps, const int32_t *lnt, int block,
+                                             hipStream_t stream)
+{
+    const int wpb = block / 64;
+    const int grid = (R + wpb - 1) / wpb;
+    hipLaunchKernelGGL(k_plain_init<MDA_TILE>, dim3(grid), dim3(block), 0, stream, run);
+    for (uint32_t t = 1; t <= steps; ++t)
+        hipLaunchKernelGGL(k_plain_step<MDA_TILE>, dim3(grid), dim3(block), 0, stream, run, t, lnt);
+    hipLaunchKernelGGL(k_plain_final<MDA_TILE>, dim3(grid), dim3(block), 0, stream, run);
+    return hipGetLastError();
+}
+
+}  // namespace mda
