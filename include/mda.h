@@ -133,8 +133,8 @@ void mda_params_default(mda_params *p);
  * start, per-step energy differences of both objectives for all m bits from
  * maintained local fields, parallel acceptance with the dynamic offset,
  * uniform choice of one accepted flip, field update, archive update.
- * Asynchronous on p->stream.  Errors: MDA_EINVAL, MDA_EOVERFLOW (schedule
- * threshold beyond 2^32-2), MDA_ENOMEM, MDA_EDEVICE.
+ * Asynchronous on p->stream.  Errors: MDA_EINVAL, MDA_EOVERFLOW (delta0 above
+ * 2^35, or a schedule threshold beyond 2^32-2), MDA_ENOMEM, MDA_EDEVICE.
  */
 int da_run(const mda_qubo *q, const mda_params *p, mda_run **out);
 
@@ -187,11 +187,21 @@ typedef struct {
     int64_t moves;          /* accepted flips */
     int64_t scanned;        /* archive entries compared */
     int64_t rng_blocks;     /* acceptance random blocks drawn */
-    int32_t *trace;         /* steps entries (bit index or -1), may be NULL; needs trace_replicas */
+    int32_t *trace;         /* resolved-steps entries (bit index or -1), may be NULL; needs trace_replicas */
 } mda_state;
 
-/* Final state of one replica (synchronises). */
+/* Final state of one replica (synchronises).  st->trace receives as many
+ * entries as the run's resolved step count (da_params_get), which differs from
+ * the steps passed in when those were 0. */
 int da_state_get(mda_run *r, int32_t replica, mda_state *st);
+
+/* The parameters run r uses, each default resolved: steps (0 -> m^2 / 4, Table
+ * param), delta0, deltaf, xi and beta (the schedule of Table param scaled by
+ * max |C| / 2^23 when delta0 <= 0; beta < 0 -> max(1, floor(delta0 / steps))),
+ * archive_size (0 -> m) and waves_per_replica (0 -> the layout chosen).  The
+ * other fields are returned as given.  Does not synchronise.
+ * Errors: MDA_EINVAL (NULL argument). */
+int da_params_get(const mda_run *r, mda_params *out);
 
 /* Run statistics summed over replicas: moves, archive entries compared, random
  * blocks drawn, total archive entries (synchronises). */
@@ -293,7 +303,9 @@ int mda_server_stats(mda_server *s, mda_server_counters *st);
 /* Fails requests not yet admitted, waits for launched ones, frees uncollected results. */
 void mda_server_destroy(mda_server *s);
 
-/* Debug/verification exports: the library's own host tables. */
+/* Debug/verification exports: the library's own host tables.
+ * mda_temperature_table errors: MDA_EINVAL (NULL T, steps < 1), MDA_EOVERFLOW
+ * (delta0 above 2^35, the largest starting temperature a run accepts). */
 int mda_threshold_table(int32_t *lnt4096);
 int mda_temperature_table(double delta0, double deltaf, double xi, int64_t steps, int64_t *T);
 

@@ -151,6 +151,9 @@ void threshold_table(int32_t *lnt)
 
 // Geometric cooling evaluated at the top of every step; T_t = floor(256 delta_t).
 // Returns the number of entries until the temperature stops changing.
+// Largest scaled temperature T = floor(256 delta) a run accepts.
+constexpr double kMaxTemp = (double)((int64_t)1 << 43);
+
 int64_t temperature_table(double delta0, double deltaf, double xi, int64_t steps, std::vector<int64_t> &T)
 {
     T.clear();
@@ -179,6 +182,7 @@ extern "C" int mda_threshold_table(int32_t *lnt4096)
 extern "C" int mda_temperature_table(double delta0, double deltaf, double xi, int64_t steps, int64_t *T)
 {
     if (!T || steps < 1) return fail(MDA_EINVAL, "bad arguments");
+    if (!(delta0 * 256.0 <= kMaxTemp)) return fail(MDA_EOVERFLOW, "delta0 = %g exceeds 2^35", delta0);
     std::vector<int64_t> tab;
     temperature_table(delta0, deltaf, xi, steps, tab);
     for (int64_t t = 0; t < steps; ++t) T[t] = tab[std::min<int64_t>(t, (int64_t)tab.size() - 1)];
@@ -588,6 +592,9 @@ static int prepare_run(mda_qubo *q, const mda_params *pin, hipStream_t stream, m
         if (p.xi <= 0.0) p.xi = 0.001;
     }
     if (!(p.xi >= 0.0 && p.xi < 1.0)) return fail(MDA_EINVAL, "xi = %g", p.xi);
+    // every temperature is at most delta0 (the schedule only cools), so this
+    // bound keeps each conversion of delta * 256 to an integer in range
+    if (!(p.delta0 * 256.0 <= kMaxTemp)) return fail(MDA_EOVERFLOW, "delta0 = %g exceeds 2^35", p.delta0);
     if (p.beta < 0) p.beta = std::max<int64_t>(1, (int64_t)std::floor(p.delta0 / (double)p.steps));
 
     std::vector<int64_t> T;
@@ -596,7 +603,7 @@ static int prepare_run(mda_qubo *q, const mda_params *pin, hipStream_t stream, m
     threshold_table(lnt);
     std::vector<uint32_t> thrmax(T.size());
     for (size_t t = 0; t < T.size(); ++t) {
-        if (T[t] < 0 || T[t] > ((int64_t)1 << 43)) return fail(MDA_EOVERFLOW, "temperature %lld out of range", (long long)T[t]);
+        if (T[t] < 0 || (double)T[t] > kMaxTemp) return fail(MDA_EOVERFLOW, "temperature %lld out of range", (long long)T[t]);
         const uint64_t v = ((uint64_t)T[t] * (uint64_t)lnt[0]) >> 24;
         if (v > 0xFFFFFFFEull) return fail(MDA_EOVERFLOW, "largest acceptance threshold %llu exceeds 2^32-2 (delta0 too large)", (unsigned long long)v);
         thrmax[t] = (uint32_t)v;
@@ -912,6 +919,15 @@ static int copy_d2h(void *dst, const void *src, size_t bytes, hipStream_t s)
 {
     HIP_TRY(hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
+    return MDA_OK;
+}
+
+extern "C" int da_params_get(const mda_run *r, mda_params *out)
+{
+    if (!r || !out) return fail(MDA_EINVAL, "NULL argument");
+    *out = r->p;
+    out->archive_size = r->h.s;
+    out->waves_per_replica = r->h.wr * r->h.wc;
     return MDA_OK;
 }
 

@@ -129,6 +129,8 @@ def lib():
     L.archive_get.restype = C.c_int
     L.da_state_get.argtypes = [vp, i32, C.POINTER(State)]
     L.da_state_get.restype = C.c_int
+    L.da_params_get.argtypes = [vp, C.POINTER(Params)]
+    L.da_params_get.restype = C.c_int
     L.da_stats.argtypes = [vp, C.POINTER(i64), C.POINTER(i64), C.POINTER(i64), C.POINTER(i64)]
     L.da_stats.restype = C.c_int
     L.da_run_free.argtypes = [vp]
@@ -160,7 +162,7 @@ def lib():
 
 
 EXPORTED = ["qubo_build_bqap", "qubo_info", "qubo_free", "mda_params_default", "da_run", "da_run_batch",
-            "da_sync", "da_elapsed_ms", "da_kernel_ms", "archive_get", "da_state_get", "da_stats", "da_run_free",
+            "da_sync", "da_elapsed_ms", "da_kernel_ms", "archive_get", "da_state_get", "da_params_get", "da_stats", "da_run_free",
             "mda_set_allocator", "mda_last_error", "mda_threshold_table", "mda_temperature_table",
             "mda_autotune", "mda_footprint", "mda_server_create", "mda_server_submit", "mda_server_wait", "mda_server_stats",
             "mda_server_destroy"]
@@ -329,10 +331,11 @@ class ArchiveResult:
 class Run:
     """One da_run (or one member of a da_run_batch)."""
 
-    def __init__(self, handle: C.c_void_p, qubo: Qubo, params: Params):
+    def __init__(self, handle: C.c_void_p, qubo: Qubo):
         self._h = handle
         self.qubo = qubo           # keeps the QUBO alive on the Python side too
-        self.params = params
+        self.params = Params()     # as resolved by the library (steps, schedule, archive size)
+        _check(lib().da_params_get(self._h, C.byref(self.params)))
 
     def sync(self):
         _check(lib().da_sync(self._h))
@@ -402,7 +405,7 @@ class Run:
 def da_run(q: Qubo, params: Params) -> Run:
     h = C.c_void_p()
     _check(lib().da_run(q.handle, C.byref(params), C.byref(h)))
-    return Run(h, q, params)
+    return Run(h, q)
 
 
 def da_run_batch(qs: Sequence[Qubo], params: Sequence[Params]) -> list:
@@ -413,7 +416,7 @@ def da_run_batch(qs: Sequence[Qubo], params: Sequence[Params]) -> list:
     parr = (Params * k)(*params)
     outs = (C.c_void_p * k)()
     _check(lib().da_run_batch(harr, parr, k, outs))
-    return [Run(C.c_void_p(outs[i]), qs[i], params[i]) for i in range(k)]
+    return [Run(C.c_void_p(outs[i]), qs[i]) for i in range(k)]
 
 
 # ---------------------------------------------------------------- footprint and serving
@@ -439,7 +442,7 @@ class Server:
         self._h = C.c_void_p()
         opts = ServerOpts(int(hbm_budget), int(max_inflight), int(max_batch), int(device), 0)
         _check(lib().mda_server_create(C.byref(opts), C.byref(self._h)))
-        self._params = {}
+        self._n = {}            # ticket -> n of the submitted instance
 
     def submit(self, F1, F2, D, params: Params, path: int = PATH_AUTO, penalty: int = PEN_2MAX,
                dense_budget: int = 0) -> int:
@@ -451,7 +454,7 @@ class Server:
         bo = BuildOpts(int(penalty), int(path), int(dense_budget))
         _check(lib().mda_server_submit(self._h, n, _ptr(F1), _ptr(F2), _ptr(D), C.byref(bo), C.byref(params),
                                        C.byref(t)))
-        self._params[int(t.value)] = (n, params)
+        self._n[int(t.value)] = n
         return int(t.value)
 
     def wait(self, ticket: int, timeout: float = -1.0, keep: bool = True):
@@ -461,9 +464,9 @@ class Server:
         rc = lib().mda_server_wait(self._h, int(ticket), float(timeout), C.byref(h) if keep else None,
                                    C.byref(info))
         _check(rc)
-        n, params = self._params.pop(int(ticket))
+        n = self._n.pop(int(ticket))
         d = {k: getattr(info, k) for k, _ in RequestInfo._fields_ if k != "reserved"}
-        run = Run(h, _Shape(n), params) if keep else None
+        run = Run(h, _Shape(n)) if keep else None
         return run, d
 
     def stats(self) -> dict:
