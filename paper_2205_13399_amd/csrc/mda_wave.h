@@ -343,10 +343,20 @@ __device__ __forceinline__ int anneal_step(Desc *Dp, const Hot &H, Replica<NS> &
     const int64_t Xl = (int64_t)EoC + (int64_t)thrmax;
     const int32_t X = (int32_t)(Xl < (int64_t)(INT_MAX - 1) ? Xl : (int64_t)(INT_MAX - 1));
 
-    // 1. can any bit be accepted?
+    // 1. can any bit be accepted?  The minimum is kept per group of 8 slots so
+    // that step 2 passes over groups in which no lane comes within reach.
+    int32_t gmin[NS / 8];
+#pragma unroll
+    for (int g = 0; g < NS; g += 8) {
+        int32_t gm = INT_MAX;
+#pragma unroll
+        for (int f = 0; f < 8; ++f)
+            gm = min(gm, strict ? max(S.e1[g + f], S.e2[g + f]) : min(S.e1[g + f], S.e2[g + f]));
+        gmin[g >> 3] = gm;
+    }
     int32_t mn = INT_MAX;
 #pragma unroll
-    for (int i = 0; i < NS; ++i) mn = min(mn, strict ? max(S.e1[i], S.e2[i]) : min(S.e1[i], S.e2[i]));
+    for (int g = 0; g < NS / 8; ++g) mn = min(mn, gmin[g]);
     const uint64_t cand = __ballot(mn <= X) & actmask;
 
     int j = -1;
@@ -364,7 +374,9 @@ __device__ __forceinline__ int anneal_step(Desc *Dp, const Hot &H, Replica<NS> &
         const int ng = opaque(n);
 #pragma unroll
         for (int g = 0; g < NS; g += 8) {
-            if (g < ng) {
+            // a group whose slots all exceed X on every lane has neither
+            // certain nor possible acceptances and draws no random block
+            if (g < ng && __ballot(gmin[g >> 3] <= X)) {
                 // slots g .. g+7 that are facilities (< n)
                 const uint32_t slots = (ng - g >= 8) ? 0xFFu : ((1u << (ng - g)) - 1u);
                 uint32_t certain = 0, maybe = 0;
