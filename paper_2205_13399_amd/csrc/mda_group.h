@@ -355,9 +355,20 @@ __device__ __forceinline__ void g_step(Desc *Dp, const Hot &H, Replica<NS> &S, i
     const int64_t Xl = (int64_t)EoC + (int64_t)thrmax;
     const int32_t X = (int32_t)(Xl < (int64_t)(INT_MAX - 1) ? Xl : (int64_t)(INT_MAX - 1));
 
+    // minimum per group of 8 slots: the exact test below passes over groups in
+    // which no lane of this wave comes within reach
+    int32_t gmin[NS / 8];
+#pragma unroll
+    for (int gg = 0; gg < NS; gg += 8) {
+        int32_t gm = INT_MAX;
+#pragma unroll
+        for (int f = 0; f < 8; ++f)
+            gm = min(gm, strict ? max(S.e1[gg + f], S.e2[gg + f]) : min(S.e1[gg + f], S.e2[gg + f]));
+        gmin[gg >> 3] = gm;
+    }
     int32_t mn = INT_MAX;
 #pragma unroll
-    for (int s = 0; s < NS; ++s) mn = min(mn, strict ? max(S.e1[s], S.e2[s]) : min(S.e1[s], S.e2[s]));
+    for (int gg = 0; gg < NS / 8; ++gg) mn = min(mn, gmin[gg]);
     const uint64_t cand = __ballot(live && mn <= X);
     if (lane == 0) L.flag[t & 1u][g.w] = cand != 0ull ? 1 : 0;
     __syncthreads();   // B1
@@ -374,7 +385,9 @@ __device__ __forceinline__ void g_step(Desc *Dp, const Hot &H, Replica<NS> &S, i
         const int rows = opaque(n - g.i0);   // facilities of this wave's block below n
 #pragma unroll
         for (int gg = 0; gg < NS; gg += 8) {
-            if (gg < rows) {   // dead lanes hold INT_MAX and never qualify
+            // dead lanes hold INT_MAX and never qualify; a group with no slot
+            // within X on any lane has no acceptance and draws no random block
+            if (gg < rows && __ballot(gmin[gg >> 3] <= X)) {
                 const uint32_t slots = (rows - gg >= 8) ? 0xFFu : ((1u << (rows - gg)) - 1u);
                 uint32_t certain = 0, maybe = 0;
 #pragma unroll
