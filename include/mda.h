@@ -66,9 +66,17 @@ typedef struct mda_qubo mda_qubo;  /* one bQAP instance: host copies + device op
 typedef struct mda_run mda_run;    /* one run: device replica state and archives */
 
 typedef struct {
-    int32_t penalty;       /* MDA_PEN_* */
-    int32_t path;          /* MDA_PATH_* */
-    int64_t dense_budget;  /* bytes for MDA_PATH_AUTO; <= 0 means 2 GiB */
+    int32_t penalty;         /* MDA_PEN_* */
+    int32_t path;            /* MDA_PATH_* */
+    int64_t dense_budget;    /* bytes for MDA_PATH_AUTO; <= 0 means 2 GiB */
+    int32_t normalise_log2;  /* objective normalisation (Sec. Parameter Settings, which
+                                sets the largest coefficient of each C_k to 2^23):
+                                0 = none; L in [1, 30] = each F_k is scaled by
+                                s_k = 2^L / max|C_k| and rounded to the nearest integer
+                                (halves up), so max|C_k| is 2^L up to that rounding;
+                                -1 = the largest L <= 23 for which the int32 bounds of
+                                qubo_build_bqap hold */
+    int32_t reserved;        /* 0 */
 } mda_build_opts;
 
 typedef struct {
@@ -77,8 +85,11 @@ typedef struct {
     int32_t symmetric;       /* 1 when D (or F1 and F2) is symmetric */
     int64_t alpha1, alpha2;  /* penalty weights */
     int64_t q1, q2;          /* constant terms alpha_k * 2n of Y and Z */
-    int64_t maxabs_c;        /* max(max|C_1|, max|C_2|) */
+    int64_t maxabs_c;        /* max(max|C_1|, max|C_2|), after normalisation */
     int64_t device_bytes;    /* device memory held by the handle */
+    int32_t normalise_log2;  /* L applied (0 = none) */
+    int32_t reserved;
+    double scale1, scale2;   /* s_k applied to F_k (1 when none; energies are in scaled units) */
 } mda_qubo_info;
 
 /*
@@ -92,10 +103,11 @@ typedef struct {
  *   opts         NULL for defaults (MDA_PEN_2MAX, MDA_PATH_AUTO, 2 GiB)
  *   stream       hipStream_t for the uploads (NULL = default stream)
  *   out          receives the handle
- * Errors: MDA_EINVAL (n outside [2, 64] in this build -- the interface admits
- * n <= 100 -- or a NULL array), MDA_EOVERFLOW (some bit's |P_aa| + sum_b |P_ab|
- * exceeds 2^31-2, so its energy difference would not fit int32, or
- * 2 * alpha_k * n >= 2^30), MDA_ENOMEM, MDA_EDEVICE.
+ * Errors: MDA_EINVAL (n outside [2, 100], a NULL array, an unknown option),
+ * MDA_EOVERFLOW (some bit's |P_aa| + sum_b |P_ab| exceeds 2^31-2, so its energy
+ * difference would not fit int32; or 2 * alpha_k * n >= 2^30; or a scaled flow
+ * beyond int32; with normalise_log2 = -1: no L in [1, 23] fits), MDA_ENOMEM,
+ * MDA_EDEVICE.
  */
 int qubo_build_bqap(int32_t n, const int32_t *F1, const int32_t *F2, const int32_t *D,
                     const mda_build_opts *opts, void *stream, mda_qubo **out);
@@ -134,7 +146,7 @@ void mda_params_default(mda_params *p);
  * maintained local fields, parallel acceptance with the dynamic offset,
  * uniform choice of one accepted flip, field update, archive update.
  * Asynchronous on p->stream.  Errors: MDA_EINVAL, MDA_EOVERFLOW (delta0 above
- * 2^35, or a schedule threshold beyond 2^32-2), MDA_ENOMEM, MDA_EDEVICE.
+ * 2^35), MDA_ENOMEM, MDA_EDEVICE.
  */
 int da_run(const mda_qubo *q, const mda_params *p, mda_run **out);
 

@@ -13,7 +13,7 @@ import numpy as np
 
 __all__ = [
     "build", "lib", "qap_cost", "cost_direct", "constraint_direct", "cost_qubo",
-    "constraint_qubo", "qubo_energy", "delta_energy", "penalty_2max", "penalty_vl_w",
+    "constraint_qubo", "normalise_flows", "qubo_energy", "delta_energy", "penalty_2max", "penalty_vl_w",
     "philox", "lnt", "temperature", "accept", "dominates", "Archive", "Qubo", "run_replica",
     "default_schedule", "STRICT", "LENIENT", "EXPLORE", "EXPLOIT", "ESC_OFFSET",
     "ESC_ARCHIVE", "PEN_2MAX", "PEN_VL", "nondominated",
@@ -163,6 +163,24 @@ def constraint_qubo(n):
     pg = C.c_int64(0)
     lib().orc_constraint_qubo(n, out, C.byref(pg))
     return out, int(pg.value)
+
+
+def normalise_flows(F, D, log2: int):
+    """Objective normalisation (Sec. Parameter Settings): the objective QUBO is
+    scaled so that its largest coefficient is 2^log2 (the paper uses 2^23).
+    The cost QUBO of Sec. 2.2 is linear in the flows, so the flows are scaled by
+    s = 2^log2 / max|C| (C the upper-triangular cost QUBO) and rounded to the
+    nearest integer, halves up.  Returns (scaled flows, s); a flow matrix whose
+    QUBO vanishes is returned unchanged with s = 1."""
+    F = _i32(F)
+    mx = int(np.abs(cost_qubo(F, D)).max())
+    if mx == 0:
+        return F.copy(), 1.0
+    s = float(2 ** int(log2)) / float(mx)
+    r = np.floor(F.astype(np.float64) * s + 0.5)
+    if np.abs(r).max() > np.iinfo(np.int32).max:
+        raise OverflowError("scaled flow beyond int32")
+    return r.astype(np.int32), s
 
 
 def qubo_energy(Q, q, x) -> int:

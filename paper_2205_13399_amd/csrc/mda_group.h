@@ -414,7 +414,9 @@ __device__ __forceinline__ void g_step(Desc *Dp, const Hot &H, Replica<NS> &S, i
                             const uint32_t Sx = strict ? (u1 + u2) : (u1 < u2 ? u1 : u2);
                             const uint32_t Lk = (uint32_t)L.lnt[idx] & 0xFFFFFu;
                             const uint64_t low = (uint64_t)Tl * (uint64_t)Lk;
-                            const uint32_t thr = __umul24(Th, Lk) + (uint32_t)(low >> 24);
+                            // saturated at 2^32 - 2, above every statistic
+                            const uint64_t t64 = (uint64_t)Th * (uint64_t)Lk + (low >> 24);
+                            const uint32_t thr = t64 < 0xFFFFFFFEull ? (uint32_t)t64 : 0xFFFFFFFEu;
                             if (Sx <= thr) certain |= (1u << f);
                         }
                     }

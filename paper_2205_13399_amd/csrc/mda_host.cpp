@@ -196,6 +196,8 @@ struct mda_qubo {
     int32_t path = 0, kform = 0, symmetric = 0;
     int64_t alpha[2] = {0, 0}, q[2] = {0, 0};
     int64_t maxabs = 0;
+    int32_t norm = 0;                  // normalisation 2^norm of both objectives (0: none)
+    double scale[2] = {1.0, 1.0};      // s_k applied to F_k
     std::vector<int32_t> F1, F2, D, diag1, diag2;
     int32_t *dKA1 = nullptr, *dKA2 = nullptr, *dKB1 = nullptr, *dKB2 = nullptr, *dDA = nullptr, *dDB = nullptr;
     int32_t *dP1 = nullptr, *dP2 = nullptr, *ddiag1 = nullptr, *ddiag2 = nullptr;
@@ -231,19 +233,31 @@ static inline int64_t cost_upper(const int32_t *F, const int32_t *Dm, int n, int
     return (int64_t)F[i * n + j] * Dm[u * n + v] + (int64_t)F[j * n + i] * Dm[v * n + u];
 }
 
-extern "C" int qubo_build_bqap(int32_t n, const int32_t *F1, const int32_t *F2, const int32_t *D,
-                               const mda_build_opts *opts, void *stream_, mda_qubo **out)
+// Largest |entry| of the upper-triangular cost QUBO C of flows F (Sec. 2.2):
+// F[i][i] D[u][u] on the diagonal, F[i][j] D[u][v] + F[j][i] D[v][u] off it.
+// The off-diagonal form is unchanged by swapping (i, u) and (j, v), so a scan
+// over all ordered pairs gives the maximum over the upper triangle.
+static int64_t objective_maxabs(const int32_t *F, const int32_t *Dm, int n)
 {
-    if (!out) return fail(MDA_EINVAL, "out is NULL");
-    *out = nullptr;
-    if (n < 2 || n > 100) return fail(MDA_EINVAL, "n = %d outside [2, 100]", n);
-    if (!F1 || !F2 || !D) return fail(MDA_EINVAL, "F1, F2 and D must be non-NULL");
-    mda_build_opts o{MDA_PEN_2MAX, MDA_PATH_AUTO, 0};
-    if (opts) o = *opts;
-    if (o.penalty != MDA_PEN_2MAX && o.penalty != MDA_PEN_VL) return fail(MDA_EINVAL, "unknown penalty %d", o.penalty);
-    if (o.path < MDA_PATH_AUTO || o.path > MDA_PATH_KRON) return fail(MDA_EINVAL, "unknown path %d", o.path);
+    int64_t mx = 0;
+    for (int i = 0; i < n; ++i)
+        for (int j = 0; j < n; ++j) {
+            const int64_t fij = F[i * n + j], fji = F[j * n + i];
+            for (int u = 0; u < n; ++u)
+                for (int v = 0; v < n; ++v) {
+                    const int64_t c = (i == j && u == v) ? fij * Dm[u * n + u]
+                                                         : fij * Dm[u * n + v] + fji * Dm[v * n + u];
+                    mx = std::max<int64_t>(mx, std::llabs(c));
+                }
+        }
+    return mx;
+}
+
+// One build with the objectives normalised to 2^L (L = 0: as given).
+static int build_bqap(int32_t n, const int32_t *F1, const int32_t *F2, const int32_t *D, const mda_build_opts &o,
+                      int L, hipStream_t stream, mda_qubo **out)
+{
     const int64_t budget = o.dense_budget > 0 ? o.dense_budget : (int64_t)2 << 30;
-    hipStream_t stream = (hipStream_t)stream_;
 
     std::unique_ptr<mda_qubo> q(new mda_qubo);
     const int m = n * n;
@@ -253,6 +267,27 @@ extern "C" int qubo_build_bqap(int32_t n, const int32_t *F1, const int32_t *F2, 
     q->F1.assign(F1, F1 + nn);
     q->F2.assign(F2, F2 + nn);
     q->D.assign(D, D + nn);
+
+    // Objective normalisation (Sec. Parameter Settings): C_k is linear in F_k,
+    // so scaling the flows by s_k = 2^L / max|C_k| scales C_k by s_k and keeps
+    // its Kronecker form; the scaled flows are rounded to the nearest integer
+    // (halves up).  An objective that vanishes is left as it is.
+    q->norm = L;
+    if (L > 0) {
+        std::vector<int32_t> *Fv[2] = {&q->F1, &q->F2};
+        for (int k = 0; k < 2; ++k) {
+            const int64_t mx = objective_maxabs(Fv[k]->data(), q->D.data(), n);
+            if (mx == 0) continue;
+            const double s = std::ldexp(1.0, L) / (double)mx;
+            for (int32_t &f : *Fv[k]) {
+                const double r = std::floor((double)f * s + 0.5);
+                if (!(std::fabs(r) <= (double)INT32_MAX))
+                    return fail(MDA_EOVERFLOW, "objective %d: scaled flow %g beyond int32", k + 1, r);
+                f = (int32_t)r;
+            }
+            q->scale[k] = s;
+        }
+    }
     const int32_t *Fk[2] = {q->F1.data(), q->F2.data()};
     const int32_t *Dm = q->D.data();
 
@@ -484,6 +519,29 @@ extern "C" int qubo_build_bqap(int32_t n, const int32_t *F1, const int32_t *F2, 
     return MDA_OK;
 }
 
+extern "C" int qubo_build_bqap(int32_t n, const int32_t *F1, const int32_t *F2, const int32_t *D,
+                               const mda_build_opts *opts, void *stream_, mda_qubo **out)
+{
+    if (!out) return fail(MDA_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (n < 2 || n > 100) return fail(MDA_EINVAL, "n = %d outside [2, 100]", n);
+    if (!F1 || !F2 || !D) return fail(MDA_EINVAL, "F1, F2 and D must be non-NULL");
+    mda_build_opts o{MDA_PEN_2MAX, MDA_PATH_AUTO, 0, 0, 0};
+    if (opts) o = *opts;
+    if (o.penalty != MDA_PEN_2MAX && o.penalty != MDA_PEN_VL) return fail(MDA_EINVAL, "unknown penalty %d", o.penalty);
+    if (o.path < MDA_PATH_AUTO || o.path > MDA_PATH_KRON) return fail(MDA_EINVAL, "unknown path %d", o.path);
+    if (o.normalise_log2 < -1 || o.normalise_log2 > 30)
+        return fail(MDA_EINVAL, "normalise_log2 = %d outside [-1, 30]", o.normalise_log2);
+    hipStream_t stream = (hipStream_t)stream_;
+    if (o.normalise_log2 != -1) return build_bqap(n, F1, F2, D, o, o.normalise_log2, stream, out);
+    // the paper's 2^23 where the int32 bounds allow it, else the largest power below
+    for (int L = 23; L >= 1; --L) {
+        const int rc = build_bqap(n, F1, F2, D, o, L, stream, out);
+        if (rc != MDA_EOVERFLOW) return rc;
+    }
+    return fail(MDA_EOVERFLOW, "no normalisation 2^L with 1 <= L <= 23 keeps every field within int32");
+}
+
 extern "C" int qubo_info(const mda_qubo *q, mda_qubo_info *info)
 {
     if (!q || !info) return fail(MDA_EINVAL, "NULL argument");
@@ -497,6 +555,10 @@ extern "C" int qubo_info(const mda_qubo *q, mda_qubo_info *info)
     info->q2 = q->q[1];
     info->maxabs_c = q->maxabs;
     info->device_bytes = q->pool.total;
+    info->normalise_log2 = q->norm;
+    info->reserved = 0;
+    info->scale1 = q->scale[0];
+    info->scale2 = q->scale[1];
     return MDA_OK;
 }
 
@@ -604,9 +666,9 @@ static int prepare_run(mda_qubo *q, const mda_params *pin, hipStream_t stream, m
     std::vector<uint32_t> thrmax(T.size());
     for (size_t t = 0; t < T.size(); ++t) {
         if (T[t] < 0 || (double)T[t] > kMaxTemp) return fail(MDA_EOVERFLOW, "temperature %lld out of range", (long long)T[t]);
+        // saturated like the kernels' thresholds: 2^32 - 2 exceeds every statistic
         const uint64_t v = ((uint64_t)T[t] * (uint64_t)lnt[0]) >> 24;
-        if (v > 0xFFFFFFFEull) return fail(MDA_EOVERFLOW, "largest acceptance threshold %llu exceeds 2^32-2 (delta0 too large)", (unsigned long long)v);
-        thrmax[t] = (uint32_t)v;
+        thrmax[t] = (uint32_t)std::min<uint64_t>(v, 0xFFFFFFFEull);
     }
 
     std::unique_ptr<mda_run> r(new mda_run);

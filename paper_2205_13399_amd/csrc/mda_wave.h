@@ -364,10 +364,10 @@ __device__ __forceinline__ int anneal_step(Desc *Dp, const Hot &H, Replica<NS> &
         S.detailed++;
         const int lane = opaque_lane(lane_);
         // 2. exact acceptance, 8 facilities per random block.  The threshold
-        // (T * LNT[k]) >> 24 is formed exactly from 24-bit products: with
-        // T = Th 2^24 + Tl (T < 2^43, so Th < 2^19; LNT < 2^20) it equals
-        // Th LNT + ((Tl LNT) >> 24), and it is below 2^32 because the largest
-        // one, (T LNT[0]) >> 24, is (checked on the host).
+        // (T * LNT[k]) >> 24 is formed exactly: with T = Th 2^24 + Tl (T < 2^43,
+        // so Th < 2^19; LNT < 2^20) it equals Th LNT + ((Tl LNT) >> 24).  Each
+        // statistic is at most 2^32 - 4 (two parts below 2^31 - 1), so a
+        // threshold saturated at 2^32 - 2 takes the same decisions.
         const int64_t T = H.T[ti];
         const uint32_t Th = (uint32_t)((uint64_t)T >> 24), Tl = (uint32_t)T & 0xFFFFFFu;
         uint64_t acc = 0;
@@ -410,7 +410,8 @@ __device__ __forceinline__ int anneal_step(Desc *Dp, const Hot &H, Replica<NS> &
                             const uint32_t Sx = strict ? (u1 + u2) : (u1 < u2 ? u1 : u2);
                             const uint32_t L = (uint32_t)lnt[idx] & 0xFFFFFu;
                             const uint64_t low = (uint64_t)Tl * (uint64_t)L;   // 24 x 20 bits
-                            const uint32_t thr = __umul24(Th, L) + (uint32_t)(low >> 24);
+                            const uint64_t t64 = (uint64_t)Th * (uint64_t)L + (low >> 24);
+                            const uint32_t thr = t64 < 0xFFFFFFFEull ? (uint32_t)t64 : 0xFFFFFFFEu;
                             if (Sx <= thr) certain |= (1u << f);
                         }
                     }

@@ -61,6 +61,11 @@ def test_errors_without_device(mda):
     assert b"n = 1" in mda.lib().mda_last_error()
     rc = mda.lib().qubo_build_bqap(3, None, None, None, None, None, ctypes.byref(h))
     assert rc == mda.MDA_EINVAL
+    for bad in (-2, 31):   # normalise_log2 outside [-1, 30], rejected before any device call
+        bo = mda.BuildOpts(mda.PEN_2MAX, mda.PATH_AUTO, 0, bad, 0)
+        rc = mda.lib().qubo_build_bqap(3, F.ctypes.data_as(ctypes.c_void_p), F.ctypes.data_as(ctypes.c_void_p),
+                                       F.ctypes.data_as(ctypes.c_void_p), ctypes.byref(bo), None, ctypes.byref(h))
+        assert rc == mda.MDA_EINVAL and b"normalise_log2" in mda.lib().mda_last_error()
     assert mda.lib().da_run(None, None, None) == mda.MDA_EINVAL
     assert mda.lib().archive_get(None, 0, 0, None, None) == mda.MDA_EINVAL
     mda.lib().da_run_free(None)
