@@ -222,9 +222,10 @@ def serve_bench(args, mda):
 def sbda_vs_mda(args, mda):
     """The paper's comparison on synthetic instances: MDA (strict, explore) and
     SB-DA (11 weights), 20 runs each at I_max = 0.25 m^2 steps, Verma-Lewis
-    penalty for both; per run the non-dominated feasible set in (f1, f2),
-    normalised together, its hypervolume and size; and each method's
-    throughput."""
+    penalty for both, on the QUBOs as given and with both objectives normalised
+    to one largest coefficient 2^L (Sec. Parameter Settings); per run the
+    non-dominated feasible set in the true (f1, f2), normalised together, its
+    hypervolume and size; and each method's throughput."""
     import torch
     from paper_2205_13399_amd import quality, sbda
     runs = args.replicas or 20
@@ -236,39 +237,55 @@ def sbda_vs_mda(args, mda):
     tot = {"mda": [0, 0.0], "sbda": [0, 0.0]}
     for inst in insts:
         q = mda.Qubo(inst.F1, inst.F2, inst.D, penalty=mda.PEN_VL, path=mda.PATH_KRON)
+        qn = mda.Qubo(inst.F1, inst.F2, inst.D, penalty=mda.PEN_VL, path=mda.PATH_KRON, normalise=mda.NORM_AUTO)
 
-        def mda_runs(escape):
+        def mda_runs(escape, qq=q):
             torch.cuda.synchronize()
             t0 = time.perf_counter()
-            run = mda.da_run(q, mda.make_params(runs, steps, inst.seed, escape=escape))
+            run = mda.da_run(qq, mda.make_params(runs, steps, inst.seed, escape=escape))
             run.sync()
             dt = time.perf_counter() - t0
+            scaled = qq.info().normalise_log2 != 0
             sets = []
             for r in range(runs):
-                a = run.archive(r, raw=True, bits=False)
-                pts = (np.stack([a.e1[a.feasible == 1], a.e2[a.feasible == 1]], axis=1) if len(a)
-                       else np.zeros((0, 2)))
-                sets.append(pts[quality.nondominated(pts)] if len(pts) else pts)
+                a = run.archive(r, raw=True, bits=scaled)
+                ok = a.feasible == 1
+                if not len(a) or not ok.any():
+                    sets.append(np.zeros((0, 2)))
+                    continue
+                if scaled:   # energies in scaled units: cost the permutations in the true objectives
+                    pts = np.array([(sbda.qap_cost(inst.F1, inst.D, p), sbda.qap_cost(inst.F2, inst.D, p))
+                                    for p in a.perm[ok]], np.int64)
+                else:
+                    pts = np.stack([a.e1[ok], a.e2[ok]], axis=1)
+                sets.append(pts[quality.nondominated(pts)])
             return sets, dt
 
         mda_sets, t_mda = mda_runs(mda.ESC_OFFSET)
         rst_sets, t_rst = mda_runs(mda.ESC_ARCHIVE)
+        mdan_sets, _ = mda_runs(mda.ESC_OFFSET, qn)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         res = sbda.sbda(inst.F1, inst.F2, inst.D, runs, steps, inst.seed)
         t_sb = time.perf_counter() - t0
-        sets = mda_sets + rst_sets + res.points
+        resn = sbda.sbda(inst.F1, inst.F2, inst.D, runs, steps, inst.seed, normalise=mda.NORM_AUTO)
+        sets = mda_sets + rst_sets + res.points + mdan_sets + resn.points
         qual = quality.compare([s for s in sets if len(s)] or [np.zeros((1, 2))])
         norm = quality.normaliser([s for s in sets if len(s)])
         hv = lambda ss: [quality.hypervolume_2d(norm(s)) if len(s) else 0.0 for s in ss]
         hv_m, hv_r, hv_s = hv(mda_sets), hv(rst_sets), hv(res.points)
+        hv_mn, hv_sn = hv(mdan_sets), hv(resn.points)
         per_inst.append({"rho": inst.rho,
                          "mda": {"hv_mean": float(np.mean(hv_m)), "nondominated_mean": float(np.mean([len(s) for s in mda_sets])),
                                  "seconds": t_mda},
                          "mda_restart": {"hv_mean": float(np.mean(hv_r)),
                                          "nondominated_mean": float(np.mean([len(s) for s in rst_sets])), "seconds": t_rst},
                          "sbda": {"hv_mean": float(np.mean(hv_s)), "nondominated_mean": float(np.mean([len(s) for s in res.points])),
-                                  "seconds": t_sb}})
+                                  "seconds": t_sb},
+                         "mda_normalised": {"hv_mean": float(np.mean(hv_mn)), "log2": int(qn.info().normalise_log2),
+                                            "nondominated_mean": float(np.mean([len(s) for s in mdan_sets]))},
+                         "sbda_normalised": {"hv_mean": float(np.mean(hv_sn)), "log2": int(resn.normalise_log2),
+                                             "nondominated_mean": float(np.mean([len(s) for s in resn.points]))}})
         tot["mda"][0] += runs * m * steps
         tot["mda"][1] += t_mda
         tot["sbda"][0] += len(res.weights) * runs * m * steps
@@ -278,6 +295,10 @@ def sbda_vs_mda(args, mda):
              % (inst.rho, per_inst[-1]["mda"]["hv_mean"], per_inst[-1]["mda"]["nondominated_mean"], t_mda,
                 per_inst[-1]["mda_restart"]["hv_mean"], per_inst[-1]["mda_restart"]["nondominated_mean"],
                 per_inst[-1]["sbda"]["hv_mean"], per_inst[-1]["sbda"]["nondominated_mean"], t_sb))
+        _log("rho %+.2f normalised to 2^%d / 2^%d: MDA hv %.4f (%.1f points/run), SB-DA hv %.4f (%.1f points/run)"
+             % (inst.rho, per_inst[-1]["mda_normalised"]["log2"], per_inst[-1]["sbda_normalised"]["log2"],
+                per_inst[-1]["mda_normalised"]["hv_mean"], per_inst[-1]["mda_normalised"]["nondominated_mean"],
+                per_inst[-1]["sbda_normalised"]["hv_mean"], per_inst[-1]["sbda_normalised"]["nondominated_mean"]))
         del qual
     out = {"metric": "bit-trials/s", "value": tot["sbda"][0] / tot["sbda"][1], "unit": "bit-trials/s", "n_gpus": 1,
            "steps": 1, "warmup": 0, "ms_per_step": round(tot["sbda"][1] * 1e3, 3), "higher_is_better": True,

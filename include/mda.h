@@ -111,6 +111,10 @@ typedef struct {
  */
 int qubo_build_bqap(int32_t n, const int32_t *F1, const int32_t *F2, const int32_t *D,
                     const mda_build_opts *opts, void *stream, mda_qubo **out);
+
+/* The flows q was built from, after normalisation: host, row-major n*n int32
+ * each (either may be NULL).  Errors: MDA_EINVAL (NULL q). */
+int qubo_flows(const mda_qubo *q, int32_t *F1, int32_t *F2);
 int qubo_info(const mda_qubo *q, mda_qubo_info *info);
 void qubo_free(mda_qubo *q);
 

@@ -253,9 +253,10 @@ static int64_t objective_maxabs(const int32_t *F, const int32_t *Dm, int n)
     return mx;
 }
 
-// One build with the objectives normalised to 2^L (L = 0: as given).
+// One build with the objectives normalised to 2^L (L = 0: as given); mxk[k]
+// is max|C_k| of the given flows (only read when L > 0).
 static int build_bqap(int32_t n, const int32_t *F1, const int32_t *F2, const int32_t *D, const mda_build_opts &o,
-                      int L, hipStream_t stream, mda_qubo **out)
+                      int L, const int64_t *mxk, hipStream_t stream, mda_qubo **out)
 {
     const int64_t budget = o.dense_budget > 0 ? o.dense_budget : (int64_t)2 << 30;
 
@@ -276,7 +277,7 @@ static int build_bqap(int32_t n, const int32_t *F1, const int32_t *F2, const int
     if (L > 0) {
         std::vector<int32_t> *Fv[2] = {&q->F1, &q->F2};
         for (int k = 0; k < 2; ++k) {
-            const int64_t mx = objective_maxabs(Fv[k]->data(), q->D.data(), n);
+            const int64_t mx = mxk[k];
             if (mx == 0) continue;
             const double s = std::ldexp(1.0, L) / (double)mx;
             for (int32_t &f : *Fv[k]) {
@@ -533,13 +534,26 @@ extern "C" int qubo_build_bqap(int32_t n, const int32_t *F1, const int32_t *F2, 
     if (o.normalise_log2 < -1 || o.normalise_log2 > 30)
         return fail(MDA_EINVAL, "normalise_log2 = %d outside [-1, 30]", o.normalise_log2);
     hipStream_t stream = (hipStream_t)stream_;
-    if (o.normalise_log2 != -1) return build_bqap(n, F1, F2, D, o, o.normalise_log2, stream, out);
+    int64_t mxk[2] = {0, 0};
+    if (o.normalise_log2 != 0) {
+        mxk[0] = objective_maxabs(F1, D, n);
+        mxk[1] = objective_maxabs(F2, D, n);
+    }
+    if (o.normalise_log2 != -1) return build_bqap(n, F1, F2, D, o, o.normalise_log2, mxk, stream, out);
     // the paper's 2^23 where the int32 bounds allow it, else the largest power below
     for (int L = 23; L >= 1; --L) {
-        const int rc = build_bqap(n, F1, F2, D, o, L, stream, out);
+        const int rc = build_bqap(n, F1, F2, D, o, L, mxk, stream, out);
         if (rc != MDA_EOVERFLOW) return rc;
     }
     return fail(MDA_EOVERFLOW, "no normalisation 2^L with 1 <= L <= 23 keeps every field within int32");
+}
+
+extern "C" int qubo_flows(const mda_qubo *q, int32_t *F1, int32_t *F2)
+{
+    if (!q) return fail(MDA_EINVAL, "NULL qubo");
+    if (F1) std::memcpy(F1, q->F1.data(), q->F1.size() * sizeof(int32_t));
+    if (F2) std::memcpy(F2, q->F2.data(), q->F2.size() * sizeof(int32_t));
+    return MDA_OK;
 }
 
 extern "C" int qubo_info(const mda_qubo *q, mda_qubo_info *info)

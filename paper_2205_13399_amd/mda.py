@@ -112,6 +112,8 @@ def lib():
     vp, i32, i64 = C.c_void_p, C.c_int32, C.c_int64
     L.qubo_build_bqap.argtypes = [i32, vp, vp, vp, C.POINTER(BuildOpts), vp, C.POINTER(vp)]
     L.qubo_build_bqap.restype = C.c_int
+    L.qubo_flows.argtypes = [vp, vp, vp]
+    L.qubo_flows.restype = C.c_int
     L.qubo_info.argtypes = [vp, C.POINTER(QuboInfo)]
     L.qubo_info.restype = C.c_int
     L.qubo_free.argtypes = [vp]
@@ -164,7 +166,7 @@ def lib():
     return L
 
 
-EXPORTED = ["qubo_build_bqap", "qubo_info", "qubo_free", "mda_params_default", "da_run", "da_run_batch",
+EXPORTED = ["qubo_build_bqap", "qubo_flows", "qubo_info", "qubo_free", "mda_params_default", "da_run", "da_run_batch",
             "da_sync", "da_elapsed_ms", "da_kernel_ms", "archive_get", "da_state_get", "da_params_get", "da_stats", "da_run_free",
             "mda_set_allocator", "mda_last_error", "mda_threshold_table", "mda_temperature_table",
             "mda_autotune", "mda_footprint", "mda_server_create", "mda_server_submit", "mda_server_wait", "mda_server_stats",
@@ -271,6 +273,13 @@ class Qubo:
     @property
     def handle(self):
         return self._h
+
+    def flows(self):
+        """qubo_flows: (F1, F2) as built, after normalisation."""
+        F1 = np.zeros((self.n, self.n), np.int32)
+        F2 = np.zeros((self.n, self.n), np.int32)
+        _check(lib().qubo_flows(self._h, _ptr(F1), _ptr(F2)))
+        return F1, F2
 
     def info(self) -> QuboInfo:
         inf = QuboInfo()

@@ -10,6 +10,11 @@ the archive holds the lowest-energy states, so each replica's best solution
 is its archive entry of least E1.  Every weight runs in one batched launch;
 replica r of every weight together form SB-DA run r, whose result is the
 non-dominated subset of its 11 solutions in the true objectives (f1, f2).
+
+With normalisation (Sec. Parameter Settings), R and S are first put on the
+same scale -- both flow matrices scaled so that max|R| = max|S| = 2^L -- and
+the aggregation uses the scaled flows; the points are still reported in the
+true objectives.
 """
 from __future__ import annotations
 
@@ -43,18 +48,45 @@ class SbdaResult:
     best: np.ndarray          # [weights, replicas, 2] archive energy (E1, slot) of each replica's best
     points: List[np.ndarray]  # per SB-DA run (replica): non-dominated (f1, f2) of its feasible solutions
     perms: List[np.ndarray]   # per SB-DA run: the permutations of those points
+    normalise_log2: int = 0   # L of the normalisation applied (0: none)
+
+
+def _aggregated_qubos(F1, F2, D, weights, penalty, path, stream):
+    n = D.shape[0]
+    zero = np.zeros((n, n), np.int32)
+    return [mda.Qubo(scalarised_flows(F1, F2, g), zero, D, penalty=penalty, path=path, stream=stream)
+            for g in weights]
+
+
+def normalised_qubos(F1, F2, D, normalise: int, weights: Sequence[int] = WEIGHTS, penalty: int = mda.PEN_VL,
+                     path: int = mda.PATH_KRON, stream: Optional[int] = None):
+    """The aggregated QUBOs of normalised R and S: L = normalise, or with
+    NORM_AUTO the largest L <= 23 for which the normalisation and every
+    aggregated QUBO pass the library's int32 bounds.  Returns (qubos, L)."""
+    for L in ([normalise] if normalise > 0 else range(23, 0, -1)):
+        try:
+            q = mda.Qubo(F1, F2, D, penalty=penalty, path=path, stream=stream, normalise=L)
+            A, B = q.flows()
+            q.close()
+            return _aggregated_qubos(A, B, D, weights, penalty, path, stream), L
+        except (mda.MdaError, ValueError) as e:
+            if normalise > 0 or (isinstance(e, mda.MdaError) and e.code != mda.MDA_EOVERFLOW):
+                raise
+    raise mda.MdaError(mda.MDA_EOVERFLOW, "no normalisation 2^L, 1 <= L <= 23, fits every aggregated QUBO")
 
 
 def sbda(F1, F2, D, replicas: int, steps: int, seed: int, weights: Sequence[int] = WEIGHTS,
          penalty: int = mda.PEN_VL, path: int = mda.PATH_KRON, stream: Optional[int] = None,
-         graph: bool = False) -> SbdaResult:
+         graph: bool = False, normalise: int = mda.NORM_NONE) -> SbdaResult:
     """Runs SB-DA: weight g uses Philox key seed + g."""
     F1 = np.asarray(F1, np.int32)
     F2 = np.asarray(F2, np.int32)
     D = np.asarray(D, np.int32)
     n = D.shape[0]
-    zero = np.zeros((n, n), np.int32)
-    qs = [mda.Qubo(scalarised_flows(F1, F2, g), zero, D, penalty=penalty, path=path, stream=stream) for g in weights]
+    if normalise == mda.NORM_NONE:
+        qs, L = _aggregated_qubos(F1, F2, D, weights, penalty, path, stream), 0
+    else:
+        qs, L = normalised_qubos(F1, F2, D, normalise, weights, penalty, path, stream)
     ps = [mda.make_params(replicas, steps, seed + g, stream=stream, graph=graph) for g in weights]
     runs = mda.da_run_batch(qs, ps)
     best = np.zeros((len(weights), replicas, 2), np.int64)
@@ -80,4 +112,4 @@ def sbda(F1, F2, D, replicas: int, steps: int, seed: int, weights: Sequence[int]
         nd = quality.nondominated(pts)
         points.append(pts[nd])
         perms.append(np.array([cand[r][k][2] for k in nd], np.int32))
-    return SbdaResult(runs=runs, weights=tuple(weights), best=best, points=points, perms=perms)
+    return SbdaResult(runs=runs, weights=tuple(weights), best=best, points=points, perms=perms, normalise_log2=L)

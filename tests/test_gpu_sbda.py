@@ -50,3 +50,33 @@ def test_sbda_against_oracle(mods):
             for b in range(len(p)):
                 if a != b:
                     assert not (p[b][0] <= p[a][0] and p[b][1] <= p[a][1])
+
+
+def test_sbda_normalised_against_oracle(mods):
+    """R and S normalised to one 2^L before aggregation (Sec. Parameter
+    Settings): every weight bit-exact against the oracle on the aggregated
+    oracle-normalised flows; points still in the true objectives."""
+    mda, sbda = mods
+    inst = synth.make_instance(8, 0.5, seed=89)
+    R, steps, seed = 3, 3000, 321
+    res = sbda.sbda(inst.F1, inst.F2, inst.D, R, steps, seed, normalise=mda.NORM_AUTO)
+    L = res.normalise_log2
+    print("SB-DA normalised to 2^%d" % L, flush=True)
+    assert 1 <= L <= 23
+    if L < 23:
+        with pytest.raises((mda.MdaError, ValueError)):
+            sbda.normalised_qubos(inst.F1, inst.F2, inst.D, L + 1)
+    A, _ = oracle.normalise_flows(inst.F1, inst.D, L)
+    B, _ = oracle.normalise_flows(inst.F2, inst.D, L)
+    zero = np.zeros_like(inst.F1)
+    for w, g in enumerate(res.weights):
+        Fg = (g * A.astype(np.int64) + (10 - g) * B.astype(np.int64)).astype(np.int32)
+        oq = oracle.Qubo(Fg, zero, inst.D, 1)
+        out = run_replicas(Fg, zero, inst.D, range(R), penalty=1, workers=4,
+                           **oracle_kwargs(oq, steps, seed + g, trace=False))
+        for r in range(R):
+            compare_replica(res.runs[w], out[r], r, trace=False, label="normalised SB-DA weight %d" % g)
+    for r in range(R):
+        for (f1, f2), perm in zip(res.points[r], res.perms[r]):
+            assert f1 == oracle.qap_cost(inst.F1, inst.D, perm)
+            assert f2 == oracle.qap_cost(inst.F2, inst.D, perm)
