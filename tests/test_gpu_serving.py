@@ -114,3 +114,24 @@ def test_served_request_against_oracle(mda):
     for r in range(3):
         compare_replica(run, res[r], r, label="served n=70")
     srv.close()
+
+
+def test_served_normalised_request(mda):
+    """A request with objective normalisation equals a direct run on the
+    QUBO built with the same option."""
+    inst = synth.make_instance(30, 0.2, seed=3030)
+    srv = mda.Server()
+    t = srv.submit(inst.F1, inst.F2, inst.D, mda.make_params(R, STEPS, inst.seed, trace_replicas=R), path=2,
+                   normalise=mda.NORM_AUTO)
+    run, info = srv.wait(t, timeout=120.0)
+    assert info["status"] == 2
+    q = mda.Qubo(inst.F1, inst.F2, inst.D, path=2, normalise=mda.NORM_AUTO)
+    assert q.info().normalise_log2 >= 1
+    alone = mda.da_run(q, mda.make_params(R, STEPS, inst.seed, trace_replicas=R))
+    for r in range(R):
+        a, b = alone.state(r, trace=True), run.state(r, trace=True)
+        assert np.array_equal(a["trace"], b["trace"]), r
+        assert (a["E1"], a["E2"], a["moves"]) == (b["E1"], b["E2"], b["moves"]), r
+    fa, fb = alone.archive(-1), run.archive(-1)
+    assert np.array_equal(fa.e1, fb.e1) and np.array_equal(fa.e2, fb.e2)
+    srv.close()
