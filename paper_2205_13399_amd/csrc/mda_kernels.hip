@@ -19,15 +19,30 @@ __global__ void __launch_bounds__(256) k_nondominated(const RunDesc *runs, const
     const int s = D.s;
     int asz = uni((int)rw(D.st)[(size_t)r * kStWords + kStArch]);
     asz = asz < 0 ? 0 : (asz > s ? s : asz);
-    const MDA_GLOBAL int64_t *AE = rw(D.archE) + (size_t)r * s * 2;
+    // the archive is only read here, so the scan goes through the constant
+    // path: the entries compared against are uniform and load as scalars, 8 at
+    // a time so that their latencies overlap
+    const MDA_CONST int64_t *AE = ro(D.archE) + (size_t)r * s * 2;
     MDA_GLOBAL uint8_t *nd = rw(D.nd) + (size_t)r * s;
     int count = 0;
     for (int b = 0; b < asz; b += 64) {
         const int e = b + lane;
+        const int ec = e < asz ? e : asz - 1;
+        const int64_t a1 = AE[2 * ec], a2 = AE[2 * ec + 1];
+        bool dom = false;
+        int f = 0;
+        for (; f + 8 <= asz; f += 8) {
+            int64_t q1[8], q2[8];
+#pragma unroll
+            for (int k = 0; k < 8; ++k) {
+                q1[k] = AE[2 * (f + k)];
+                q2[k] = AE[2 * (f + k) + 1];
+            }
+#pragma unroll
+            for (int k = 0; k < 8; ++k) dom |= dominates(q1[k], q2[k], a1, a2);
+        }
+        for (; f < asz; ++f) dom |= dominates(AE[2 * f], AE[2 * f + 1], a1, a2);
         if (e < asz) {
-            const int64_t a1 = AE[2 * e], a2 = AE[2 * e + 1];
-            bool dom = false;
-            for (int f = 0; f < asz; ++f) dom |= dominates(AE[2 * f], AE[2 * f + 1], a1, a2);
             nd[e] = dom ? 0 : 1;
             count += dom ? 0 : 1;
         }
