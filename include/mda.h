@@ -73,7 +73,8 @@ typedef struct {
                                 sets the largest coefficient of each C_k to 2^23):
                                 0 = none; L in [1, 30] = each F_k is scaled by
                                 s_k = 2^L / max|C_k| and rounded to the nearest integer
-                                (halves up), so max|C_k| is 2^L up to that rounding;
+                                (halves up), so max|C_k| is 2^L up to that rounding
+                                (an objective with C_k = 0 is left as it is);
                                 -1 = the largest L <= 23 for which the int32 bounds of
                                 qubo_build_bqap hold */
     int32_t reserved;        /* 0 */
@@ -115,6 +116,8 @@ int qubo_build_bqap(int32_t n, const int32_t *F1, const int32_t *F2, const int32
 /* The flows q was built from, after normalisation: host, row-major n*n int32
  * each (either may be NULL).  Errors: MDA_EINVAL (NULL q). */
 int qubo_flows(const mda_qubo *q, int32_t *F1, int32_t *F2);
+/* Sizes, chosen path, penalty weights, normalisation and device bytes of q.
+ * Errors: MDA_EINVAL (NULL argument). */
 int qubo_info(const mda_qubo *q, mda_qubo_info *info);
 void qubo_free(mda_qubo *q);
 
