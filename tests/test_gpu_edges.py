@@ -142,3 +142,23 @@ def test_argument_errors(mda):
         run.archive(-1, raw=True)                     # the raw archive is per replica
     assert e.value.code == mda.MDA_EINVAL
     assert len(run.state(0, trace=True)["trace"]) == 100
+
+
+def test_batch_members_resolve_their_own_defaults(mda):
+    """In one batched launch, a member with the default step count (m^2 / 4)
+    and one with an explicit count each report their own resolved parameters
+    and equal their single runs."""
+    a = synth.make_instance(4, 0.3, seed=441)
+    b = synth.make_instance(6, -0.3, seed=661)
+    qa, qb = mda.Qubo(a.F1, a.F2, a.D, path=2), mda.Qubo(b.F1, b.F2, b.D, path=2)
+    pa = mda.make_params(3, 0, 11, trace_replicas=3)
+    pb = mda.make_params(5, 700, 12, trace_replicas=5, archive_size=9)
+    ra, rb = mda.da_run_batch([qa, qb], [pa, pb])
+    assert ra.params.steps == 16 * 16 // 4 and ra.params.archive_size == 16
+    assert rb.params.steps == 700 and rb.params.archive_size == 9
+    for q, p, run, R in ((qa, pa, ra, 3), (qb, pb, rb, 5)):
+        alone = mda.da_run(q, p)
+        for r in range(R):
+            x, y = alone.state(r, trace=True), run.state(r, trace=True)
+            assert len(x["trace"]) == run.params.steps
+            assert np.array_equal(x["trace"], y["trace"]) and (x["E1"], x["E2"]) == (y["E1"], y["E2"])
