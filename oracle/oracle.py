@@ -1,7 +1,8 @@
 """ctypes wrapper of the C oracle (TEST INFRASTRUCTURE ONLY).
 
-Every function forwards to ``mda_oracle.c``; see that file's header for the
-readings of the paper (arXiv:2205.13399) it implements.  Arrays are numpy.
+Every function forwards to ``mda_oracle.c`` except ``normalise_flows``, plain
+numpy over the oracle's own cost QUBO; see the C file's header for the readings
+of the paper (arXiv:2205.13399) it implements.  Arrays are numpy.
 """
 from __future__ import annotations
 
