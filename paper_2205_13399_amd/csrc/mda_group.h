@@ -269,10 +269,13 @@ __device__ __forceinline__ void g_archive(Desc *Dp, Replica<NS> &S, int r, uint3
     const int64_t E1 = S.E1, E2 = S.E2;
     int slot = -1;
     if (D.archive == 0) {
-        for (int b = 0; b < asz; b += 256) {
-            uint64_t M[4];
+        // first member that x dominates, 8 blocks of 64 members per round trip
+        // (indices clamped into the archive, so every read is in bounds)
+        constexpr int kAB = 8;
+        for (int b = 0; b < asz; b += 64 * kAB) {
+            uint64_t M[kAB];
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
+            for (int q = 0; q < kAB; ++q) {
                 const int e = b + 64 * q + lane;
                 const int ec = e < asz ? e : asz - 1;
                 const int64_t a1 = AE[2 * ec], a2 = AE[2 * ec + 1];
@@ -280,15 +283,17 @@ __device__ __forceinline__ void g_archive(Desc *Dp, Replica<NS> &S, int r, uint3
             }
             int q = -1;
 #pragma unroll
-            for (int qq = 3; qq >= 0; --qq) q = M[qq] ? qq : q;
+            for (int qq = kAB - 1; qq >= 0; --qq) q = M[qq] ? qq : q;
             if (q >= 0) {
-                const uint64_t Mq = (q == 0) ? M[0] : (q == 1) ? M[1] : (q == 2) ? M[2] : M[3];
+                uint64_t Mq = M[0];
+#pragma unroll
+                for (int qq = 1; qq < kAB; ++qq) Mq = (q == qq) ? M[qq] : Mq;
                 const int f = __ffsll((long long)Mq) - 1;
                 S.scanned += 64 * q + f + 1;
                 slot = b + 64 * q + f;
                 break;
             }
-            S.scanned += (asz - b < 256) ? (asz - b) : 256;
+            S.scanned += (asz - b < 64 * kAB) ? (asz - b) : 64 * kAB;
         }
     } else {
         int nb = 0;
