@@ -124,7 +124,7 @@ void qubo_free(mda_qubo *q);
 typedef struct {
     int32_t replicas;         /* independent annealing chains, >= 1 */
     int32_t archive_size;     /* s; 0 = m (Table param) */
-    int64_t steps;            /* I_max, 1 <= steps < 2^32; 0 = 0.25 * m^2 (Table param) */
+    int64_t steps;            /* I_max, 1 <= steps <= 2^32 - 2; 0 = 0.25 * m^2 (Table param) */
     double delta0, deltaf, xi;/* geometric schedule; delta0 <= 0 selects 1e9*M/2^23, 1e4*M/2^23, 1e-3
                                  where M = max|C| (the paper's values on coefficients scaled to 2^23) */
     int64_t beta;             /* E_offset increment; < 0 selects max(1, floor(delta0/steps)) */
@@ -142,6 +142,12 @@ typedef struct {
     int32_t waves_per_replica;/* 0: one wave for n <= 64, else a workgroup of 2 * ceil(n / 64) waves;
                                  1: one wave (n <= 64); 2..8: a workgroup of that many waves, split into
                                  ceil(n / 64) location blocks and facility blocks of equal size */
+    const int64_t *temp_table;/* optional host array of the resolved step count's entries: T_t of step t
+                                 (t = 1..steps) at index t - 1, the temperature delta_t in fixed point with
+                                 8 fractional bits (floor(256 delta_t)), each in [0, 2^43]; it replaces the
+                                 geometric schedule of delta0, deltaf and xi (Table param) as input data.
+                                 Copied before da_run returns.  delta0 still sets the default beta.
+                                 NULL: the geometric schedule */
 } mda_params;
 
 /* Fills p with the defaults of Table (param) and the benchmark settings. */
@@ -153,7 +159,7 @@ void mda_params_default(mda_params *p);
  * maintained local fields, parallel acceptance with the dynamic offset,
  * uniform choice of one accepted flip, field update, archive update.
  * Asynchronous on p->stream.  Errors: MDA_EINVAL, MDA_EOVERFLOW (delta0 above
- * 2^35), MDA_ENOMEM, MDA_EDEVICE.
+ * 2^35, or a temp_table entry outside [0, 2^43]), MDA_ENOMEM, MDA_EDEVICE.
  */
 int da_run(const mda_qubo *q, const mda_params *p, mda_run **out);
 
@@ -217,8 +223,9 @@ int da_state_get(mda_run *r, int32_t replica, mda_state *st);
 /* The parameters run r uses, each default resolved: steps (0 -> m^2 / 4, Table
  * param), delta0, deltaf, xi and beta (the schedule of Table param scaled by
  * max |C| / 2^23 when delta0 <= 0; beta < 0 -> max(1, floor(delta0 / steps))),
- * archive_size (0 -> m) and waves_per_replica (0 -> the layout chosen).  The
- * other fields are returned as given.  Does not synchronise.
+ * archive_size (0 -> m) and waves_per_replica (0 -> the layout chosen).
+ * temp_table is returned as NULL (the run keeps its own copy).  The other
+ * fields are returned as given.  Does not synchronise.
  * Errors: MDA_EINVAL (NULL argument). */
 int da_params_get(const mda_run *r, mda_params *out);
 
@@ -300,7 +307,7 @@ typedef struct {
     int64_t bit_trials;      /* replicas * n^2 * steps */
     int64_t footprint;       /* device bytes accounted to the request */
     int32_t batch;           /* requests in its launch */
-    int32_t reserved;
+    int32_t slot;            /* server stream (0 .. max_inflight - 1) its launch ran on */
 } mda_request_info;
 
 typedef struct {
@@ -311,11 +318,13 @@ typedef struct {
 } mda_server_counters;
 
 int mda_server_create(const mda_server_opts *opts, mda_server **out);
-/* Copies the instance; p->stream and p->graph are ignored; steps and replicas must be set. */
+/* Copies the instance (and p->temp_table, if given); p->stream and p->graph are ignored; steps and
+ * replicas must be set. */
 int mda_server_submit(mda_server *s, int32_t n, const int32_t *F1, const int32_t *F2, const int32_t *D,
                       const mda_build_opts *opts, const mda_params *p, int64_t *ticket);
 /* Waits up to timeout_s (< 0: no limit) for the request; on success hands its run to the caller
- * (NULL run: freed at once) and fills info.  MDA_EBUSY on timeout (the ticket stays valid); the
+ * (NULL run: freed at once) and fills info.  The request's footprint counts against the budget
+ * until its run is freed (da_run_free), also after the run has been handed over.  MDA_EBUSY on timeout (the ticket stays valid); the
  * request's own error code if it failed.  A ticket is collected once. */
 int mda_server_wait(mda_server *s, int64_t ticket, double timeout_s, mda_run **run, mda_request_info *info);
 int mda_server_stats(mda_server *s, mda_server_counters *st);

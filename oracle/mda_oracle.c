@@ -379,7 +379,7 @@ int orc_mda_replica(const orc_qubo *q, const orc_params *p, int32_t r, orc_repli
         return -3;
     }
 
-    /* Line 2 of Algorithm 3: a random binary solution (reading: i.i.d. fair
+    /* Algorithm 3 starts from a random binary solution (reading: i.i.d. fair
      * bits).  Bit (i, u) is bit i%32 of word (i/32)%4 of the block (i/128, u). */
     for (int32_t a = 0; a < m; ++a) {
         int32_t i = a / n, u = a % n;
@@ -394,7 +394,7 @@ int orc_mda_replica(const orc_qubo *q, const orc_params *p, int32_t r, orc_repli
     int64_t E2 = energy_of(q, q->P2, q->q2, x);
     int64_t Eoff = 0, moves = 0;
 
-    /* Line 1: an empty archive of capacity s. */
+    /* Algorithm 3: the archive starts empty, with capacity s. */
     orc_archive A;
     A.size = 0;
     A.cap = s;
@@ -409,11 +409,17 @@ int orc_mda_replica(const orc_qubo *q, const orc_params *p, int32_t r, orc_repli
 
     double delta = p->delta0;
     for (int64_t t = 1; t <= p->steps; ++t) {
-        /* Line 5: geometric cooling. */
-        if (delta > p->deltaf) delta = delta * (1.0 - p->xi);
-        int64_t T = (int64_t)floor(delta * 256.0);
+        /* Algorithm 3: geometric cooling at the top of each iteration, unless
+         * the schedule is given as data. */
+        int64_t T;
+        if (p->temp_table) {
+            T = p->temp_table[t - 1];
+        } else {
+            if (delta > p->deltaf) delta = delta * (1.0 - p->xi);
+            T = (int64_t)floor(delta * 256.0);
+        }
 
-        /* Line 6: energy differences of every neighbour, both objectives
+        /* Algorithm 3: energy differences of every neighbour, both objectives
          * (Eq. cale with Y and Z in place of Q). */
         for (int32_t a = 0; a < m; ++a) {
             int64_t sgn = 1 - 2 * (int64_t)x[a];
@@ -436,7 +442,7 @@ int orc_mda_replica(const orc_qubo *q, const orc_params *p, int32_t r, orc_repli
             }
         }
 
-        /* Lines 7-9: parallel acceptance test of every bit. */
+        /* Algorithm 3: parallel acceptance test of every bit. */
         int64_t c = 0;
         for (int32_t a = 0; a < m; ++a) {
             acc[a] = (uint8_t)orc_accept(dE1[a], dE2[a], Eoff, T, lnt[field[a]], p->accept);
@@ -444,7 +450,7 @@ int orc_mda_replica(const orc_qubo *q, const orc_params *p, int32_t r, orc_repli
         }
 
         if (c > 0) {
-            /* Lines 11-13: uniform choice among the accepted flips, move, archive. */
+            /* Algorithm 3: uniform choice among the accepted flips, move, archive. */
             uint32_t ctr[4] = {0u, (uint32_t)t, (uint32_t)r, ORC_TAG_SEL};
             uint32_t o[4];
             orc_philox4x32_10(ctr, key, o);
@@ -480,7 +486,7 @@ int orc_mda_replica(const orc_qubo *q, const orc_params *p, int32_t r, orc_repli
             if (p->escape == ORC_ESC_OFFSET) {
                 Eoff += p->beta;   /* Algorithm 1: raise the offset */
             } else if (A.size > 0) {
-                /* Algorithm 3, line 15: continue from a random archive member. */
+                /* Algorithm 3 (escape): continue from a random archive member. */
                 uint32_t ca[4] = {0u, (uint32_t)t, (uint32_t)r, ORC_TAG_ARC};
                 uint32_t oa[4];
                 orc_philox4x32_10(ca, key, oa);

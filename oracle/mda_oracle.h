@@ -29,10 +29,12 @@
  *  R5 the dynamic offset of Algorithm 1 (E_offset <- 0 on a move, += beta when
  *     nothing is accepted) is applied inside the MDA by default; the MDA's own
  *     escape (restart from a random archive member, Algorithm 3) is a switch.
- *  R6 "choose one flip at random": uniform over the accepted bits counted in
- *     ascending bit index, k = floor(w * c / 2^32) for a 32-bit random word w.
- *  R7 archive: fixed capacity s; "first" = lowest slot; equivalent points are
- *     appended while not full; dominance compares energies only.
+ *  R6 the flip made among the accepted ones (Algorithm 3) is drawn uniformly
+ *     over the accepted bits counted in ascending bit index,
+ *     k = floor(w * c / 2^32) for a 32-bit random word w.
+ *  R7 archive: fixed capacity s; the first dominated member is the lowest
+ *     slot; equivalent points are appended while not full; dominance compares
+ *     energies only.
  */
 #ifndef MDA_ORACLE_H
 #define MDA_ORACLE_H
@@ -143,6 +145,10 @@ typedef struct {
     int64_t beta;
     int32_t accept, archive, escape, archive_size;
     uint64_t seed;
+    /* The schedule as input data: when not NULL, T_t = temp_table[t-1] for
+     * t = 1..steps (fixed point, 8 fractional bits) replaces the geometric
+     * cooling of delta0, deltaf and xi (Table param). */
+    const int64_t *temp_table;
 } orc_params;
 
 typedef struct {

@@ -37,7 +37,9 @@ _u32p = np.ctypeslib.ndpointer(np.uint32, flags="C_CONTIGUOUS")
 
 def build(force: bool = True) -> str:
     """Compiles the oracle with gcc (plain -O2, no fast-math, no contraction)."""
-    if force or not os.path.exists(_SO):
+    stale = os.path.exists(_SO) and any(
+        os.path.getmtime(src) > os.path.getmtime(_SO) for src in (_SRC, os.path.join(_HERE, "mda_oracle.h")))
+    if force or stale or not os.path.exists(_SO):
         tmp = _SO + ".tmp%d" % os.getpid()
         subprocess.check_call([
             "gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-ffp-contract=off",
@@ -61,6 +63,7 @@ class _Params(C.Structure):
         ("steps", C.c_int64), ("delta0", C.c_double), ("deltaf", C.c_double), ("xi", C.c_double),
         ("beta", C.c_int64), ("accept", C.c_int32), ("archive", C.c_int32),
         ("escape", C.c_int32), ("archive_size", C.c_int32), ("seed", C.c_uint64),
+        ("temp_table", C.c_void_p),
     ]
 
 
@@ -317,8 +320,11 @@ def default_schedule(maxabs_c: int, steps: int):
 
 def run_replica(q: Qubo, r: int, steps: int, delta0: float, deltaf: float, xi: float,
                 beta: int, seed: int, accept: int = STRICT, archive: int = EXPLORE,
-                escape: int = ESC_OFFSET, archive_size: int = 0, trace: bool = False) -> dict:
-    """Runs replica r of Algorithm 3 and returns its final state and raw archive."""
+                escape: int = ESC_OFFSET, archive_size: int = 0, trace: bool = False,
+                temp_table=None) -> dict:
+    """Runs replica r of Algorithm 3 and returns its final state and raw archive.
+    temp_table (steps int64 entries, T_t in fixed point) replaces the geometric
+    schedule of delta0, deltaf and xi when given."""
     m = q.m
     s = archive_size if archive_size > 0 else m
     x = np.zeros(m, np.uint8)
@@ -332,8 +338,14 @@ def run_replica(q: Qubo, r: int, steps: int, delta0: float, deltaf: float, xi: f
     out = _ReplicaOut(x.ctypes.data, h1.ctypes.data, h2.ctypes.data, state.ctypes.data,
                       asz.ctypes.data, ae.ctypes.data, ax.ctypes.data,
                       tr.ctypes.data if trace else None)
+    tt = None
+    if temp_table is not None:
+        tt = np.ascontiguousarray(temp_table, np.int64)
+        if tt.shape != (int(steps),):
+            raise ValueError("temp_table needs one entry per step")
     p = _Params(int(steps), float(delta0), float(deltaf), float(xi), int(beta), accept, archive,
-                escape, int(archive_size), int(seed) & 0xFFFFFFFFFFFFFFFF)
+                escape, int(archive_size), int(seed) & 0xFFFFFFFFFFFFFFFF,
+                tt.ctypes.data if tt is not None else None)
     rc = lib().orc_mda_replica(C.byref(q._q), C.byref(p), int(r), C.byref(out))
     if rc != 0:
         raise ValueError("oracle run failed: %d" % rc)

@@ -622,6 +622,7 @@ struct mda_run {
     DevPool pool;                      // this run's outputs and tables
     std::vector<FrontEntry> merged;    // non-dominated union over replicas, once computed
     bool merged_ok = false;
+    std::function<void()> on_release;  // set by the serving engine
     ~mda_run()
     {
         if (launch) {
@@ -631,6 +632,7 @@ struct mda_run {
         pool.release_all();
         launch.reset();
         if (q) qubo_release(q);
+        if (on_release) on_release();
     }
 };
 
@@ -656,7 +658,9 @@ static int prepare_run(mda_qubo *q, const mda_params *pin, hipStream_t stream, m
     mda_params p = *pin;
     if (p.replicas < 1) return fail(MDA_EINVAL, "replicas = %d", p.replicas);
     if (p.steps == 0) p.steps = (int64_t)std::llround(0.25 * (double)q->m * (double)q->m);
-    if (p.steps < 1 || p.steps > 0xFFFFFFFFLL) return fail(MDA_EINVAL, "steps = %lld", (long long)p.steps);
+    // the kernels count steps t = 1..steps in 32 bits and stop after t == steps
+    if (p.steps < 1 || p.steps > 0xFFFFFFFELL)
+        return fail(MDA_EINVAL, "steps = %lld outside [1, 2^32 - 2]", (long long)p.steps);
     if (p.accept != MDA_STRICT && p.accept != MDA_LENIENT) return fail(MDA_EINVAL, "accept = %d", p.accept);
     if (p.archive != MDA_EXPLORE && p.archive != MDA_EXPLOIT) return fail(MDA_EINVAL, "archive = %d", p.archive);
     if (p.escape != MDA_ESC_OFFSET && p.escape != MDA_ESC_ARCHIVE) return fail(MDA_EINVAL, "escape = %d", p.escape);
@@ -674,7 +678,13 @@ static int prepare_run(mda_qubo *q, const mda_params *pin, hipStream_t stream, m
     if (p.beta < 0) p.beta = std::max<int64_t>(1, (int64_t)std::floor(p.delta0 / (double)p.steps));
 
     std::vector<int64_t> T;
-    temperature_table(p.delta0, p.deltaf, p.xi, p.steps, T);
+    if (p.temp_table) {
+        // the schedule given as data: one entry per step, copied here
+        T.assign(p.temp_table, p.temp_table + p.steps);
+        p.temp_table = nullptr;
+    } else {
+        temperature_table(p.delta0, p.deltaf, p.xi, p.steps, T);
+    }
     int32_t lnt[4096];
     threshold_table(lnt);
     std::vector<uint32_t> thrmax(T.size());
@@ -1254,6 +1264,11 @@ int set_error(int code, const char *msg)
 int64_t qubo_device_bytes(const mda_qubo *q)
 {
     return q->pool.total;
+}
+
+void set_release_hook(mda_run *r, std::function<void()> hook)
+{
+    r->on_release = std::move(hook);
 }
 
 }  // namespace mda

@@ -3,6 +3,8 @@
 
 #include <stdint.h>
 
+#include <functional>
+
 #include "mda.h"
 
 namespace mda {
@@ -19,5 +21,9 @@ int set_error(int code, const char *msg);
 
 // Device bytes held by the QUBO handle.
 int64_t qubo_device_bytes(const mda_qubo *q);
+
+// Called once, from da_run_free, after the run's device memory (and its
+// reference to the QUBO) has been released.
+void set_release_hook(mda_run *r, std::function<void()> hook);
 
 }  // namespace mda

@@ -8,6 +8,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <condition_variable>
 #include <cstdarg>
@@ -42,9 +43,11 @@ struct Request {
     std::vector<int32_t> F1, F2, D;
     mda_build_opts bo{};
     mda_params p{};
+    std::vector<int64_t> T;   // the request's own copy of p.temp_table, if given
     double t_submit = 0, t_admit = 0, t_launch = 0, t_done = 0;
     int64_t footprint = 0;
     int32_t batch = 0;
+    int32_t slot = -1;
     mda_qubo *q = nullptr;
     mda_run *run = nullptr;
     int status = 0;   // 0 pending, 1 on the device, 2 done, < 0 failed (an MDA_E* code)
@@ -68,7 +71,11 @@ struct mda_server {
     std::deque<std::shared_ptr<Request>> pending;
     std::map<int64_t, std::shared_ptr<Request>> live;   // submitted and not yet collected
     std::vector<Flight> flights;
-    int64_t used = 0;
+    // device bytes of admitted requests whose runs still hold their memory: a
+    // run's footprint is returned when its device memory is freed (da_run_free,
+    // by the server or by the client that collected it, before or after
+    // mda_server_destroy), so the counter outlives the server
+    std::shared_ptr<std::atomic<int64_t>> used = std::make_shared<std::atomic<int64_t>>(0);
     int64_t next_id = 1;
     bool stop = false;
     std::thread worker;
@@ -125,7 +132,7 @@ void mda_server::run_worker()
             }
         if (slot >= 0 && !pending.empty()) {
             std::vector<std::shared_ptr<Request>> batch;
-            int64_t left = o.hbm_budget - used;
+            int64_t left = o.hbm_budget - used->load();
             while (!pending.empty() && (int)batch.size() < o.max_batch) {
                 auto r = pending.front();
                 if (r->footprint > o.hbm_budget) {
@@ -141,7 +148,7 @@ void mda_server::run_worker()
                 batch.push_back(r);
             }
             if (!batch.empty()) {
-                for (auto &r : batch) used += r->footprint;
+                for (auto &r : batch) used->fetch_add(r->footprint);
                 busy[slot] = 1;
                 hipStream_t st = streams[slot];
                 const double ta = now();
@@ -178,7 +185,7 @@ void mda_server::run_worker()
                 }
                 for (auto &r : batch) {
                     if (r->status < 0) {
-                        used -= r->footprint;
+                        used->fetch_sub(r->footprint);
                         if (r->q) qubo_free(r->q);
                         r->q = nullptr;
                     }
@@ -187,10 +194,14 @@ void mda_server::run_worker()
                 fl.slot = slot;
                 for (size_t k = 0; k < ok.size(); ++k) {
                     if (rc) continue;
+                    const int64_t fp = ok[k]->footprint;
+                    std::shared_ptr<std::atomic<int64_t>> ctr = used;
+                    mda::set_release_hook(outs[k], [ctr, fp] { ctr->fetch_sub(fp); });
                     ok[k]->run = outs[k];
                     ok[k]->status = 1;
                     ok[k]->t_launch = tl;
                     ok[k]->batch = (int32_t)ok.size();
+                    ok[k]->slot = slot;
                     fl.reqs.push_back(ok[k]);
                 }
                 if (!fl.reqs.empty()) {
@@ -204,8 +215,10 @@ void mda_server::run_worker()
                 continue;   // look again at once: more may fit on another stream
             }
         }
-        // 3. wait for work or for the device
-        if (flights.empty()) cv_work.wait(lk);
+        // 3. wait for work, for the device, or (requests waiting for memory
+        // that collected runs still hold) for a release
+        if (flights.empty() && pending.empty()) cv_work.wait(lk);
+        else if (flights.empty()) cv_work.wait_for(lk, std::chrono::milliseconds(1));
         else cv_work.wait_for(lk, std::chrono::microseconds(200));
     }
 }
@@ -265,6 +278,10 @@ extern "C" int mda_server_submit(mda_server *s, int32_t n, const int32_t *F1, co
     r->D.assign(D, D + nn);
     r->bo = bo ? *bo : mda_build_opts{MDA_PEN_2MAX, MDA_PATH_AUTO, 0};
     r->p = *p;
+    if (p->temp_table) {
+        r->T.assign(p->temp_table, p->temp_table + p->steps);
+        r->p.temp_table = r->T.data();
+    }
     r->footprint = mda_footprint(n, p, &r->bo);
     if (r->footprint < 0) return (int)r->footprint;
     std::lock_guard<std::mutex> g(s->mu);
@@ -301,14 +318,15 @@ extern "C" int mda_server_wait(mda_server *s, int64_t ticket, double timeout_s, 
         info->bit_trials = (int64_t)r->n * r->n * (int64_t)r->p.replicas * r->p.steps;
         info->footprint = r->footprint;
         info->batch = r->batch;
+        info->slot = r->slot;
     }
     const int st = r->status;
     const std::string msg = r->msg;
     if (st == 2) {
+        // the footprint is returned when the run is freed (its release hook)
         if (run) *run = r->run;
         else da_run_free(r->run);
         r->run = nullptr;
-        s->used -= r->footprint;
     }
     s->live.erase(it);
     s->cv_work.notify_all();
@@ -326,7 +344,7 @@ extern "C" int mda_server_stats(mda_server *s, mda_server_counters *out)
     out->bit_trials = s->bit_trials;
     out->pending = (int64_t)s->pending.size();
     out->in_flight = (int64_t)s->flights.size();
-    out->hbm_used = s->used;
+    out->hbm_used = s->used->load();
     out->hbm_budget = s->o.hbm_budget;
     out->now = s->now();
     out->first_launch = s->first_launch;

@@ -314,7 +314,7 @@ __device__ __forceinline__ void archive_update(Desc *Dp, int n, Replica<NS> &S, 
     }
 }
 
-// Random start (Algorithm 3, line 2): bit (i, u) is bit i of the 64-bit word
+// Random start (Algorithm 3): bit (i, u) is bit i of the 64-bit word
 // (o.x, o.y) of Philox block (0, u); fields and energies from scratch.
 template <int NS, int PV>
 __device__ __forceinline__ void init_replica(Desc *Dp, Replica<NS> &S, int r, int lane)

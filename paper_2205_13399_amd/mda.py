@@ -54,7 +54,8 @@ class Params(C.Structure):
                 ("beta", C.c_int64), ("accept", C.c_int32), ("archive", C.c_int32),
                 ("escape", C.c_int32), ("variant", C.c_int32), ("seed", C.c_uint64),
                 ("trace_replicas", C.c_int32), ("waves_per_block", C.c_int32),
-                ("stream", C.c_void_p), ("graph", C.c_int32), ("waves_per_replica", C.c_int32)]
+                ("stream", C.c_void_p), ("graph", C.c_int32), ("waves_per_replica", C.c_int32),
+                ("temp_table", C.c_void_p)]
 
 
 class ArchiveOut(C.Structure):
@@ -85,7 +86,7 @@ class RequestInfo(C.Structure):
     _fields_ = [("ticket", C.c_int64), ("n", C.c_int32), ("status", C.c_int32),
                 ("t_submit", C.c_double), ("t_admit", C.c_double), ("t_launch", C.c_double),
                 ("t_done", C.c_double), ("bit_trials", C.c_int64), ("footprint", C.c_int64),
-                ("batch", C.c_int32), ("reserved", C.c_int32)]
+                ("batch", C.c_int32), ("slot", C.c_int32)]
 
 
 class ServerCounters(C.Structure):
@@ -302,7 +303,12 @@ def make_params(replicas: int, steps: int, seed: int, *, archive_size: int = 0,
                 delta0: float = 0.0, deltaf: float = 0.0, xi: float = 0.001, beta: int = -1,
                 accept: int = STRICT, archive: int = EXPLORE, escape: int = ESC_OFFSET,
                 variant: int = VARIANT_AUTO, trace_replicas: int = 0, waves_per_block: int = 0,
-                stream: Optional[int] = None, graph: bool = False, waves_per_replica: int = 0) -> Params:
+                stream: Optional[int] = None, graph: bool = False, waves_per_replica: int = 0,
+                temp_table: Optional[np.ndarray] = None) -> Params:
+    """A parameter block (mda_params).  temp_table: steps int64 entries of T_t
+    (fixed point, 8 fractional bits) in place of the geometric schedule; the
+    array is kept alive with the returned block and copied by the library when
+    a run starts."""
     p = Params()
     lib().mda_params_default(C.byref(p))
     p.replicas = int(replicas)
@@ -323,6 +329,12 @@ def make_params(replicas: int, steps: int, seed: int, *, archive_size: int = 0,
     p.waves_per_replica = int(waves_per_replica)
     s = current_stream_handle() if stream is None else stream
     p.stream = C.c_void_p(s) if s else None
+    if temp_table is not None:
+        tt = np.ascontiguousarray(temp_table, np.int64)
+        if tt.shape != (int(steps),):
+            raise ValueError("temp_table needs one entry per step")
+        p._temp_keep = tt
+        p.temp_table = tt.ctypes.data
     return p
 
 

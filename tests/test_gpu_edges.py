@@ -7,7 +7,8 @@
   - degenerate instances: every flow zero (both objectives vanish, only the
     penalty is left), and equal objectives (F1 = F2, so e1 = e2 on every state
     and the merged front is a single point);
-  - the argument errors of da_run, da_state_get and archive_get.
+  - the argument errors of da_run, da_state_get and archive_get (including a
+    step count of 2^32 - 1 and temperature tables out of range).
 Every replica's trajectory, final state and raw archive are compared bit for bit.
 """
 import numpy as np
@@ -116,6 +117,9 @@ def test_argument_errors(mda):
     assert code(replicas=0) == mda.MDA_EINVAL
     assert code(steps=-1) == mda.MDA_EINVAL
     assert code(steps=1 << 32) == mda.MDA_EINVAL
+    assert code(steps=(1 << 32) - 1) == mda.MDA_EINVAL             # t would wrap before reaching it
+    assert code(steps=10, temp_table=np.full(10, 1 << 44)) == mda.MDA_EOVERFLOW
+    assert code(steps=10, temp_table=np.full(10, -1)) == mda.MDA_EOVERFLOW
     assert code(accept=2) == mda.MDA_EINVAL
     assert code(archive=2) == mda.MDA_EINVAL
     assert code(escape=2) == mda.MDA_EINVAL

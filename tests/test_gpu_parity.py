@@ -95,6 +95,15 @@ def test_negative_entries(mda, penalty):
         assert (q.info().alpha1, q.info().alpha2) == (oq.alpha[0], oq.alpha[1])
 
 
+@pytest.mark.parametrize("path", [1, 2])
+def test_plain_form_against_oracle(mda, path):
+    """The plain form (one launch per annealing step, state in HBM) on the
+    n = 8 configuration (16 replicas x 10^4 steps, seed 0), every replica
+    bit-exact against the oracle: trajectory, final state, raw archive."""
+    inst = synth.make_instance(8, 0.0, seed=0, structured=False)
+    _check_all(mda, inst, 16, 10000, 0, path=path, variant=mda.VARIANT_PLAIN)
+
+
 def test_plain_form_equals_persistent(mda):
     inst = synth.make_instance(9, 0.0, seed=5)
     steps, R = 1200, 5

@@ -13,7 +13,7 @@ import pytest
 
 import oracle
 import synth
-from tests.gpu_common import compare_replica, oracle_kwargs
+from tests.gpu_common import compare_replica, oracle_kwargs, sample_replicas
 from tests.oracle_jobs import run_replicas
 
 pytestmark = [pytest.mark.gpu, pytest.mark.timeout(900)]
@@ -63,11 +63,14 @@ def _picks(insts, count=10, seed=3):
 
 
 def test_sampled_instances_against_oracle(batch):
+    """12 instances (the smallest, the largest and 10 seeded picks), 16
+    replicas each (0, 1, R - 1 and 13 seeded picks)."""
     insts, qs, runs, _ = batch
-    for k in _picks(insts):
+    for k in _picks(insts, count=12):
         inst = insts[k]
         oq = oracle.Qubo(inst.F1, inst.F2, inst.D)
-        reps = [0, R - 1]
+        reps = sample_replicas(R, extra=13, seed=300 + k)
+        assert len(reps) == 16
         res = run_replicas(inst.F1, inst.F2, inst.D, reps, **oracle_kwargs(oq, STEPS, inst.seed, trace=False))
         for r in reps:
             compare_replica(runs[k], res[r], r, trace=False, label="batch instance %d (n=%d)" % (k, inst.n))

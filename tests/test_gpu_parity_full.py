@@ -2,12 +2,14 @@
 benchmark times.
 
   n = 25, rho = 0.75, 1024 replicas x 10^5 steps, dense and Kronecker updates:
-      sampled replicas bit-exact against the oracle (whole trajectory, final
-      state, raw archive); the two update paths identical on every replica.
+      every replica bit-exact against the oracle (final state, raw archive),
+      16 of them also step by step (whole trajectory); the two update paths
+      identical on every replica.
   n = 50, rho in {-0.75, 0, 0.75}, 4096 replicas x 10^5 steps, the three
-      instances in one persistent launch: sampled replicas bit-exact against
-      the oracle (final state and raw archive); the merged front checked for
-      the properties that hold at any size.
+      instances in one persistent launch: 16 replicas per instance (0, 1,
+      R - 1 and 13 seeded picks) bit-exact against the oracle (final state and
+      raw archive); the merged front checked for the properties that hold at
+      any size.
 """
 import numpy as np
 import pytest
@@ -46,21 +48,33 @@ def n25(mda):
         run = mda.da_run(q, mda.make_params(R, STEPS, inst.seed, trace_replicas=R))
         run.sync()
         runs[path] = run
-    picks = sample_replicas(R, extra=5, seed=25)
+    picks = sample_replicas(R, extra=13, seed=25)
     oq = oracle.Qubo(inst.F1, inst.F2, inst.D)
-    res = run_replicas(inst.F1, inst.F2, inst.D, picks, **oracle_kwargs(oq, STEPS, inst.seed))
-    return inst, R, runs, res
+    print("n=25: oracle on all %d replicas" % R, flush=True)
+    res = run_replicas(inst.F1, inst.F2, inst.D, range(R), **oracle_kwargs(oq, STEPS, inst.seed, trace=False))
+    print("n=25: oracle trajectories of %d replicas" % len(picks), flush=True)
+    traced = run_replicas(inst.F1, inst.F2, inst.D, picks, **oracle_kwargs(oq, STEPS, inst.seed))
+    return inst, R, runs, res, traced
 
 
 @pytest.mark.parametrize("path", [1, 2])
-def test_n25_sampled_replicas(n25, path):
-    inst, R, runs, res = n25
-    for r, o in res.items():
+def test_n25_all_replicas(n25, path):
+    inst, R, runs, res, traced = n25
+    assert len(res) == R
+    for r in range(R):
+        compare_replica(runs[path], res[r], r, trace=False, label="n=25 path=%d" % path)
+
+
+@pytest.mark.parametrize("path", [1, 2])
+def test_n25_sampled_trajectories(n25, path):
+    inst, R, runs, res, traced = n25
+    assert len(traced) == 16
+    for r, o in traced.items():
         compare_replica(runs[path], o, r, label="n=25 path=%d" % path)
 
 
 def test_n25_dense_equals_kronecker(n25):
-    inst, R, runs, res = n25
+    inst, R, runs, res, traced = n25
     for r in range(R):
         a, b = runs[1].state(r, trace=True), runs[2].state(r, trace=True)
         assert np.array_equal(a["trace"], b["trace"]), r
@@ -75,7 +89,7 @@ def test_n25_dense_equals_kronecker(n25):
 def test_n25_front_equals_union_of_archives(n25):
     """The merged front (filtered on the device, merged on the host) equals the
     non-dominated set of the union of every replica's raw archive."""
-    inst, R, runs, res = n25
+    inst, R, runs, res, traced = n25
     e1, e2, rep, slot = [], [], [], []
     for r in range(R):
         a = runs[2].archive(r, raw=True, bits=False)
@@ -117,7 +131,8 @@ def n50(mda):
 def test_n50_sampled_replicas(n50, k):
     insts, R, qs, runs = n50
     inst = insts[k]
-    picks = sample_replicas(R, extra=5, seed=50 + k)
+    picks = sample_replicas(R, extra=13, seed=50 + k)
+    assert len(picks) == 16
     oq = oracle.Qubo(inst.F1, inst.F2, inst.D)
     res = run_replicas(inst.F1, inst.F2, inst.D, picks, **oracle_kwargs(oq, STEPS, inst.seed, trace=False))
     for r, o in res.items():

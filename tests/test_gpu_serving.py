@@ -35,9 +35,9 @@ def _requests():
     return out
 
 
-def _same_as_alone(mda, inst, path, run):
+def _same_as_alone(mda, inst, path, run, steps=STEPS):
     q = mda.Qubo(inst.F1, inst.F2, inst.D, path=path)
-    alone = mda.da_run(q, mda.make_params(R, STEPS, inst.seed, trace_replicas=R))
+    alone = mda.da_run(q, mda.make_params(R, steps, inst.seed, trace_replicas=R))
     for r in range(R):
         a, b = alone.state(r, trace=True), run.state(r, trace=True)
         assert np.array_equal(a["trace"], b["trace"]), (inst.n, r)
@@ -46,10 +46,10 @@ def _same_as_alone(mda, inst, path, run):
     assert np.array_equal(fa.e1, fb.e1) and np.array_equal(fa.e2, fb.e2) and np.array_equal(fa.xbits, fb.xbits)
 
 
-def _serve(mda, srv, reqs, gap=0.0):
+def _serve(mda, srv, reqs, gap=0.0, steps=STEPS):
     tickets = []
     for inst, path in reqs:
-        tickets.append(srv.submit(inst.F1, inst.F2, inst.D, mda.make_params(R, STEPS, inst.seed, trace_replicas=R),
+        tickets.append(srv.submit(inst.F1, inst.F2, inst.D, mda.make_params(R, steps, inst.seed, trace_replicas=R),
                                   path=path))
         if gap:
             time.sleep(gap)
@@ -69,28 +69,68 @@ def test_mix_at_once(mda):
 
 
 def test_staggered_arrivals_overlap(mda):
+    """Requests arriving while earlier ones are on the device are launched on
+    another stream before those finish, and each result is the one it has alone."""
     srv = mda.Server(max_inflight=4)
     reqs = _requests()
-    got = _serve(mda, srv, reqs, gap=0.002)
+    got = _serve(mda, srv, reqs, gap=0.002, steps=20000)
     for (inst, path), (run, info) in zip(reqs, got):
-        _same_as_alone(mda, inst, path, run)
+        _same_as_alone(mda, inst, path, run, steps=20000)
     assert srv.stats()["launches"] >= 2
+    infos = [info for _, info in got]
+    overlapped = [(i, j) for i in range(len(infos)) for j in range(i + 1, len(infos))
+                  if infos[j]["t_launch"] < infos[i]["t_done"] and infos[j]["slot"] != infos[i]["slot"]
+                  and infos[j]["t_launch"] > infos[i]["t_launch"]]
+    assert overlapped, [(k["t_launch"], k["t_done"], k["slot"]) for k in infos]
     srv.close()
 
 
 def test_budget_limits_admission(mda):
     """With room for the largest request only, it cannot share a launch with
-    the requests admitted before it; memory returns as results are collected."""
+    the requests admitted before it.  A collected run keeps its memory, so its
+    footprint stays on the budget until the run is freed."""
+    import gc
     reqs = _requests()
     sizes = [mda.footprint(i.n, mda.make_params(R, STEPS, 1, trace_replicas=R), path=p) for i, p in reqs]
     big = int(np.argmax(sizes))
     srv = mda.Server(hbm_budget=max(sizes) + 1, max_inflight=4)
-    got = _serve(mda, srv, reqs)
-    for k, ((inst, path), (run, info)) in enumerate(zip(reqs, got)):
+    got = []
+    for k, (inst, path) in enumerate(reqs):
+        t = srv.submit(inst.F1, inst.F2, inst.D, mda.make_params(R, STEPS, inst.seed, trace_replicas=R), path=path)
+        run, info = srv.wait(t, timeout=120.0)
         assert info["footprint"] == sizes[k]
         _same_as_alone(mda, inst, path, run)
-    assert got[big][1]["batch"] == 1
+        # the collected run still holds its memory
+        assert srv.stats()["hbm_used"] == sizes[k]
+        run.close()
+        del run
+        gc.collect()
+        assert srv.stats()["hbm_used"] == 0
+        got.append(info)
+    # all at once: the largest cannot share a launch; each run is closed as it
+    # is collected, which returns its memory to the budget for the next ones
+    tickets = [srv.submit(i.F1, i.F2, i.D, mda.make_params(R, STEPS, i.seed, trace_replicas=R), path=p)
+               for i, p in reqs]
+    infos = []
+    for t in tickets:
+        run, info = srv.wait(t, timeout=120.0)
+        run.close()
+        infos.append(info)
+    assert infos[big]["batch"] == 1
     assert srv.stats()["launches"] >= 2 and srv.stats()["hbm_used"] == 0
+    srv.close()
+
+
+def test_held_runs_keep_their_footprint(mda):
+    """Runs the client holds count against the budget until they are freed."""
+    reqs = _requests()
+    sizes = [mda.footprint(i.n, mda.make_params(R, STEPS, 1, trace_replicas=R), path=p) for i, p in reqs]
+    srv = mda.Server(max_inflight=4)
+    got = _serve(mda, srv, reqs)
+    assert srv.stats()["hbm_used"] == sum(sizes)
+    for k, (run, _) in enumerate(got):
+        run.close()
+        assert srv.stats()["hbm_used"] == sum(sizes[k + 1:])
     srv.close()
 
 

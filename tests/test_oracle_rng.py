@@ -72,7 +72,7 @@ def test_acceptance_frequency(orc, delta):
 
 
 def test_temperature_closed_form(orc):
-    """Algorithm 3 line 5: delta_t = delta0 (1-xi)^t until it first drops to
+    """Algorithm 3 (cooling): delta_t = delta0 (1-xi)^t until it first drops to
     delta_f or below, constant afterwards; T_t = floor(256 delta_t)."""
     d0, df, xi, steps = 2.0e6, 20.0, 0.001, 15000
     T = orc.temperature(d0, df, xi, steps)

@@ -31,12 +31,12 @@ def _init_x(orc, n, r, key):
     return x
 
 
-def _validate(orc, F1, F2, D, steps, seed, r, accept, archive, escape, d0, df, xi, beta, s=0):
+def _validate(orc, F1, F2, D, steps, seed, r, accept, archive, escape, d0, df, xi, beta, s=0, table=None):
     n = D.shape[0]
     m = n * n
     q = orc.Qubo(F1, F2, D)
     res = orc.run_replica(q, r, steps, d0, df, xi, beta, seed, accept=accept, archive=archive,
-                          escape=escape, archive_size=s, trace=True)
+                          escape=escape, archive_size=s, trace=True, temp_table=table)
     Y = [q.Y(1), q.Y(2)]
     qc = list(q.q)
     key = [seed & 0xFFFFFFFF, seed >> 32]
@@ -54,7 +54,7 @@ def _validate(orc, F1, F2, D, steps, seed, r, accept, archive, escape, d0, df, x
     for t in range(1, steps + 1):
         if delta > df:
             delta = delta * (1.0 - xi)
-        T = int(math.floor(delta * 256.0))
+        T = int(math.floor(delta * 256.0)) if table is None else int(table[t - 1])
         acc = []
         dEs = []
         for a in range(m):
@@ -112,6 +112,21 @@ def test_trajectory_bruteforce_n4(orc):
     d0, df, xi, beta = orc.default_schedule(q.maxabs_c, 300)
     res = _validate(orc, F1, F2, D, 300, (7 << 32) | 99, 5, 0, 0, 0, d0, df, 0.01, beta)
     assert res["moves"] > 50
+
+
+def test_trajectory_bruteforce_given_schedule(orc):
+    """The schedule as input data: T_t read from a table (cooling with a
+    reheat half-way and a stretch at T = 0) instead of the geometric loop."""
+    F1, F2, D = _small_instance(3, 4)
+    q = orc.Qubo(F1, F2, D)
+    d0, df, xi, beta = orc.default_schedule(q.maxabs_c, 400)
+    t = np.arange(400)
+    table = np.floor(d0 * 256.0 * 0.98 ** (t % 200)).astype(np.int64)
+    table[300:340] = 0
+    res = _validate(orc, F1, F2, D, 400, 4242, 1, 0, 0, 0, d0, df, xi, beta, table=table)
+    # the table, not the geometric loop, drove the run
+    other = orc.run_replica(q, 1, 400, d0, df, xi, beta, 4242, trace=True)
+    assert not np.array_equal(res["trace"], other["trace"])
 
 
 def _fields(P, x):
