@@ -331,6 +331,70 @@ int mda_server_stats(mda_server *s, mda_server_counters *st);
 /* Fails requests not yet admitted, waits for launched ones, frees uncollected results. */
 void mda_server_destroy(mda_server *s);
 
+/* ---------------- runs into caller-owned buffers, allocating nothing ----------------
+ *
+ * For callers that cannot allocate device memory: code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation.  The
+ * variant of da_run below writes every result into device buffers the caller
+ * owns and keeps the launch's own data (run descriptor, work list, -ln table,
+ * temperature tables) in a fixed scratch area of MDA_NOALLOC_SCRATCH_BYTES
+ * that the library holds on each device it has run on until the process ends.
+ * It calls no hipMalloc, hipFree or allocator callback.
+ *
+ * Every call on one device shares that device's scratch area and overwrites
+ * it (nothing in it has to start at zero): calls on the same stream run in
+ * order, calls that overlap on one device (different streams, other threads)
+ * race and must not be made.
+ */
+#define MDA_NOALLOC_SCRATCH_BYTES ((int64_t)4 << 20)
+
+typedef struct {
+    int32_t n, m, replicas;
+    int32_t archive_size;      /* s, resolved */
+    int64_t steps;             /* resolved step count */
+    int32_t trace_replicas;
+    int32_t wr, wc, gns;       /* layout over waves: wr x wc waves per replica (1 x 1: one wave), gns
+                                  facilities per wave row */
+    int64_t x_words;           /* uint64 words of x per replica: 64 (one wave) or wr * wc * 64 */
+    int64_t arch_x_words;      /* uint64 words per archived solution: n (one wave) or wr * wc * 64 */
+    /* element counts of the buffers of mda_run_buffers */
+    int64_t n_x, n_h, n_st, n_arch_e, n_arch_x, n_nd, n_trace;
+    int64_t scratch_bytes;     /* of the scratch area this run needs (<= MDA_NOALLOC_SCRATCH_BYTES) */
+} mda_run_layout;
+
+/* Sizes of the buffers da_run_noalloc writes for q and p (host only; the
+ * checks of da_run are applied).  Errors: those of da_run's argument checks,
+ * MDA_ERANGE when the run's work list and tables need more scratch than
+ * MDA_NOALLOC_SCRATCH_BYTES (layout still filled). */
+int da_run_layout(const mda_qubo *q, const mda_params *p, mda_run_layout *out);
+
+/* Device buffers of one run, owned by the caller, sized by da_run_layout.
+ * Solution words: with one wave per replica, word u (u < n) holds location u's
+ * column, bit i = x_{i,u}; with a workgroup, word (p*wc + c)*64 + (u mod 64)
+ * with c = u / 64 holds bit i - p*gns = x_{i,u} for facilities
+ * i in [p*gns, p*gns + gns). */
+typedef struct {
+    uint64_t *x;       /* [R][x_words] final solution */
+    int32_t *h;        /* [R][2][m] final local fields h_1, h_2 at bit a = i*n + u */
+    int64_t *st;       /* [R][16] E_1, E_2, E_offset, moves, archive entries compared, random blocks drawn,
+                          archive size, steps with an exact acceptance test, non-dominated count; rest unused */
+    int64_t *arch_e;   /* [R][s][2] archive energies (E_1, E_2) in slot order; slots [0, size) are defined */
+    uint64_t *arch_x;  /* [R][s][arch_x_words] archived solutions */
+    uint8_t *nd;       /* [R][s] 1 = not dominated within its archive; slots [0, size) are defined */
+    int32_t *trace;    /* [trace_replicas][steps] flipped bit or -1; NULL when trace_replicas = 0 */
+} mda_run_buffers;
+
+/* da_run of q with parameters p, results in b instead of a run handle: the
+ * same trajectories, states, archives and flags as da_run.  Asynchronous on
+ * p->stream; the caller synchronises before reading b.  Host arrays (p and
+ * p->temp_table) may be released when it returns.  p->variant must not be
+ * MDA_VARIANT_PLAIN and p->graph must be 0.  Errors: MDA_EINVAL (a NULL
+ * argument or buffer, the plain form, the graph flag, and the argument checks
+ * of da_run), MDA_ERANGE (more than MDA_NOALLOC_SCRATCH_BYTES of scratch
+ * needed: replicas * 8 + steps * 12 bytes, roughly, with a temp_table or a
+ * schedule that keeps cooling), MDA_EOVERFLOW, MDA_EDEVICE. */
+int da_run_noalloc(const mda_qubo *q, const mda_params *p, const mda_run_buffers *b);
+
 /* Debug/verification exports: the library's own host tables.
  * mda_temperature_table errors: MDA_EINVAL (NULL T, steps < 1), MDA_EOVERFLOW
  * (delta0 above 2^35, the largest starting temperature a run accepts). */

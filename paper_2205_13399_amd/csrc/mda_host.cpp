@@ -653,9 +653,14 @@ extern "C" void mda_params_default(mda_params *p)
     p->variant = MDA_VARIANT_AUTO;
 }
 
-static int prepare_run(mda_qubo *q, const mda_params *pin, hipStream_t stream, mda_run **out)
+// Checks p against q, resolves its defaults and fills the run descriptor d
+// (every field but the device buffers of the run) and the host tables: the
+// fixed-point temperature T_t and the largest threshold (T_t LNT[0]) >> 24 of
+// each step.  Allocates nothing on the device.
+static int resolve_run(const mda_qubo *q, const mda_params *pin, mda_params &p, RunDesc &d, std::vector<int64_t> &T,
+                       std::vector<uint32_t> &thrmax)
 {
-    mda_params p = *pin;
+    p = *pin;
     if (p.replicas < 1) return fail(MDA_EINVAL, "replicas = %d", p.replicas);
     if (p.steps == 0) p.steps = (int64_t)std::llround(0.25 * (double)q->m * (double)q->m);
     // the kernels count steps t = 1..steps in 32 bits and stop after t == steps
@@ -677,7 +682,7 @@ static int prepare_run(mda_qubo *q, const mda_params *pin, hipStream_t stream, m
     if (!(p.delta0 * 256.0 <= kMaxTemp)) return fail(MDA_EOVERFLOW, "delta0 = %g exceeds 2^35", p.delta0);
     if (p.beta < 0) p.beta = std::max<int64_t>(1, (int64_t)std::floor(p.delta0 / (double)p.steps));
 
-    std::vector<int64_t> T;
+    T.clear();
     if (p.temp_table) {
         // the schedule given as data: one entry per step, copied here
         T.assign(p.temp_table, p.temp_table + p.steps);
@@ -687,7 +692,7 @@ static int prepare_run(mda_qubo *q, const mda_params *pin, hipStream_t stream, m
     }
     int32_t lnt[4096];
     threshold_table(lnt);
-    std::vector<uint32_t> thrmax(T.size());
+    thrmax.assign(T.size(), 0u);
     for (size_t t = 0; t < T.size(); ++t) {
         if (T[t] < 0 || (double)T[t] > kMaxTemp) return fail(MDA_EOVERFLOW, "temperature %lld out of range", (long long)T[t]);
         // saturated like the kernels' thresholds: 2^32 - 2 exceeds every statistic
@@ -695,11 +700,8 @@ static int prepare_run(mda_qubo *q, const mda_params *pin, hipStream_t stream, m
         thrmax[t] = (uint32_t)std::min<uint64_t>(v, 0xFFFFFFFEull);
     }
 
-    std::unique_ptr<mda_run> r(new mda_run);
-    r->p = p;
     const int n = q->n, m = q->m, R = p.replicas;
     const int s = p.archive_size > 0 ? p.archive_size : m;
-    RunDesc &d = r->h;
     std::memset(&d, 0, sizeof d);
     d.n = n;
     d.m = m;
@@ -753,7 +755,22 @@ static int prepare_run(mda_qubo *q, const mda_params *pin, hipStream_t stream, m
     d.KA1 = q->dKA1; d.KA2 = q->dKA2; d.KB1 = q->dKB1; d.KB2 = q->dKB2; d.DA = q->dDA; d.DB = q->dDB;
     d.P1 = q->dP1; d.P2 = q->dP2;
     d.diag1 = q->ddiag1; d.diag2 = q->ddiag2;
+    d.ns_plain = ns_for(n);
+    return MDA_OK;
+}
 
+static int prepare_run(mda_qubo *q, const mda_params *pin, hipStream_t stream, mda_run **out)
+{
+    std::unique_ptr<mda_run> r(new mda_run);
+    std::vector<int64_t> T;
+    std::vector<uint32_t> thrmax;
+    {
+        const int rc = resolve_run(q, pin, r->p, r->h, T, thrmax);
+        if (rc) return rc;
+    }
+    const mda_params &p = r->p;
+    RunDesc &d = r->h;
+    const int m = q->m, R = p.replicas, s = d.s;
     DevPool &pool = r->pool;
     int64_t *dT = pool.alloc<int64_t>(T.size(), stream);
     uint32_t *dthr = pool.alloc<uint32_t>(T.size(), stream);
@@ -764,9 +781,7 @@ static int prepare_run(mda_qubo *q, const mda_params *pin, hipStream_t stream, m
     d.archX = pool.alloc<uint64_t>((size_t)R * s * d.xw, stream);
     d.nd = pool.alloc<uint8_t>((size_t)R * s, stream);
     d.trace = pool.alloc<int32_t>((size_t)std::max(1, p.trace_replicas) * (size_t)(p.trace_replicas ? p.steps : 1), stream);
-    const int ns = ns_for(n);
-    d.ns_plain = ns;
-    if (p.variant == MDA_VARIANT_PLAIN) d.pe = pool.alloc<int32_t>((size_t)R * 2 * ns * 64, stream);
+    if (p.variant == MDA_VARIANT_PLAIN) d.pe = pool.alloc<int32_t>((size_t)R * 2 * d.ns_plain * 64, stream);
     if (!dT || !dthr || !d.x || !d.h || !d.st || !d.archE || !d.archX || !d.nd || !d.trace ||
         (p.variant == MDA_VARIANT_PLAIN && !d.pe))
         return fail(MDA_ENOMEM, "device allocation failed for the run (%lld bytes so far)", (long long)pool.total);
@@ -788,6 +803,95 @@ static int default_block(int wpb)
     if (wpb > 4) wpb = 4;
     return 64 * wpb;
 }
+
+namespace {
+
+// One persistent launch: the work items [off, off + cnt) of one register tile
+// and replica layout.
+struct Group {
+    int ns, wr, wc, off, cnt;
+};
+
+// Work list of a launch: runs grouped by register tile, largest tile first
+// (one persistent launch per tile, each with the occupancy of its own register
+// budget); within a tile, largest instances first so that the round-robin
+// assignment ends with the short items.
+void plan_work(const std::vector<RunDesc> &descs, std::vector<WorkItem> &work, std::vector<Group> &groups)
+{
+    const int count = (int)descs.size();
+    std::vector<int> order(count);
+    for (int i = 0; i < count; ++i) order[i] = i;
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+        const RunDesc &x = descs[a], &y = descs[b];
+        if (x.wr * x.wc != y.wr * y.wc) return x.wr * x.wc > y.wr * y.wc;
+        if (x.wc != y.wc) return x.wc > y.wc;
+        if (x.gns != y.gns) return x.gns > y.gns;
+        return (int64_t)x.m * x.steps > (int64_t)y.m * y.steps;
+    });
+    work.clear();
+    groups.clear();
+    for (int i : order) {
+        const RunDesc &d = descs[i];
+        if (groups.empty() || groups.back().ns != d.gns || groups.back().wr != d.wr || groups.back().wc != d.wc)
+            groups.push_back(Group{d.gns, d.wr, d.wc, (int)work.size(), 0});
+        for (int rr = 0; rr < d.R; ++rr) work.push_back(WorkItem{i, rr});
+        groups.back().cnt += d.R;
+    }
+}
+
+// Enqueues the annealing kernel(s) of a planned launch on stream: the plain
+// form (one launch per step), or one persistent launch per group.  ddesc,
+// dwork and dlnt are the device copies of the descriptors, the work list and
+// the -ln table; cus is the device's compute-unit count.
+int enqueue_anneal(const std::vector<Group> &groups, const RunDesc &first, bool plain, const RunDesc *ddesc,
+                   const WorkItem *dwork, const int32_t *dlnt, int block, int cus, hipStream_t stream)
+{
+    if (plain) {
+        HIP_TRY(launch_plain(groups[0].ns, ddesc, first.R, first.steps, dlnt, block, stream));
+        return MDA_OK;
+    }
+    for (const Group &g : groups) {
+        int per_cu = 0;
+        if (g.wr * g.wc == 1) {
+            // one wave per SIMD when that holds every replica of the launch
+            // at once, the two-wave build when more are waiting
+            const int wpb = block / 64;
+            HIP_TRY(persistent_occupancy(g.ns, 1, block, &per_cu));
+            if (per_cu < 1) per_cu = 1;
+            const int occ = (int64_t)g.cnt > (int64_t)cus * per_cu * wpb ? 2 : 1;
+            if (occ == 2) {
+                HIP_TRY(persistent_occupancy(g.ns, 2, block, &per_cu));
+                if (per_cu < 1) per_cu = 1;
+            }
+            int grid = cus * per_cu;
+            const int need = (g.cnt + wpb - 1) / wpb;
+            if (grid > need) grid = need;
+            const hipError_t le = launch_persistent(g.ns, occ, ddesc, dwork + g.off, g.cnt, dlnt, grid, block, stream);
+            if (le != hipSuccess)
+                return fail(MDA_EDEVICE, "persistent launch (ns %d, grid %d, block %d, %d blocks/CU) failed: %s", g.ns,
+                            grid, block, per_cu, hipGetErrorString(le));
+        } else {
+            // one replica per workgroup of wr x wc waves; the two-workgroups-per-CU
+            // build when one per CU cannot hold every replica at once
+            HIP_TRY(group_occupancy(g.ns, 1, g.wr, g.wc, &per_cu));
+            if (per_cu < 1) per_cu = 1;
+            const int occ = (int64_t)g.cnt > (int64_t)cus * per_cu ? 2 : 1;
+            if (occ == 2) {
+                HIP_TRY(group_occupancy(g.ns, 2, g.wr, g.wc, &per_cu));
+                if (per_cu < 1) per_cu = 1;
+            }
+            int grid = cus * per_cu;
+            if (grid > g.cnt) grid = g.cnt;
+            const hipError_t le = launch_group(g.ns, occ, g.wr, g.wc, ddesc, dwork + g.off, g.cnt, dlnt, grid, stream);
+            if (le != hipSuccess)
+                return fail(MDA_EDEVICE, "workgroup launch (ns %d, %d x %d waves, grid %d, %d blocks/CU) failed: %s",
+                            g.ns, g.wr, g.wc, grid, per_cu, hipGetErrorString(le));
+        }
+    }
+    return MDA_OK;
+}
+
+}  // namespace
 
 extern "C" int da_run_batch(const mda_qubo *const *qs, const mda_params *ps, int32_t count, mda_run **outs)
 {
@@ -819,37 +923,10 @@ extern "C" int da_run_batch(const mda_qubo *const *qs, const mda_params *ps, int
     const bool graph = ps[0].graph != 0;
     if (graph && !stream) return fail(MDA_EINVAL, "graph launches need a created stream, not the default one");
     std::vector<RunDesc> descs;
-    // launch key of each run: register tile (slots per lane) and waves per replica
-    std::vector<int> tile(count), wrk(count), wck(count);
-    for (int i = 0; i < count; ++i) {
-        descs.push_back(runs[i]->h);
-        tile[i] = runs[i]->h.gns;
-        wrk[i] = runs[i]->h.wr;
-        wck[i] = runs[i]->h.wc;
-    }
-    // Work list: runs grouped by register tile, largest tile first (one
-    // persistent launch per tile, each with the occupancy of its own register
-    // budget); within a tile, largest instances first so that the round-robin
-    // assignment ends with the short items.
-    std::vector<int> order(count);
-    for (int i = 0; i < count; ++i) order[i] = i;
-    std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
-        if (wrk[a] * wck[a] != wrk[b] * wck[b]) return wrk[a] * wck[a] > wrk[b] * wck[b];
-        if (wck[a] != wck[b]) return wck[a] > wck[b];
-        if (tile[a] != tile[b]) return tile[a] > tile[b];
-        return (int64_t)descs[a].m * descs[a].steps > (int64_t)descs[b].m * descs[b].steps;
-    });
-    struct Group {
-        int ns, wr, wc, off, cnt;
-    };
+    for (int i = 0; i < count; ++i) descs.push_back(runs[i]->h);
     std::vector<Group> groups;
     std::vector<WorkItem> work;
-    for (int i : order) {
-        if (groups.empty() || groups.back().ns != tile[i] || groups.back().wr != wrk[i] || groups.back().wc != wck[i])
-            groups.push_back(Group{tile[i], wrk[i], wck[i], (int)work.size(), 0});
-        for (int rr = 0; rr < descs[i].R; ++rr) work.push_back(WorkItem{i, rr});
-        groups.back().cnt += descs[i].R;
-    }
+    plan_work(descs, work, groups);
     if (plain && groups.size() != 1) return fail(MDA_EINVAL, "the plain form runs one instance per call");
     L->nwork = (int)work.size();
     L->ddesc = L->pool.alloc<RunDesc>(descs.size(), stream);
@@ -874,50 +951,8 @@ extern "C" int da_run_batch(const mda_qubo *const *qs, const mda_params *ps, int
     // flags.  Either enqueued directly or captured into one graph.
     auto enqueue = [&](bool timed) -> int {
         if (timed) HIP_TRY(hipEventRecord(L->evk0, stream));
-        if (plain) {
-            HIP_TRY(launch_plain(groups[0].ns, L->ddesc, descs[0].R, descs[0].steps, L->dlnt, block, stream));
-        } else {
-            for (const Group &g : groups) {
-                int per_cu = 0;
-                if (g.wr * g.wc == 1) {
-                    // one wave per SIMD when that holds every replica of the launch
-                    // at once, the two-wave build when more are waiting
-                    const int wpb = block / 64;
-                    HIP_TRY(persistent_occupancy(g.ns, 1, block, &per_cu));
-                    if (per_cu < 1) per_cu = 1;
-                    const int occ = (int64_t)g.cnt > (int64_t)cus * per_cu * wpb ? 2 : 1;
-                    if (occ == 2) {
-                        HIP_TRY(persistent_occupancy(g.ns, 2, block, &per_cu));
-                        if (per_cu < 1) per_cu = 1;
-                    }
-                    int grid = cus * per_cu;
-                    const int need = (g.cnt + wpb - 1) / wpb;
-                    if (grid > need) grid = need;
-                    const hipError_t le =
-                        launch_persistent(g.ns, occ, L->ddesc, L->dwork + g.off, g.cnt, L->dlnt, grid, block, stream);
-                    if (le != hipSuccess)
-                        return fail(MDA_EDEVICE, "persistent launch (ns %d, grid %d, block %d, %d blocks/CU) failed: %s",
-                                    g.ns, grid, block, per_cu, hipGetErrorString(le));
-                } else {
-                    // one replica per workgroup of wr x wc waves; the two-workgroups-per-CU
-                    // build when one per CU cannot hold every replica at once
-                    HIP_TRY(group_occupancy(g.ns, 1, g.wr, g.wc, &per_cu));
-                    if (per_cu < 1) per_cu = 1;
-                    const int occ = (int64_t)g.cnt > (int64_t)cus * per_cu ? 2 : 1;
-                    if (occ == 2) {
-                        HIP_TRY(group_occupancy(g.ns, 2, g.wr, g.wc, &per_cu));
-                        if (per_cu < 1) per_cu = 1;
-                    }
-                    int grid = cus * per_cu;
-                    if (grid > g.cnt) grid = g.cnt;
-                    const hipError_t le =
-                        launch_group(g.ns, occ, g.wr, g.wc, L->ddesc, L->dwork + g.off, g.cnt, L->dlnt, grid, stream);
-                    if (le != hipSuccess)
-                        return fail(MDA_EDEVICE, "workgroup launch (ns %d, %d x %d waves, grid %d, %d blocks/CU) failed: %s",
-                                    g.ns, g.wr, g.wc, grid, per_cu, hipGetErrorString(le));
-                }
-            }
-        }
+        const int rc = enqueue_anneal(groups, descs[0], plain, L->ddesc, L->dwork, L->dlnt, block, cus, stream);
+        if (rc) return rc;
         if (timed) HIP_TRY(hipEventRecord(L->evk1, stream));
         HIP_TRY(launch_nondominated(L->ddesc, L->dwork, L->nwork, stream));
         return MDA_OK;
@@ -988,6 +1023,168 @@ extern "C" int da_kernel_ms(mda_run *r, double *ms)
 extern "C" void da_run_free(mda_run *r)
 {
     delete r;
+}
+
+// ---------------------------------------------------------------- runs without allocation
+
+namespace {
+
+// The scratch area of da_run_noalloc: run descriptor, work list, -ln table and
+// temperature tables of the latest call on this device.  Each device holds its
+// own copy; host code only ever uses the device address that
+// hipGetSymbolAddress returns for the current device.
+static __device__ __align__(256) uint8_t scratch[MDA_NOALLOC_SCRATCH_BYTES];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of the current device's scratch area, looked up once per
+// device with that device current.
+int scratch_address(void **out)
+{
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) return fail(MDA_EDEVICE, "device %d beyond the scratch table", dev);
+    std::lock_guard<std::mutex> g(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr)
+            return fail(MDA_EDEVICE, "hipGetSymbolAddress(scratch) on device %d failed: %s", dev, hipGetErrorString(e));
+        g_scratch_ptr[dev] = ptr;
+    }
+    *out = g_scratch_ptr[dev];
+    return MDA_OK;
+}
+
+size_t align256(size_t b)
+{
+    return (b + 255) & ~(size_t)255;
+}
+
+// Byte offsets of the parts of the scratch area for R work items and ntab
+// table entries; returns the total.
+struct ScratchPlan {
+    size_t desc, work, lnt, T, thr, total;
+};
+
+ScratchPlan scratch_plan(int64_t R, int64_t ntab)
+{
+    ScratchPlan sp;
+    sp.desc = 0;
+    sp.work = sp.desc + align256(sizeof(RunDesc));
+    sp.lnt = sp.work + align256((size_t)R * sizeof(WorkItem));
+    sp.T = sp.lnt + align256(4096 * sizeof(int32_t));
+    sp.thr = sp.T + align256((size_t)ntab * sizeof(int64_t));
+    sp.total = sp.thr + align256((size_t)ntab * sizeof(uint32_t));
+    return sp;
+}
+
+int fill_layout(const mda_params &p, const RunDesc &d, int64_t ntab, mda_run_layout *out)
+{
+    std::memset(out, 0, sizeof *out);
+    const int64_t R = d.R, s = d.s, m = d.m;
+    out->n = d.n;
+    out->m = d.m;
+    out->replicas = d.R;
+    out->archive_size = d.s;
+    out->steps = p.steps;
+    out->trace_replicas = p.trace_replicas;
+    out->wr = d.wr;
+    out->wc = d.wc;
+    out->gns = d.gns;
+    out->x_words = d.xrw;
+    out->arch_x_words = d.xw;
+    out->n_x = R * d.xrw;
+    out->n_h = R * 2 * m;
+    out->n_st = R * kStWords;
+    out->n_arch_e = R * s * 2;
+    out->n_arch_x = R * s * d.xw;
+    out->n_nd = R * s;
+    out->n_trace = (int64_t)p.trace_replicas * p.steps;
+    out->scratch_bytes = (int64_t)scratch_plan(R, ntab).total;
+    if (out->scratch_bytes > MDA_NOALLOC_SCRATCH_BYTES)
+        return fail(MDA_ERANGE, "the run needs %lld bytes of scratch (%d work items, %lld table entries); the "
+                                "limit is %lld", (long long)out->scratch_bytes, d.R, (long long)ntab,
+                    (long long)MDA_NOALLOC_SCRATCH_BYTES);
+    return MDA_OK;
+}
+
+}  // namespace
+
+extern "C" int da_run_layout(const mda_qubo *q, const mda_params *pin, mda_run_layout *out)
+{
+    if (!q || !pin || !out) return fail(MDA_EINVAL, "NULL argument");
+    mda_params p;
+    RunDesc d;
+    std::vector<int64_t> T;
+    std::vector<uint32_t> thrmax;
+    const int rc = resolve_run(q, pin, p, d, T, thrmax);
+    if (rc) return rc;
+    return fill_layout(p, d, (int64_t)T.size(), out);
+}
+
+extern "C" int da_run_noalloc(const mda_qubo *q, const mda_params *pin, const mda_run_buffers *b)
+{
+    if (!q || !pin || !b) return fail(MDA_EINVAL, "NULL argument");
+    if (pin->variant == MDA_VARIANT_PLAIN) return fail(MDA_EINVAL, "da_run_noalloc runs the persistent form only");
+    if (pin->graph) return fail(MDA_EINVAL, "da_run_noalloc launches directly (graph must be 0)");
+    if (!b->x || !b->h || !b->st || !b->arch_e || !b->arch_x || !b->nd)
+        return fail(MDA_EINVAL, "a result buffer is NULL");
+    if (pin->trace_replicas > 0 && !b->trace) return fail(MDA_EINVAL, "trace_replicas > 0 needs a trace buffer");
+    hipStream_t stream = (hipStream_t)pin->stream;
+    {
+        const hipError_t pending = hipGetLastError();
+        if (pending != hipSuccess)
+            return fail(MDA_EDEVICE, "pending device error before the launch: %s", hipGetErrorString(pending));
+    }
+    mda_params p;
+    RunDesc d;
+    std::vector<int64_t> T;
+    std::vector<uint32_t> thrmax;
+    int rc = resolve_run(q, pin, p, d, T, thrmax);
+    if (rc) return rc;
+    mda_run_layout lay;
+    rc = fill_layout(p, d, (int64_t)T.size(), &lay);
+    if (rc) return rc;
+    void *base = nullptr;
+    rc = scratch_address(&base);
+    if (rc) return rc;
+    const ScratchPlan sp = scratch_plan(d.R, (int64_t)T.size());
+    uint8_t *sb = static_cast<uint8_t *>(base);
+    RunDesc *ddesc = reinterpret_cast<RunDesc *>(sb + sp.desc);
+    WorkItem *dwork = reinterpret_cast<WorkItem *>(sb + sp.work);
+    int32_t *dlnt = reinterpret_cast<int32_t *>(sb + sp.lnt);
+    d.T = reinterpret_cast<const int64_t *>(sb + sp.T);
+    d.thrmax = reinterpret_cast<const uint32_t *>(sb + sp.thr);
+    d.x = b->x;
+    d.h = b->h;
+    d.st = b->st;
+    d.archE = b->arch_e;
+    d.archX = b->arch_x;
+    d.nd = b->nd;
+    d.trace = b->trace;
+    d.pe = nullptr;
+    std::vector<RunDesc> descs(1, d);
+    std::vector<Group> groups;
+    std::vector<WorkItem> work;
+    plan_work(descs, work, groups);
+    int32_t lnt[4096];
+    threshold_table(lnt);
+    // every part of the scratch area the kernels read is written here
+    HIP_TRY(hipMemcpyAsync(ddesc, descs.data(), sizeof(RunDesc), hipMemcpyHostToDevice, stream));
+    HIP_TRY(hipMemcpyAsync(dwork, work.data(), work.size() * sizeof(WorkItem), hipMemcpyHostToDevice, stream));
+    HIP_TRY(hipMemcpyAsync(dlnt, lnt, sizeof lnt, hipMemcpyHostToDevice, stream));
+    HIP_TRY(hipMemcpyAsync(sb + sp.T, T.data(), T.size() * sizeof(int64_t), hipMemcpyHostToDevice, stream));
+    HIP_TRY(hipMemcpyAsync(sb + sp.thr, thrmax.data(), thrmax.size() * sizeof(uint32_t), hipMemcpyHostToDevice, stream));
+    int dev = 0, cus = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    rc = enqueue_anneal(groups, d, false, ddesc, dwork, dlnt, default_block(p.waves_per_block), cus, stream);
+    if (rc) return rc;
+    HIP_TRY(launch_nondominated(ddesc, dwork, (int)work.size(), stream));
+    return MDA_OK;
 }
 
 // ---------------------------------------------------------------- readout

@@ -77,6 +77,23 @@ class Tuning(C.Structure):
                 ("cand_wpr", C.c_int32 * 16), ("probe_ms", C.c_double * 16)]
 
 
+class RunLayout(C.Structure):
+    _fields_ = [("n", C.c_int32), ("m", C.c_int32), ("replicas", C.c_int32), ("archive_size", C.c_int32),
+                ("steps", C.c_int64), ("trace_replicas", C.c_int32), ("wr", C.c_int32), ("wc", C.c_int32),
+                ("gns", C.c_int32), ("x_words", C.c_int64), ("arch_x_words", C.c_int64),
+                ("n_x", C.c_int64), ("n_h", C.c_int64), ("n_st", C.c_int64), ("n_arch_e", C.c_int64),
+                ("n_arch_x", C.c_int64), ("n_nd", C.c_int64), ("n_trace", C.c_int64),
+                ("scratch_bytes", C.c_int64)]
+
+
+class RunBuffers(C.Structure):
+    _fields_ = [("x", C.c_void_p), ("h", C.c_void_p), ("st", C.c_void_p), ("arch_e", C.c_void_p),
+                ("arch_x", C.c_void_p), ("nd", C.c_void_p), ("trace", C.c_void_p)]
+
+
+NOALLOC_SCRATCH_BYTES = 4 << 20
+
+
 class ServerOpts(C.Structure):
     _fields_ = [("hbm_budget", C.c_int64), ("max_inflight", C.c_int32), ("max_batch", C.c_int32),
                 ("device", C.c_int32), ("reserved", C.c_int32)]
@@ -153,6 +170,10 @@ def lib():
     L.mda_autotune.restype = C.c_int
     L.mda_footprint.argtypes = [i32, C.POINTER(Params), C.POINTER(BuildOpts)]
     L.mda_footprint.restype = C.c_int64
+    L.da_run_layout.argtypes = [vp, C.POINTER(Params), C.POINTER(RunLayout)]
+    L.da_run_layout.restype = C.c_int
+    L.da_run_noalloc.argtypes = [vp, C.POINTER(Params), C.POINTER(RunBuffers)]
+    L.da_run_noalloc.restype = C.c_int
     L.mda_server_create.argtypes = [C.POINTER(ServerOpts), C.POINTER(vp)]
     L.mda_server_create.restype = C.c_int
     L.mda_server_submit.argtypes = [vp, i32, vp, vp, vp, C.POINTER(BuildOpts), C.POINTER(Params), C.POINTER(i64)]
@@ -170,7 +191,7 @@ def lib():
 EXPORTED = ["qubo_build_bqap", "qubo_flows", "qubo_info", "qubo_free", "mda_params_default", "da_run", "da_run_batch",
             "da_sync", "da_elapsed_ms", "da_kernel_ms", "archive_get", "da_state_get", "da_params_get", "da_stats", "da_run_free",
             "mda_set_allocator", "mda_last_error", "mda_threshold_table", "mda_temperature_table",
-            "mda_autotune", "mda_footprint", "mda_server_create", "mda_server_submit", "mda_server_wait", "mda_server_stats",
+            "mda_autotune", "mda_footprint", "da_run_layout", "da_run_noalloc", "mda_server_create", "mda_server_submit", "mda_server_wait", "mda_server_stats",
             "mda_server_destroy"]
 
 
@@ -441,6 +462,22 @@ def da_run_batch(qs: Sequence[Qubo], params: Sequence[Params]) -> list:
     outs = (C.c_void_p * k)()
     _check(lib().da_run_batch(harr, parr, k, outs))
     return [Run(C.c_void_p(outs[i]), qs[i]) for i in range(k)]
+
+
+def run_layout(q: Qubo, params: Params) -> RunLayout:
+    """da_run_layout: sizes of the buffers da_run_noalloc writes."""
+    lay = RunLayout()
+    _check(lib().da_run_layout(q.handle, C.byref(params), C.byref(lay)))
+    return lay
+
+
+def da_run_noalloc(q: Qubo, params: Params, x: int, h: int, st: int, arch_e: int, arch_x: int, nd: int,
+                   trace: int = 0) -> None:
+    """da_run_noalloc: the run of da_run written into caller-owned device
+    buffers (raw device addresses, sized by run_layout); asynchronous on the
+    parameters' stream."""
+    b = RunBuffers(x, h, st, arch_e, arch_x, nd, trace or None)
+    _check(lib().da_run_noalloc(q.handle, C.byref(params), C.byref(b)))
 
 
 # ---------------------------------------------------------------- footprint and serving
