@@ -52,17 +52,38 @@ WORKLOADS = {
 # Peak of plain 32-bit integer VALU work: 256 CUs x 4 SIMDs x 16 lanes per clock
 # x 2.4 GHz (a wave64 VALU instruction occupies a 16-lane SIMD for 4 clocks).
 ALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
+# MI355X HBM3E bandwidth (vendor figure), GB/s
+HBM_PEAK_GBS = 8000.0
 
-# Algorithmic integer operations (lane-ops) of the annealing step:
-#   per bit-trial   combine the two energy differences (max or min) and compare
-#                   against the step's largest acceptance threshold        2
-#   per move        per bit, both objectives: column entry (product of the
-#                   flow and distance factors), penalty term, field add     6 per bit
-#   per random block one Philox4x32-10 call (10 rounds of two 32x32->64
-#                   products, four xors, two key additions)               100 per lane
-OPS_PER_BIT_TRIAL = 2
-OPS_PER_MOVE_BIT = 6
-OPS_PER_PHILOX = 100
+OPMODEL_PATH = os.path.join(ROOT, "paper_2205_13399_amd", "opmodel.json")
+
+
+def load_opmodel() -> dict:
+    """The algorithmic op model (versioned file): lane-ops per bit-trial, per
+    moved bit and per random block."""
+    with open(OPMODEL_PATH) as f:
+        return json.load(f)
+
+
+def alu_roofline(opm, bit_trials, m, moves, rng_blocks, kernel_ms, kernel="k_persistent", traffic=None):
+    ops = (opm["ops"]["per_bit_trial"] * bit_trials + opm["ops"]["per_move_bit"] * m * moves
+           + opm["ops"]["per_random_block"] * 64 * rng_blocks)
+    achieved = ops / (kernel_ms * 1e-3) / 1e12
+    return {"bound": "alu", "achieved": round(achieved, 3), "peak": round(ALU_PEAK_TOPS, 2), "unit": "TOP/s",
+            "frac": round(achieved / ALU_PEAK_TOPS, 4), "traffic": traffic, "kernel": kernel,
+            "kernel_ms": round(kernel_ms, 3), "ops_per_launch": int(ops), "opmodel_version": opm["version"]}
+
+
+def hbm_roofline_dense(m, moves, kernel_ms, traffic=None):
+    """Dense update path: each move streams the flipped bit's row of P_1 and
+    P_2 restricted to the m bits, 2 x 4 B per bit (8 B per bit-trial that
+    moves)."""
+    nbytes = 8.0 * m * moves
+    achieved = nbytes / (kernel_ms * 1e-3) / 1e9
+    return {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": traffic, "kernel": "k_persistent",
+            "kernel_ms": round(kernel_ms, 3), "algorithmic_bytes_per_launch": int(nbytes)}
+
 
 # sources of the persistent kernel (the per-tile translation units only name a tile)
 KERNEL_SOURCES = ("paper_2205_13399_amd/csrc/mda_wave.h", "paper_2205_13399_amd/csrc/mda_wave_tile.h",
@@ -81,10 +102,10 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def measured_traffic(workload: str):
-    """HBM bytes per launch of the persistent kernel from the committed counter
-    summary, or None when there is none or the kernel source has changed since."""
-    path = os.path.join(ROOT, "profiles", "traffic_k_persistent_%s.md" % workload)
+def measured_traffic(workload: str, kernel: str = "k_persistent"):
+    """HBM bytes per launch of a kernel from the committed counter summary, or
+    None when there is none or the kernel source has changed since."""
+    path = os.path.join(ROOT, "profiles", "traffic_%s_%s.md" % (kernel, workload))
     if not os.path.exists(path):
         return None
     fields = {}
@@ -111,6 +132,28 @@ def make_instances(w):
 
 # ---------------------------------------------------------------- oracle leg
 
+def _pin_worker(cores, counter):
+    """Pins this oracle worker process to one host core of its own."""
+    with counter.get_lock():
+        k = counter.value
+        counter.value += 1
+    try:
+        os.sched_setaffinity(0, {cores[k % len(cores)]})
+    except (AttributeError, OSError):
+        pass
+
+
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def _oracle_job(args):
     import oracle
     (n, F1, F2, D, r, steps, seed) = args
@@ -127,13 +170,16 @@ def _oracle_job(args):
 
 
 def cpu_baseline(inst, steps, replicas, cores):
-    """The oracle, unmodified, on a sample of replicas: one process per replica."""
+    """The oracle, unmodified, on a sample of replicas: one process per replica,
+    each worker pinned to a host core of its own."""
     import multiprocessing as mp
     jobs = [(inst.n, inst.F1.tobytes(), inst.F2.tobytes(), inst.D.tobytes(), r, steps, inst.seed)
             for r in replicas]
     ctx = mp.get_context("spawn")
+    avail = sorted(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else list(range(os.cpu_count() or 1))
+    counter = ctx.Value("i", 0)
     t0 = time.perf_counter()
-    with ctx.Pool(cores) as pool:
+    with ctx.Pool(cores, initializer=_pin_worker, initargs=(avail[:cores], counter)) as pool:
         res = pool.map(_oracle_job, jobs, chunksize=1)
     wall = time.perf_counter() - t0
     return wall, {r: (dt, out) for r, dt, out in res}
@@ -144,19 +190,12 @@ def cpu_baseline(inst, steps, replicas, cores):
 SERVE = dict(count=48, n_lo=10, n_hi=100, replicas=256, steps=50_000, config=4)
 
 
-def serve_bench(args, mda):
+def serving_measure(mda, w, factors=(0.5, 0.9, 1.2)):
     """Poisson stream of bQAP solves through the serving engine: the saturated
-    rate first (everything submitted at once), then arrivals at 0.5, 0.9 and
-    1.2 times it; per-request latency (submission to results on the device)
-    and throughput."""
+    rate first (everything submitted at once), then arrivals at the given
+    multiples of it; per-request latency (submission to results on the
+    device) and throughput."""
     import threading
-    w = dict(SERVE)
-    if args.anneal_steps:
-        w["steps"] = args.anneal_steps
-    if args.replicas:
-        w["replicas"] = args.replicas
-    if args.serve_requests:
-        w["count"] = args.serve_requests
     insts = synth.mixed_batch(count=w["count"], n_lo=w["n_lo"], n_hi=w["n_hi"], config=w["config"])
     params = [mda.make_params(w["replicas"], w["steps"], i.seed) for i in insts]
     srv = mda.Server(max_inflight=4)
@@ -188,33 +227,198 @@ def serve_bench(args, mda):
         return dict(p50_s=float(np.percentile(lat, 50)), p99_s=float(np.percentile(lat, 99)),
                     mean_s=float(lat.mean()), span_s=span, bit_trials_per_s=bt / span,
                     requests_per_s=len(insts) / span,
-                    mean_batch=float(np.mean([i["batch"] for i in infos]))), bt
+                    mean_batch=float(np.mean([i["batch"] for i in infos])))
 
     # warm-up: compile paths and fill the memory pool
     _log("serving: warm-up")
     t = srv.submit(insts[0].F1, insts[0].F2, insts[0].D, mda.make_params(8, 1000, 1))
     srv.wait(t, keep=False)
     _log("serving: saturated (%d requests at once)" % len(insts))
-    sat, bt = run_stream(np.zeros(len(insts)))
+    sat = run_stream(np.zeros(len(insts)))
     rates = {"saturated": sat}
     rng = np.random.default_rng(w["config"])
-    for f in (0.5, 0.9, 1.2):
+    for f in factors:
         lam = f * sat["requests_per_s"]
         _log("serving: Poisson arrivals at %.2f requests/s (%.1f x saturated)" % (lam, f))
-        res, _ = run_stream(rng.exponential(1.0 / lam, len(insts)))
+        res = run_stream(rng.exponential(1.0 / lam, len(insts)))
         res["arrival_rate"] = lam
         rates["%.1fx" % f] = res
+        _log("serving: p50 %.3f s, p99 %.3f s, %.3g bit-trials/s" % (res["p50_s"], res["p99_s"],
+                                                                   res["bit_trials_per_s"]))
     srv.close()
+    return rates, insts
+
+
+def serve_config(w, insts):
+    return {"workload": "bqap-serve-n10-100", "requests": len(insts), "n": [w["n_lo"], w["n_hi"]],
+            "replicas": w["replicas"], "anneal_steps": w["steps"], "path": "automatic (dense up to 2 GB)",
+            "arrivals": "all at once (saturated), then Poisson at the stated multiples of the saturated rate",
+            "server": "admission by device footprint, up to 4 launches in flight"}
+
+
+def serve_bench(args, mda):
+    w = dict(SERVE)
+    if args.anneal_steps:
+        w["steps"] = args.anneal_steps
+    if args.replicas:
+        w["replicas"] = args.replicas
+    if args.serve_requests:
+        w["count"] = args.serve_requests
+    rates, insts = serving_measure(mda, w)
+    sat = rates["saturated"]
     out = {
         "metric": "bit-trials/s", "value": sat["bit_trials_per_s"], "unit": "bit-trials/s", "n_gpus": 1,
         "steps": 1, "warmup": 1, "ms_per_step": round(sat["span_s"] * 1e3, 3), "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "int32", "data": "synthetic",
-        "config": {"workload": "bqap-serve-n10-100", "requests": len(insts), "n": [w["n_lo"], w["n_hi"]],
-                   "replicas": w["replicas"], "anneal_steps": w["steps"], "path": "automatic (dense up to 2 GB)",
-                   "server": "admission by device footprint, up to 4 launches in flight"},
+        "config": serve_config(w, insts),
         "latency": rates,
     }
     print(json.dumps(out), flush=True)
+
+
+# ---------------------------------------------------------------- runs and legs
+
+def timed_launches(mda, qs, params, steps, warmup, label):
+    """warmup untimed, then steps timed bench steps of one batched launch of
+    qs (plus the merged front of each run copied to the host)."""
+    import torch
+
+    def one_step():
+        runs = mda.da_run_batch(qs, params)
+        fronts = [r.archive(-1, bits=False) for r in runs]
+        return runs, fronts
+
+    for k in range(warmup):
+        runs, _ = one_step()
+        _log("%s warmup %d: kernel %.1f ms" % (label, k, runs[0].kernel_ms()))
+        for r in runs:
+            r.close()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    kms, ems, runs_last, fronts_last, stats = [], [], None, None, None
+    for k in range(steps):
+        if runs_last:
+            # done with the previous step: its device memory goes back to the pool
+            for r in runs_last:
+                r.close()
+        runs, fronts = one_step()
+        kms.append(runs[0].kernel_ms())
+        ems.append(runs[0].elapsed_ms())
+        stats = [r.stats() for r in runs]
+        runs_last, fronts_last = runs, fronts
+        _log("%s step %d: kernel %.1f ms, launch %.1f ms" % (label, k, kms[-1], ems[-1]))
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    return dict(wall=wall, kernel_ms=float(np.mean(kms)), launch_ms=float(np.mean(ems)), runs=runs_last,
+                fronts=fronts_last, stats=stats)
+
+
+def plain_compare(mda, q, inst, R, steps, ref_run, ref_front, label):
+    """The plain GPU form (one launch per annealing step, state in HBM) of one
+    instance: wall time and whether it equals the batched launch."""
+    import torch
+    pp = mda.make_params(R, steps, inst.seed, variant=mda.VARIANT_PLAIN)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    pr = mda.da_run(q, pp)
+    fr = pr.archive(-1, bits=False)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t1
+    same = True
+    for r in sorted({0, R // 2, R - 1}):
+        a, b = pr.state(r), ref_run.state(r)
+        same &= (a["E1"], a["E2"], a["moves"]) == (b["E1"], b["E2"], b["moves"])
+    same &= np.array_equal(fr.e1, ref_front.e1) and np.array_equal(fr.e2, ref_front.e2)
+    _log("%s plain: %.2f s, identical to the persistent launch: %s" % (label, dt, same))
+    pr.close()
+    return dt, bool(same)
+
+
+def leg_single(mda, opm, name, steps_timed, warmup):
+    """One of the single-instance workloads (n = 25 dense or Kronecker):
+    persistent launch, its roofline, the plain form beside it."""
+    w = WORKLOADS[name]
+    R, steps, n = w["replicas"], w["steps"], w["n"]
+    m = n * n
+    path = mda.PATH_KRON if w["path"] == "kron" else mda.PATH_DENSE
+    insts = make_instances(w)
+    qs = [mda.Qubo(i.F1, i.F2, i.D, path=path) for i in insts]
+    params = [mda.make_params(R, steps, i.seed) for i in insts]
+    res = timed_launches(mda, qs, params, steps_timed, warmup, name)
+    bt = len(insts) * R * m * steps
+    moves = sum(s["moves"] for s in res["stats"])
+    rngb = sum(s["rng_blocks"] for s in res["stats"])
+    traffic = measured_traffic(name)
+    if path == mda.PATH_DENSE:
+        roof = hbm_roofline_dense(m, moves, res["kernel_ms"], traffic)
+        roof["note"] = ("P_1 and P_2 of n = 25 hold %.1f MB on the device, which stays in the L2 caches "
+                        "(4 MB per XCD) and the 256 MB MALL: the rows stream from cache, not HBM"
+                        % (qs[0].info().device_bytes / 1e6))
+        roof["alu"] = alu_roofline(opm, bt, m, moves, rngb, res["kernel_ms"])
+    else:
+        roof = alu_roofline(opm, bt, m, moves, rngb, res["kernel_ms"], traffic=traffic)
+    value = bt * steps_timed / res["wall"]
+    dt, same = plain_compare(mda, qs[0], insts[0], R, steps, res["runs"][0], res["fronts"][0], name)
+    out = {"value": value, "unit": "bit-trials/s", "steps": steps_timed, "warmup": warmup,
+           "ms_per_step": round(res["wall"] * 1e3 / steps_timed, 3),
+           "config": {"workload": name, "n": n, "m": m, "rho": list(w["rhos"]), "replicas": R,
+                      "anneal_steps": steps, "path": w["path"]},
+           "roofline": roof,
+           "p_move": moves / (R * steps * len(insts)),
+           "plain": {"value": R * m * steps / dt, "unit": "bit-trials/s", "identical_results": same},
+           "vs_plain": round(value / (R * m * steps / dt), 3)}
+    for r in res["runs"]:
+        r.close()
+    return out
+
+
+BATCH = dict(count=256, n_lo=10, n_hi=60, replicas=64, steps=100_000, config=3, plain_sample=4)
+
+
+def leg_batch(mda, opm, steps_timed, warmup):
+    """Configuration of many uneven instances: 256 bQAP instances, n uniform on
+    {10..60}, 64 replicas x 1e5 steps each, Kronecker updates, one batched
+    launch captured as a HIP graph; the plain form of a sample of instances
+    (the smallest, the largest and two more) beside it."""
+    import torch
+    w = BATCH
+    insts = synth.mixed_batch(count=w["count"], n_lo=w["n_lo"], n_hi=w["n_hi"], config=w["config"])
+    qs = [mda.Qubo(i.F1, i.F2, i.D, path=mda.PATH_KRON) for i in insts]
+    stream = torch.cuda.Stream()
+    params = [mda.make_params(w["replicas"], w["steps"], i.seed, graph=True, stream=stream.cuda_stream)
+              for i in insts]
+    with torch.cuda.stream(stream):
+        res = timed_launches(mda, qs, params, steps_timed, warmup, "batch")
+    bt = sum(w["replicas"] * i.m * w["steps"] for i in insts)
+    value = bt * steps_timed / res["wall"]
+    moves = sum(s["moves"] for s in res["stats"])
+    rngb = sum(s["rng_blocks"] for s in res["stats"])
+    moved_bits = sum(s["moves"] * i.m for s, i in zip(res["stats"], insts))
+    ops_roof = alu_roofline(opm, bt, 1, moved_bits, rngb, res["kernel_ms"], kernel="graph of k_persistent launches")
+    ns = [i.n for i in insts]
+    sample = sorted({int(np.argmin(ns)), int(np.argmax(ns)), 1, len(insts) // 2})[:w["plain_sample"]]
+    pl_bt, pl_s, same = 0, 0.0, True
+    for k in sample:
+        dt, ok = plain_compare(mda, qs[k], insts[k], w["replicas"], w["steps"], res["runs"][k], res["fronts"][k],
+                               "batch instance %d (n=%d)" % (k, insts[k].n))
+        pl_bt += w["replicas"] * insts[k].m * w["steps"]
+        pl_s += dt
+        same &= ok
+    out = {"value": value, "unit": "bit-trials/s", "steps": steps_timed, "warmup": warmup,
+           "ms_per_step": round(res["wall"] * 1e3 / steps_timed, 3),
+           "config": {"workload": "bqap-batch-n10-60-x256", "instances": len(insts), "n": [min(ns), max(ns)],
+                      "replicas": w["replicas"], "anneal_steps": w["steps"], "path": "kron",
+                      "launch": "one HIP graph of persistent launches (one per register tile)",
+                      "bit_trials_per_step": bt},
+           "roofline": ops_roof,
+           "moves": moves,
+           "plain": {"value": pl_bt / pl_s, "unit": "bit-trials/s",
+                     "sample": "instances %s (n = %s), one plain run each" % (sample, [ns[k] for k in sample]),
+                     "identical_results": bool(same)},
+           "vs_plain": round(value / (pl_bt / pl_s), 3)}
+    for r in res["runs"]:
+        r.close()
+    return out
 
 
 # ---------------------------------------------------------------- SB-DA vs MDA
@@ -328,6 +532,10 @@ def main():
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain device copy of 1 GiB (counter calibration)")
     ap.add_argument("--serve-requests", type=int, default=0, help="requests of the serving workload")
+    ap.add_argument("--legs", type=int, default=1,
+                    help="also measure the other configurations (n = 25 dense and Kronecker, the uneven batch, "
+                         "serving) as legs of the JSON line (0 = headline only)")
+    ap.add_argument("--leg-steps", type=int, default=2, help="timed bench steps of each leg")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -361,10 +569,10 @@ def main():
     R, steps, n = w["replicas"], w["steps"], w["n"]
     m = n * n
     path = mda.PATH_KRON if w["path"] == "kron" else mda.PATH_DENSE
+    opm = load_opmodel()
 
     torch.cuda.set_device(0)
     mda.use_torch_allocator()
-    stream = torch.cuda.current_stream()
     insts = make_instances(w)
     _log("workload %s: %d instance(s) n=%d, %d replicas x %d steps, path %s"
          % (args.workload, len(insts), n, R, steps, w["path"]))
@@ -381,50 +589,21 @@ def main():
     torch.cuda.synchronize()
 
     bit_trials_step = len(insts) * R * m * steps
-
-    def one_step():
-        runs = mda.da_run_batch(qs, params)
-        fronts = [r.archive(-1, bits=False) for r in runs]
-        return runs, fronts
-
-    for k in range(args.warmup):
-        runs, _ = one_step()
-        _log("warmup %d: kernel %.1f ms" % (k, runs[0].kernel_ms()))
-        for r in runs:
-            r.close()
-
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    kms, ems, stats, fronts_last, runs_last = [], [], [], None, None
-    for k in range(args.steps):
-        if runs_last:
-            # done with the previous step: its device memory goes back to the pool
-            for r in runs_last:
-                r.close()
-        runs, fronts = one_step()
-        kms.append(runs[0].kernel_ms())
-        ems.append(runs[0].elapsed_ms())
-        stats.append([r.stats() for r in runs])
-        runs_last, fronts_last = runs, fronts
-        _log("step %d: kernel %.1f ms, launch %.1f ms" % (k, kms[-1], ems[-1]))
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
+    res = timed_launches(mda, qs, params, args.steps, args.warmup, "")
+    runs_last, fronts_last = res["runs"], res["fronts"]
+    wall = res["wall"]
     ms_per_step = wall * 1e3 / max(1, args.steps)
     value = bit_trials_step * args.steps / wall
 
     # roofline of the persistent kernel: algorithmic lane-ops per launch / kernel time
-    st = stats[-1]
+    st = res["stats"]
     moves = sum(s["moves"] for s in st)
     rng_blocks = sum(s["rng_blocks"] for s in st)
-    ops = (OPS_PER_BIT_TRIAL * bit_trials_step + OPS_PER_MOVE_BIT * m * moves
-           + OPS_PER_PHILOX * 64 * rng_blocks)
-    kernel_ms = float(np.mean(kms))
-    achieved = ops / (kernel_ms * 1e-3) / 1e12
     traffic = measured_traffic(args.workload)
-    roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": round(ALU_PEAK_TOPS, 2),
-                "unit": "TOP/s", "frac": round(achieved / ALU_PEAK_TOPS, 4), "traffic": traffic,
-                "kernel": "k_persistent", "kernel_ms": round(kernel_ms, 3),
-                "ops_per_launch": ops}
+    if path == mda.PATH_DENSE:
+        roofline = hbm_roofline_dense(m, moves, res["kernel_ms"], traffic)
+    else:
+        roofline = alu_roofline(opm, bit_trials_step, m, moves, rng_blocks, res["kernel_ms"], traffic=traffic)
 
     out = {
         "metric": "bit-trials/s", "value": value, "unit": "bit-trials/s", "n_gpus": 1,
@@ -449,26 +628,13 @@ def main():
 
     # plain GPU form: one launch per annealing step, one instance per call
     if args.plain > 0:
-        pl_bt, pl_s = 0, 0.0
+        pl_bt, pl_s, same = 0, 0.0, True
         for idx in range(min(args.plain, len(insts))):
-            pp = mda.make_params(R, steps, insts[idx].seed, variant=mda.VARIANT_PLAIN,
-                                 waves_per_block=args.waves_per_block)
-            torch.cuda.synchronize()
-            t1 = time.perf_counter()
-            pr = mda.da_run(qs[idx], pp)
-            fr = pr.archive(-1, bits=False)
-            torch.cuda.synchronize()
-            dt = time.perf_counter() - t1
+            dt, ok = plain_compare(mda, qs[idx], insts[idx], R, steps, runs_last[idx], fronts_last[idx],
+                                   "instance %d" % idx)
             pl_bt += R * m * steps
             pl_s += dt
-            # same result as the batched launch, replica by replica
-            same = True
-            for r in (0, R // 2, R - 1):
-                a, b = pr.state(r), runs_last[idx].state(r)
-                same &= (a["E1"], a["E2"], a["moves"]) == (b["E1"], b["E2"], b["moves"])
-            same &= np.array_equal(fr.e1, fronts_last[idx].e1) and np.array_equal(fr.e2, fronts_last[idx].e2)
-            _log("plain instance %d: %.2f s, identical to batched: %s" % (idx, dt, same))
-            pr.close()
+            same &= ok
         pv = pl_bt / pl_s
         out["plain"] = {"value": pv, "unit": "bit-trials/s", "instances": min(args.plain, len(insts)),
                         "launch": "one launch per annealing step, state in HBM",
@@ -488,23 +654,43 @@ def main():
         ncpu = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
         cores = max(1, min(args.cpu_replicas, args.cpu_cores, ncpu, 16))
         sample = list(range(args.cpu_replicas))
-        inst = insts[len(insts) // 2]
         idx = len(insts) // 2
-        _log("oracle: %d replicas of instance %d on %d cores" % (len(sample), idx, cores))
-        cw, res = cpu_baseline(inst, steps, sample, cores)
+        inst = insts[idx]
+        _log("oracle: %d replicas of instance %d on %d pinned cores" % (len(sample), idx, cores))
+        cw, ores = cpu_baseline(inst, steps, sample, cores)
         exact = True
-        for r, (dt, o) in res.items():
+        for r, (dt, o) in ores.items():
             g = runs_last[idx].state(r)
             a = runs_last[idx].archive(r, raw=True, bits=False)
             exact &= (g["E1"], g["E2"], g["Eoff"], g["moves"], len(a)) == o[:5]
             exact &= a.e1.tobytes() == o[5] and a.e2.tobytes() == o[6]
+        per_core = float(np.mean([m * steps / dt for dt, _ in ores.values()]))
         out["cpu_baseline"] = {"value": len(sample) * m * steps / cw, "unit": "bit-trials/s",
                                "cores": cores, "kind": "oracle",
                                "sample": "%d replicas x %d steps of the n=%d rho=%g instance, one process "
-                                         "per replica, %.1f s wall" % (len(sample), steps, n, inst.rho, cw),
-                               "bit_exact_vs_gpu": bool(exact)}
+                                         "per replica, each pinned to its own core, %.1f s wall"
+                                         % (len(sample), steps, n, inst.rho, cw),
+                               "per_core": per_core, "cpu_model": cpu_model(), "nproc": os.cpu_count(),
+                               "affinity_cores": ncpu, "bit_exact_vs_gpu": bool(exact)}
     for r in runs_last:
         r.close()
+
+    # the other configurations, each a bench leg of its own
+    if args.legs:
+        legs = {}
+        for name in ("bqap-n25-dense", "bqap-n25-kron"):
+            if name != args.workload:
+                _log("leg %s" % name)
+                legs[name] = leg_single(mda, opm, name, args.leg_steps, 1)
+        _log("leg batch")
+        legs["bqap-batch-n10-60-x256"] = leg_batch(mda, opm, args.leg_steps, 1)
+        _log("leg serving")
+        sw = dict(SERVE)
+        rates, sinsts = serving_measure(mda, sw, factors=(0.9,))
+        legs["bqap-serve-n10-100"] = {"config": serve_config(sw, sinsts), "latency": rates,
+                                      "value": rates["saturated"]["bit_trials_per_s"], "unit": "bit-trials/s",
+                                      "p50_s_at_0.9x": rates["0.9x"]["p50_s"], "p99_s_at_0.9x": rates["0.9x"]["p99_s"]}
+        out["legs"] = legs
     print(json.dumps(out), flush=True)
 
 
