@@ -146,6 +146,18 @@ __device__ __forceinline__ int wave_sum(int v)
     return uni(v);
 }
 
+// Wave-wide sum of a per-lane integer 0 <= v < 2^B: one ballot per bit, the
+// counts taken on the scalar unit.  Unlike a tree of cross-lane shuffles the
+// B ballots do not wait on one another.
+template <int B>
+__device__ __forceinline__ int wave_sum_small(int v)
+{
+    int s = 0;
+#pragma unroll
+    for (int b = 0; b < B; ++b) s += __popcll(__ballot((v >> b) & 1)) << b;
+    return uni(s);
+}
+
 // Fields read on every step, kept in scalar registers.
 struct Hot {
     int n;
@@ -182,6 +194,10 @@ struct Replica {
     int64_t E1, E2, Eoff;
     int64_t moves, scanned, rngb, detailed;
     int32_t asize;
+    // per group of 8 slots, the lane's least combined difference (max of the
+    // two for the strict rule, min for the lenient one); it only changes when
+    // the fields do, so it is recomputed after a move or restart only
+    int32_t gmin[NS / 8];
 };
 
 // Update paths (template argument PV): dense rows of P_k, or the Kronecker

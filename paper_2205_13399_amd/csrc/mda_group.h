@@ -433,7 +433,7 @@ __device__ __forceinline__ void g_step(Desc *Dp, const Hot &H, Replica<NS> &S, i
         __syncthreads();   // B2
         int c = 0;
         for (int w2 = 0; w2 < g.G; ++w2) c += __popcll(L.acc[w2][lane]);
-        const int cnt = wave_sum(c);
+        const int cnt = wave_sum_small<10>(c);
         if (cnt > 0) {
             const U4 o = philox10(0u, t, (uint32_t)r, kTagSel, H.key0, H.key1);
             int k = (int)scale32((uint32_t)uni((int)o.x), (uint32_t)cnt);
@@ -449,7 +449,7 @@ __device__ __forceinline__ void g_step(Desc *Dp, const Hot &H, Replica<NS> &S, i
                     const uint64_t rm = rr <= 0 ? 0ull : (rr >= 64 ? ~0ull : ((1ull << rr) - 1ull));
                     b += __popcll(L.acc[w2][lane] & rm);
                 }
-                if (wave_sum(b) <= k) lo = mid;
+                if (wave_sum_small<10>(b) <= k) lo = mid;
                 else hi = mid;
             }
             const int js = uni(lo);
@@ -460,7 +460,7 @@ __device__ __forceinline__ void g_step(Desc *Dp, const Hot &H, Replica<NS> &S, i
                     const uint64_t rm = rr <= 0 ? 0ull : (rr >= 64 ? ~0ull : ((1ull << rr) - 1ull));
                     b += __popcll(L.acc[w2][lane] & rm);
                 }
-                k -= wave_sum(b);
+                k -= wave_sum_small<10>(b);
             }
             // location within row js: column-waves in order, lanes ascending
             const int pj = js / NS, sj = js - pj * NS;

@@ -330,6 +330,20 @@ __device__ __forceinline__ void init_replica(Desc *Dp, Replica<NS> &S, int r, in
     fields_from_scratch<NS, PV>(Dp, S, lane);
 }
 
+// Least combined difference of every group of 8 slots (see Replica::gmin).
+template <int NS, int AM>
+__device__ __forceinline__ void group_minima(Replica<NS> &S)
+{
+#pragma unroll
+    for (int g = 0; g < NS; g += 8) {
+        int32_t gm = INT_MAX;
+#pragma unroll
+        for (int f = 0; f < 8; ++f)
+            gm = min(gm, AM == kAmStrict ? max(S.e1[g + f], S.e2[g + f]) : min(S.e1[g + f], S.e2[g + f]));
+        S.gmin[g >> 3] = gm;
+    }
+}
+
 // One annealing step t of replica r whose largest acceptance threshold
 // (T_t * LNT[0]) >> 24 is thrmax.  Returns the flipped bit or -1.
 template <int NS, int PV, int AM, class LP>
@@ -350,15 +364,7 @@ __device__ __forceinline__ int anneal_step(Desc *Dp, const Hot &H, Replica<NS> &
 
     // 1. can any bit be accepted?  The minimum is kept per group of 8 slots so
     // that step 2 passes over groups in which no lane comes within reach.
-    int32_t gmin[NS / 8];
-#pragma unroll
-    for (int g = 0; g < NS; g += 8) {
-        int32_t gm = INT_MAX;
-#pragma unroll
-        for (int f = 0; f < 8; ++f)
-            gm = min(gm, strict ? max(S.e1[g + f], S.e2[g + f]) : min(S.e1[g + f], S.e2[g + f]));
-        gmin[g >> 3] = gm;
-    }
+    const int32_t *gmin = S.gmin;
     int32_t mn = INT_MAX;
 #pragma unroll
     for (int g = 0; g < NS / 8; ++g) mn = min(mn, gmin[g]);
@@ -402,30 +408,36 @@ __device__ __forceinline__ int anneal_step(Desc *Dp, const Hot &H, Replica<NS> &
                     S.rngb++;
                     const U4 o = philox10(((uint32_t)(g >> 3) << 16) | (uint32_t)lane, t, (uint32_t)r,
                                           kTagAcc, H.key0, H.key1);
+                    // the eight -ln lookups are issued together (one LDS wait
+                    // per block, not one per slot) and every slot is decided
+                    // without a branch; slots that are not undecided keep
+                    // their decision through the mask
+                    uint32_t Lv[8];
 #pragma unroll
                     for (int f = 0; f < 8; ++f) {
-                        if ((maybe >> f) & 1u) {
-                            const int i = g + f;
-                            const uint32_t w = (f < 2) ? o.x : (f < 4) ? o.y : (f < 6) ? o.z : o.w;
-                            const uint32_t idx = (w >> (16 * (f & 1))) & 0xFFFu;
-                            // u_k = max(0, dE_k - E_offset) < 2^31 for a real bit, so the
-                            // strict sum stays below 2^32
-                            const uint32_t u1 = (uint32_t)(max(S.e1[i], EoC) - EoC);
-                            const uint32_t u2 = (uint32_t)(max(S.e2[i], EoC) - EoC);
-                            const uint32_t Sx = strict ? (u1 + u2) : (u1 < u2 ? u1 : u2);
-                            const uint32_t L = (uint32_t)lnt[idx] & 0xFFFFFu;
-                            const uint64_t low = (uint64_t)Tl * (uint64_t)L;   // 24 x 20 bits
-                            const uint64_t t64 = (uint64_t)Th * (uint64_t)L + (low >> 24);
-                            const uint32_t thr = t64 < 0xFFFFFFFEull ? (uint32_t)t64 : 0xFFFFFFFEu;
-                            if (Sx <= thr) certain |= (1u << f);
-                        }
+                        const uint32_t w = (f < 2) ? o.x : (f < 4) ? o.y : (f < 6) ? o.z : o.w;
+                        Lv[f] = (uint32_t)lnt[(w >> (16 * (f & 1))) & 0xFFFu];
+                    }
+#pragma unroll
+                    for (int f = 0; f < 8; ++f) {
+                        const int i = g + f;
+                        // u_k = max(0, dE_k - E_offset) < 2^31 for a real bit, so the
+                        // strict sum stays below 2^32
+                        const uint32_t u1 = (uint32_t)(max(S.e1[i], EoC) - EoC);
+                        const uint32_t u2 = (uint32_t)(max(S.e2[i], EoC) - EoC);
+                        const uint32_t Sx = strict ? (u1 + u2) : (u1 < u2 ? u1 : u2);
+                        const uint32_t L = Lv[f] & 0xFFFFFu;
+                        const uint64_t low = (uint64_t)Tl * (uint64_t)L;   // 24 x 20 bits
+                        const uint64_t t64 = (uint64_t)Th * (uint64_t)L + (low >> 24);
+                        const uint32_t thr = t64 < 0xFFFFFFFEull ? (uint32_t)t64 : 0xFFFFFFFEu;
+                        certain |= (((maybe >> f) & 1u) && Sx <= thr) ? (1u << f) : 0u;
                     }
                 }
                 acc |= (uint64_t)certain << g;
             }
         }
         // 3. uniform choice in ascending bit order a = i*n + u
-        const int cnt = wave_sum(__popcll(acc));
+        const int cnt = wave_sum_small<7>(__popcll(acc));
         if (cnt > 0) {
             const U4 o = philox10(0u, t, (uint32_t)r, kTagSel, H.key0, H.key1);
             int k = (int)scale32((uint32_t)uni((int)o.x), (uint32_t)cnt);
@@ -434,12 +446,12 @@ __device__ __forceinline__ int anneal_step(Desc *Dp, const Hot &H, Replica<NS> &
             int lo = 0, hi = NS;
             while (hi - lo > 1) {
                 const int mid = (lo + hi) >> 1;
-                const int below = wave_sum(__popcll(acc & ((1ull << mid) - 1ull)));
+                const int below = wave_sum_small<7>(__popcll(acc & ((1ull << mid) - 1ull)));
                 if (below <= k) lo = mid;
                 else hi = mid;
             }
             const int js = uni(lo);
-            k -= (js == 0) ? 0 : wave_sum(__popcll(acc & ((1ull << js) - 1ull)));
+            k -= (js == 0) ? 0 : wave_sum_small<7>(__popcll(acc & ((1ull << js) - 1ull)));
             const int jl = kth_lane(__ballot((acc >> js) & 1ull), k, lane);
             int32_t v1 = 0, v2 = 0;
 #pragma unroll
@@ -450,6 +462,7 @@ __device__ __forceinline__ int anneal_step(Desc *Dp, const Hot &H, Replica<NS> &
             const int32_t d1 = rl(v1, jl), d2 = rl(v2, jl);
             // 4. move, 5. archive
             flip<NS, PV>(Dp, n, S, js, jl, d1, d2, lane);
+            group_minima<NS, AM>(S);
             S.moves++;
             archive_update<NS>(Dp, n, S, r, t, lane, H.key0, H.key1);
             j = js * n + jl;
@@ -464,6 +477,7 @@ __device__ __forceinline__ int anneal_step(Desc *Dp, const Hot &H, Replica<NS> &
         const U4 o = philox10(0u, t, (uint32_t)r, kTagArc, H.key0, H.key1);
         const int p = (int)scale32((uint32_t)uni((int)o.y), (uint32_t)S.asize);
         restart_from<NS, PV>(Dp, n, S, r, p, lane);
+        group_minima<NS, AM>(S);
     }
     if (r < H.trace_R && lane == 0) rw(cold(Dp)->trace)[(size_t)r * H.steps + (t - 1u)] = j;
     return j;
@@ -513,6 +527,7 @@ __device__ __forceinline__ void run_replica(Desc *Dp, int r, int lane, const MDA
 {
     Replica<NS> S;
     init_replica<NS, PV>(Dp, S, r, lane);
+    group_minima<NS, AM>(S);
     const Hot H = load_hot(Dp);
     // the next step's threshold is loaded one step ahead
     uint32_t thr = H.thrmax[0];
@@ -635,6 +650,7 @@ __device__ __forceinline__ void plain_step_one(Desc *Dp, int r, uint32_t t, int 
 {
     Replica<NS> S;
     plain_load<NS>(Dp, S, r, lane);
+    group_minima<NS, AM>(S);
     const Hot H = load_hot(Dp);
     anneal_step<NS, PV, AM>(Dp, H, S, r, t, lane, lnt, H.thrmax[table_index(t, H.ntab)]);
     plain_store<NS>(Dp, S, r, lane);
