@@ -372,6 +372,53 @@ def leg_single(mda, opm, name, steps_timed, warmup):
     return out
 
 
+def front_points(run):
+    """Merged non-dominated front of a run: all points and the feasible ones
+    (permutation matrices), as (E1, E2) = (f1, f2) pairs."""
+    f = run.archive(-1, bits=True)
+    pts = np.stack([f.e1, f.e2], axis=1).astype(np.float64)
+    return pts, pts[f.feasible == 1]
+
+
+def leg_quality(mda, name, qs_2max, runs_2max):
+    """Quality of the headline runs (Sec. Performance Criteria): the same
+    instances, replicas, steps and seeds run again with the Verma-Lewis
+    penalty (Eqs. vermap, wvermaa); per instance and penalty, the merged
+    front's size, how many of its points are permutations, and the 2-D
+    hypervolume of the feasible points, normalised to [1, 2] over both
+    penalties' feasible points together, reference point (2.1, 2.1)."""
+    from paper_2205_13399_amd import quality
+    w = WORKLOADS[name]
+    R, steps = w["replicas"], w["steps"]
+    insts = make_instances(w)
+    qv = [mda.Qubo(i.F1, i.F2, i.D, path=mda.PATH_KRON, penalty=mda.PEN_VL) for i in insts]
+    pv = [mda.make_params(R, steps, i.seed) for i in insts]
+    t0 = time.perf_counter()
+    runs_vl = mda.da_run_batch(qv, pv)
+    for r in runs_vl:
+        r.sync()
+    dt = time.perf_counter() - t0
+    out = []
+    for k, inst in enumerate(insts):
+        a_all, a_feas = front_points(runs_2max[k])
+        b_all, b_feas = front_points(runs_vl[k])
+        sets = [s for s in (a_feas, b_feas) if len(s)]
+        norm = quality.normaliser(sets) if sets else None
+        hv = lambda s: float(quality.hypervolume_2d(norm(s))) if len(s) and norm else 0.0
+        out.append({"rho": inst.rho,
+                    "penalty_2max": {"alpha": [int(qs_2max[k].info().alpha1), int(qs_2max[k].info().alpha2)],
+                                     "front": int(len(a_all)), "feasible": int(len(a_feas)), "hv_feasible": hv(a_feas)},
+                    "penalty_vl": {"alpha": [int(qv[k].info().alpha1), int(qv[k].info().alpha2)],
+                                   "front": int(len(b_all)), "feasible": int(len(b_feas)), "hv_feasible": hv(b_feas)}})
+        _log("quality rho %+.2f: 2max front %d (%d feasible), Verma-Lewis front %d (%d feasible, hv %.4f)"
+             % (inst.rho, len(a_all), len(a_feas), len(b_all), len(b_feas), out[-1]["penalty_vl"]["hv_feasible"]))
+    for r in runs_vl:
+        r.close()
+    return {"per_instance": out, "vl_run_s": round(dt, 3),
+            "note": "hypervolume of the feasible front points, normalised over both penalties' feasible points "
+                    "of the instance (the reference fronts of the paper's instances are not available)"}
+
+
 BATCH = dict(count=256, n_lo=10, n_hi=60, replicas=64, steps=100_000, config=3, plain_sample=4)
 
 
@@ -672,12 +719,15 @@ def main():
                                          % (len(sample), steps, n, inst.rho, cw),
                                "per_core": per_core, "cpu_model": cpu_model(), "nproc": os.cpu_count(),
                                "affinity_cores": ncpu, "bit_exact_vs_gpu": bool(exact)}
-    for r in runs_last:
-        r.close()
-
     # the other configurations, each a bench leg of its own
     if args.legs:
         legs = {}
+        if args.workload == "bqap-n50-x3-kron":
+            _log("leg quality (Verma-Lewis penalty beside 2 max|C|)")
+            out["quality"] = leg_quality(mda, args.workload, qs, runs_last)
+    for r in runs_last:
+        r.close()
+    if args.legs:
         for name in ("bqap-n25-dense", "bqap-n25-kron"):
             if name != args.workload:
                 _log("leg %s" % name)

@@ -77,7 +77,10 @@ typedef struct {
                                 (an objective with C_k = 0 is left as it is);
                                 -1 = the largest L <= 23 for which the int32 bounds of
                                 qubo_build_bqap hold */
-    int32_t reserved;        /* 0 */
+    int32_t fields;          /* width of the energy differences (local fields) the runs keep:
+                                0 = int32 when every bit's |P_aa| + sum_b |P_ab| <= 2^31 - 2 and
+                                2 alpha_k n < 2^30, else int64 (n <= 64 only); 32 = int32 only;
+                                64 = int64 (n <= 64) */
 } mda_build_opts;
 
 typedef struct {
@@ -89,7 +92,7 @@ typedef struct {
     int64_t maxabs_c;        /* max(max|C_1|, max|C_2|), after normalisation */
     int64_t device_bytes;    /* device memory held by the handle */
     int32_t normalise_log2;  /* L applied (0 = none) */
-    int32_t reserved;
+    int32_t fields;          /* 32 or 64: width of the energy differences */
     double scale1, scale2;   /* s_k applied to F_k (1 when none; energies are in scaled units) */
 } mda_qubo_info;
 
@@ -105,10 +108,11 @@ typedef struct {
  *   stream       hipStream_t for the uploads (NULL = default stream)
  *   out          receives the handle
  * Errors: MDA_EINVAL (n outside [2, 100], a NULL array, an unknown option),
- * MDA_EOVERFLOW (some bit's |P_aa| + sum_b |P_ab| exceeds 2^31-2, so its energy
- * difference would not fit int32; or 2 * alpha_k * n >= 2^30; or a scaled flow
- * beyond int32; with normalise_log2 = -1: no L in [1, 23] fits), MDA_ENOMEM,
- * MDA_EDEVICE.
+ * MDA_EOVERFLOW (a QUBO entry max|C_k| + 2 alpha_k beyond int32; a scaled flow
+ * beyond int32; int32 fields requested where some bit's |P_aa| + sum_b |P_ab|
+ * exceeds 2^31-2 or 2 alpha_k n >= 2^30; int64 fields needed or requested with
+ * n > 64; with normalise_log2 = -1: no L in [1, 23] fits int32 fields),
+ * MDA_ENOMEM, MDA_EDEVICE.
  */
 int qubo_build_bqap(int32_t n, const int32_t *F1, const int32_t *F2, const int32_t *D,
                     const mda_build_opts *opts, void *stream, mda_qubo **out);
@@ -206,7 +210,7 @@ int archive_get(mda_run *r, int32_t replica, int32_t raw, mda_archive_out *out, 
 
 typedef struct {
     uint8_t *x;             /* m bits, one byte each, may be NULL */
-    int32_t *h1, *h2;       /* local fields h_k[a] = sum_{b != a} P_k[a][b] x_b, may be NULL */
+    int64_t *h1, *h2;       /* local fields h_k[a] = sum_{b != a} P_k[a][b] x_b, may be NULL */
     int64_t e1, e2;         /* energies of x */
     int64_t e_offset;       /* current offset */
     int64_t moves;          /* accepted flips */
@@ -375,7 +379,7 @@ int da_run_layout(const mda_qubo *q, const mda_params *p, mda_run_layout *out);
  * i in [p*gns, p*gns + gns). */
 typedef struct {
     uint64_t *x;       /* [R][x_words] final solution */
-    int32_t *h;        /* [R][2][m] final local fields h_1, h_2 at bit a = i*n + u */
+    int64_t *h;        /* [R][2][m] final local fields h_1, h_2 at bit a = i*n + u */
     int64_t *st;       /* [R][16] E_1, E_2, E_offset, moves, archive entries compared, random blocks drawn,
                           archive size, steps with an exact acceptance test, non-dominated count; rest unused */
     int64_t *arch_e;   /* [R][s][2] archive energies (E_1, E_2) in slot order; slots [0, size) are defined */
@@ -391,7 +395,7 @@ typedef struct {
  * MDA_VARIANT_PLAIN and p->graph must be 0.  Errors: MDA_EINVAL (a NULL
  * argument or buffer, the plain form, the graph flag, and the argument checks
  * of da_run), MDA_ERANGE (more than MDA_NOALLOC_SCRATCH_BYTES of scratch
- * needed: replicas * 8 + steps * 12 bytes, roughly, with a temp_table or a
+ * needed: replicas * 8 + steps * 20 bytes, roughly, with a temp_table or a
  * schedule that keeps cooling), MDA_EOVERFLOW, MDA_EDEVICE. */
 int da_run_noalloc(const mda_qubo *q, const mda_params *p, const mda_run_buffers *b);
 

@@ -45,12 +45,13 @@ struct RunDesc {
     uint32_t key0, key1;       // Philox key
     uint32_t steps;            // annealing steps
     uint32_t ntab;             // temperature-table entries; T_t = T[min(t, ntab) - 1]
-    int32_t pad0;
+    int32_t f64;               // 1: int64 energy differences (fields beyond the int32 bounds)
     int64_t beta;
     int64_t q1, q2;
     // schedule tables
     const int64_t *T;          // fixed-point temperature, 8 fractional bits
-    const uint32_t *thrmax;    // (T * LNT[0]) >> 24
+    const uint32_t *thrmax;    // (T * LNT[0]) >> 24, saturated at 2^32 - 2
+    const int64_t *thrmax64;   // (T * LNT[0]) >> 24 (int64 runs)
     // Kronecker operands, n rows of kLD int32 (zero padded), row i' (or u'):
     //   P_k[(i,u)][(i',u')] = KA_k[i'][i] * DA[u'][u] (+ KB_k[i'][i] * DB[u'][u])
     //                         + 2 alpha_k [(i == i') != (u == u')]
@@ -61,7 +62,7 @@ struct RunDesc {
     const int32_t *diag1, *diag2;   // d_k[(i,u)] = P_k[a][a] at i * kLD + u
     // outputs and archives
     uint64_t *x;               // [R][64] column masks: bit i of word u is x_{i,u}
-    int32_t *h;                // [R][2][m] local fields (canonical order)
+    int64_t *h;                // [R][2][m] local fields (canonical order)
     int64_t *st;               // [R][kStWords]
     int64_t *archE;            // [R][s][2]
     uint64_t *archX;           // [R][s][n]

@@ -7,6 +7,7 @@
 #include <hip/hip_runtime.h>
 
 #include <climits>
+#include <type_traits>
 
 #include "mda_desc.h"
 
@@ -166,6 +167,7 @@ struct Hot {
     uint32_t steps, ntab, key0, key1;
     int64_t beta;
     const MDA_CONST uint32_t *thrmax;
+    const MDA_CONST int64_t *thrmax64;
     const MDA_CONST int64_t *T;
 };
 
@@ -181,15 +183,45 @@ __device__ __forceinline__ Hot load_hot(Desc *Dp)
     h.key1 = Dp->key1;
     h.beta = Dp->beta;
     h.thrmax = ro(Dp->thrmax);
+    h.thrmax64 = ro(Dp->thrmax64);
     h.T = ro(Dp->T);
     return h;
 }
 
 // ---------------------------------------------------------------- replica state
 
-template <int NS>
+// Energy-difference type of a run: int32 while every local field fits it
+// (the build-time bound), int64 beyond.  U is its unsigned counterpart (the
+// field updates wrap there), kMax the value of lanes beyond n, kDeadV the
+// value of slots beyond n (see kDead).
+template <class FT>
+struct Wide;
+template <>
+struct Wide<int32_t> {
+    using U = uint32_t;
+    static constexpr int32_t kMax = INT_MAX;
+    static constexpr int32_t kDeadV = 1 << 30;
+};
+template <>
+struct Wide<int64_t> {
+    using U = uint64_t;
+    static constexpr int64_t kMax = INT64_MAX;
+    static constexpr int64_t kDeadV = (int64_t)1 << 60;
+};
+
+__device__ __forceinline__ int32_t rlf(int32_t v, int lane)
+{
+    return __builtin_amdgcn_readlane(v, lane);
+}
+
+__device__ __forceinline__ int64_t rlf(int64_t v, int lane)
+{
+    return (int64_t)rl64((uint64_t)v, lane);
+}
+
+template <int NS, class FT = int32_t>
 struct Replica {
-    int32_t e1[NS], e2[NS];   // dE_k of bit (slot i, this lane)
+    FT e1[NS], e2[NS];        // dE_k of bit (slot i, this lane)
     uint64_t xm;              // bit i = x_{i, lane}
     int64_t E1, E2, Eoff;
     int64_t moves, scanned, rngb, detailed;
@@ -197,7 +229,7 @@ struct Replica {
     // per group of 8 slots, the lane's least combined difference (max of the
     // two for the strict rule, min for the lenient one); it only changes when
     // the fields do, so it is recomputed after a move or restart only
-    int32_t gmin[NS / 8];
+    FT gmin[NS / 8];
 };
 
 // Update paths (template argument PV): dense rows of P_k, or the Kronecker

@@ -525,8 +525,8 @@ __device__ __forceinline__ void g_export(Desc *Dp, const Replica<NS> &S, int r, 
     const int u = g.u;
     rw(D.x)[(size_t)r * D.xrw + (size_t)g.w * 64 + g.lane] = S.xm;
     if (u < n) {
-        MDA_GLOBAL int32_t *h1 = rw(D.h) + (size_t)r * 2 * m;
-        MDA_GLOBAL int32_t *h2 = h1 + m;
+        MDA_GLOBAL int64_t *h1 = rw(D.h) + (size_t)r * 2 * m;
+        MDA_GLOBAL int64_t *h2 = h1 + m;
 #pragma unroll
         for (int s = 0; s < NS; ++s) {
             const int i = g.i0 + s;
@@ -535,8 +535,8 @@ __device__ __forceinline__ void g_export(Desc *Dp, const Replica<NS> &S, int r, 
                 const bool on = (S.xm >> s) & 1ull;
                 const int32_t g1 = on ? -S.e1[s] : S.e1[s];
                 const int32_t g2 = on ? -S.e2[s] : S.e2[s];
-                h1[a] = g1 - ro(D.diag1)[i * D.ldk + u];
-                h2[a] = g2 - ro(D.diag2)[i * D.ldk + u];
+                h1[a] = (int64_t)(g1 - ro(D.diag1)[i * D.ldk + u]);
+                h2[a] = (int64_t)(g2 - ro(D.diag2)[i * D.ldk + u]);
             }
         }
     }

@@ -25,7 +25,7 @@ int group_waves_limit(int ns);
 hipError_t launch_group(int ns, int occ, int wr, int wc, const RunDesc *runs, const WorkItem *work, int nwork,
                         const int32_t *lnt, int grid, hipStream_t stream);
 hipError_t group_occupancy(int ns, int occ, int wr, int wc, int *blocks_per_cu);
-hipError_t launch_persistent(int ns, int occ, const RunDesc *runs, const WorkItem *work, int nwork,
+hipError_t launch_persistent(int ns, int occ, int f64, const RunDesc *runs, const WorkItem *work, int nwork,
                              const int32_t *lnt, int grid, int block, hipStream_t stream);
 hipError_t launch_plain(int ns, const RunDesc *run, int R, uint32_t steps, const int32_t *lnt, int block,
                         hipStream_t stream);
@@ -37,7 +37,7 @@ hipError_t launch_front_gather(const int64_t *archE, const uint8_t *nd, const in
                                const int64_t *offs, FrontEntry *out, hipStream_t stream);
 hipError_t launch_build_dense(int n, int ld, const int32_t *F, const int32_t *Dm, int32_t two_alpha, int32_t *P,
                               hipStream_t stream);
-hipError_t persistent_occupancy(int ns, int occ, int block, int *blocks_per_cu);
+hipError_t persistent_occupancy(int ns, int occ, int f64, int block, int *blocks_per_cu);
 }  // namespace mda
 
 using namespace mda;
@@ -197,6 +197,7 @@ struct mda_qubo {
     int64_t alpha[2] = {0, 0}, q[2] = {0, 0};
     int64_t maxabs = 0;
     int32_t norm = 0;                  // normalisation 2^norm of both objectives (0: none)
+    int32_t f64 = 0;                   // 1: energy differences in int64 (the int32 bounds fail)
     double scale[2] = {1.0, 1.0};      // s_k applied to F_k
     std::vector<int32_t> F1, F2, D, diag1, diag2;
     int32_t *dKA1 = nullptr, *dKA2 = nullptr, *dKB1 = nullptr, *dKB2 = nullptr, *dDA = nullptr, *dDB = nullptr;
@@ -303,6 +304,8 @@ static int build_bqap(int32_t n, const int32_t *F1, const int32_t *F2, const int
         for (int v = 0; v < n; ++v) DT[(size_t)v * n + u] = Dm[(size_t)u * n + v];
     bool nonneg = true;
     for (size_t e = 0; e < nn; ++e) nonneg &= q->D[e] >= 0 && q->F1[e] >= 0 && q->F2[e] >= 0;
+    // why int32 differences cannot hold this instance (empty: they can)
+    char why32[256] = "";
     const bool dsym_ = is_symmetric(q->D, n);
     for (int k = 0; k < 2; ++k) {
         const int32_t *F = Fk[k];
@@ -378,10 +381,15 @@ static int build_bqap(int32_t n, const int32_t *F1, const int32_t *F2, const int
         }
         q->alpha[k] = alpha;
         q->q[k] = alpha * 2 * n;
-        // slots beyond n hold 2^30 and drift by at most 2 alpha n; below 2^30 the
-        // drift keeps them positive and inside int32
-        if (2 * alpha * n >= (int64_t)1 << 30)
-            return fail(MDA_EOVERFLOW, "penalty 2*alpha_%d*n = %lld exceeds 2^30", k + 1, (long long)(2 * alpha * n));
+        // the column entries (at most max|C| + 2 alpha) and the penalty 2 alpha
+        // the kernels hold in 32 bits, at any difference width
+        if (mx + 2 * alpha > INT32_MAX)
+            return fail(MDA_EOVERFLOW, "objective %d: QUBO entries up to %lld exceed int32", k + 1,
+                        (long long)(mx + 2 * alpha));
+        // int32 differences: slots beyond n hold 2^30 and drift by at most
+        // 2 alpha n; below 2^30 the drift keeps them positive and inside int32
+        if (2 * alpha * n >= (int64_t)1 << 30 && !why32[0])
+            snprintf(why32, sizeof why32, "penalty 2*alpha_%d*n = %lld exceeds 2^30", k + 1, (long long)(2 * alpha * n));
         // Every local field |P_aa + sum_b P_ab x_b| must fit int32: with the
         // penalty 2 alpha on the 2 (n - 1) bits sharing a's row or column,
         // sum_b |P_ab| <= |P_aa| + sum |C_ab| + 4 alpha (n - 1), exact when
@@ -406,9 +414,9 @@ static int build_bqap(int32_t n, const int32_t *F1, const int32_t *F2, const int
                         }
                     }
                 }
-                if (sum > INT32_MAX - 1)
-                    return fail(MDA_EOVERFLOW, "objective %d: bit %d has sum |P_ab| = %lld > 2^31-2", k + 1, a,
-                                (long long)sum);
+                if (sum > INT32_MAX - 1 && !why32[0])
+                    snprintf(why32, sizeof why32, "objective %d: bit %d has sum |P_ab| = %lld > 2^31-2", k + 1, a,
+                             (long long)sum);
             }
     }
     q->diag1.resize(m);
@@ -456,7 +464,22 @@ static int build_bqap(int32_t n, const int32_t *F1, const int32_t *F2, const int
             for (int b = 0; b < n; ++b) DA[a * n + b] = Dm[b * n + a];
         track(DA);
     }
-    const bool kron_ok = maxop < (1 << 23);   // 24-bit multiply-adds
+    // 24-bit multiply-adds whose products (and, in the general form, their
+    // sum) fit int32; the row bound implies it for int32 differences
+    int64_t maxf = 0, maxd = 0;
+    for (int k = 0; k < 2; ++k) {
+        for (int32_t e : KA[k]) maxf = std::max<int64_t>(maxf, std::llabs((int64_t)e));
+        for (int32_t e : KB[k]) maxf = std::max<int64_t>(maxf, std::llabs((int64_t)e));
+    }
+    for (int32_t e : DA) maxd = std::max<int64_t>(maxd, std::llabs((int64_t)e));
+    for (int32_t e : DB) maxd = std::max<int64_t>(maxd, std::llabs((int64_t)e));
+    const bool kron_ok = maxop < (1 << 23) && (q->kform == kKronGen ? 2 : 1) * maxf * maxd <= INT32_MAX;
+    // width of the energy differences
+    if (o.fields == 32 && why32[0]) return fail(MDA_EOVERFLOW, "%s (int32 fields requested)", why32);
+    q->f64 = (o.fields == 64 || (o.fields == 0 && why32[0])) ? 1 : 0;
+    if (q->f64 && n > kMaxWaveN)
+        return fail(MDA_EOVERFLOW, "%s; int64 fields run one wave per replica (n <= %d), n = %d",
+                    why32[0] ? why32 : "int64 fields requested", kMaxWaveN, n);
     // Operand layouts: up to 64 facilities every row is padded to 64 entries
     // (one wave per replica reads them unmasked); beyond, rows of 128 entries
     // and the dense rows unpadded (the workgroup form masks its reads).
@@ -533,6 +556,8 @@ extern "C" int qubo_build_bqap(int32_t n, const int32_t *F1, const int32_t *F2, 
     if (o.path < MDA_PATH_AUTO || o.path > MDA_PATH_KRON) return fail(MDA_EINVAL, "unknown path %d", o.path);
     if (o.normalise_log2 < -1 || o.normalise_log2 > 30)
         return fail(MDA_EINVAL, "normalise_log2 = %d outside [-1, 30]", o.normalise_log2);
+    if (o.fields != 0 && o.fields != 32 && o.fields != 64)
+        return fail(MDA_EINVAL, "fields = %d (0, 32 or 64)", o.fields);
     hipStream_t stream = (hipStream_t)stream_;
     int64_t mxk[2] = {0, 0};
     if (o.normalise_log2 != 0) {
@@ -540,9 +565,12 @@ extern "C" int qubo_build_bqap(int32_t n, const int32_t *F1, const int32_t *F2, 
         mxk[1] = objective_maxabs(F2, D, n);
     }
     if (o.normalise_log2 != -1) return build_bqap(n, F1, F2, D, o, o.normalise_log2, mxk, stream, out);
-    // the paper's 2^23 where the int32 bounds allow it, else the largest power below
+    // the paper's 2^23 where the int32 bounds allow it, else the largest power
+    // below (int32 fields unless int64 ones were asked for)
+    mda_build_opts o32 = o;
+    if (o32.fields == 0) o32.fields = 32;
     for (int L = 23; L >= 1; --L) {
-        const int rc = build_bqap(n, F1, F2, D, o, L, mxk, stream, out);
+        const int rc = build_bqap(n, F1, F2, D, o32, L, mxk, stream, out);
         if (rc != MDA_EOVERFLOW) return rc;
     }
     return fail(MDA_EOVERFLOW, "no normalisation 2^L with 1 <= L <= 23 keeps every field within int32");
@@ -570,7 +598,7 @@ extern "C" int qubo_info(const mda_qubo *q, mda_qubo_info *info)
     info->maxabs_c = q->maxabs;
     info->device_bytes = q->pool.total;
     info->normalise_log2 = q->norm;
-    info->reserved = 0;
+    info->fields = q->f64 ? 64 : 32;
     info->scale1 = q->scale[0];
     info->scale2 = q->scale[1];
     return MDA_OK;
@@ -653,13 +681,21 @@ extern "C" void mda_params_default(mda_params *p)
     p->variant = MDA_VARIANT_AUTO;
 }
 
+// Host tables of a run: the fixed-point temperature T_t of each step and the
+// largest threshold (T_t LNT[0]) >> 24, saturated at 2^32 - 2 for int32
+// differences and as it is for int64 ones.
+struct RunTables {
+    std::vector<int64_t> T, thr64;
+    std::vector<uint32_t> thr32;
+};
+
 // Checks p against q, resolves its defaults and fills the run descriptor d
-// (every field but the device buffers of the run) and the host tables: the
-// fixed-point temperature T_t and the largest threshold (T_t LNT[0]) >> 24 of
-// each step.  Allocates nothing on the device.
-static int resolve_run(const mda_qubo *q, const mda_params *pin, mda_params &p, RunDesc &d, std::vector<int64_t> &T,
-                       std::vector<uint32_t> &thrmax)
+// (every field but the device buffers of the run) and the host tables.
+// Allocates nothing on the device.
+static int resolve_run(const mda_qubo *q, const mda_params *pin, mda_params &p, RunDesc &d, RunTables &tab)
 {
+    std::vector<int64_t> &T = tab.T;
+    std::vector<uint32_t> &thrmax = tab.thr32;
     p = *pin;
     if (p.replicas < 1) return fail(MDA_EINVAL, "replicas = %d", p.replicas);
     if (p.steps == 0) p.steps = (int64_t)std::llround(0.25 * (double)q->m * (double)q->m);
@@ -693,11 +729,13 @@ static int resolve_run(const mda_qubo *q, const mda_params *pin, mda_params &p, 
     int32_t lnt[4096];
     threshold_table(lnt);
     thrmax.assign(T.size(), 0u);
+    tab.thr64.assign(T.size(), 0);
     for (size_t t = 0; t < T.size(); ++t) {
         if (T[t] < 0 || (double)T[t] > kMaxTemp) return fail(MDA_EOVERFLOW, "temperature %lld out of range", (long long)T[t]);
         // saturated like the kernels' thresholds: 2^32 - 2 exceeds every statistic
         const uint64_t v = ((uint64_t)T[t] * (uint64_t)lnt[0]) >> 24;
         thrmax[t] = (uint32_t)std::min<uint64_t>(v, 0xFFFFFFFEull);
+        tab.thr64[t] = (int64_t)v;
     }
 
     const int n = q->n, m = q->m, R = p.replicas;
@@ -722,6 +760,9 @@ static int resolve_run(const mda_qubo *q, const mda_params *pin, mda_params &p, 
     d.beta = p.beta;
     d.q1 = q->q[0];
     d.q2 = q->q[1];
+    d.f64 = q->f64;
+    if (q->f64 && p.variant == MDA_VARIANT_PLAIN)
+        return fail(MDA_EINVAL, "the plain form runs int32 energy differences only");
     // Layout of a replica over waves: one wave (n <= 64) or a workgroup of
     // wr x wc waves, wc = ceil(n / 64) location blocks and wr facility blocks of
     // gns = 8 ceil(ceil(n / wr) / 8) slots.
@@ -730,6 +771,8 @@ static int resolve_run(const mda_qubo *q, const mda_params *pin, mda_params &p, 
         const int wc = (n + 63) / 64;
         if (want < 0 || want > 8) return fail(MDA_EINVAL, "waves_per_replica = %d outside [0, 8]", want);
         if (want == 1 && n > kMaxWaveN) return fail(MDA_EINVAL, "n = %d needs more than one wave per replica", n);
+        if (q->f64 && want > 1)
+            return fail(MDA_EINVAL, "int64 energy differences run one wave per replica (waves_per_replica = %d)", want);
         if ((want == 0 && n <= kMaxWaveN) || want == 1) {
             d.wr = d.wc = 1;
             d.gns = ns_for(n);
@@ -762,34 +805,37 @@ static int resolve_run(const mda_qubo *q, const mda_params *pin, mda_params &p, 
 static int prepare_run(mda_qubo *q, const mda_params *pin, hipStream_t stream, mda_run **out)
 {
     std::unique_ptr<mda_run> r(new mda_run);
-    std::vector<int64_t> T;
-    std::vector<uint32_t> thrmax;
+    RunTables tab;
     {
-        const int rc = resolve_run(q, pin, r->p, r->h, T, thrmax);
+        const int rc = resolve_run(q, pin, r->p, r->h, tab);
         if (rc) return rc;
     }
+    const std::vector<int64_t> &T = tab.T;
     const mda_params &p = r->p;
     RunDesc &d = r->h;
     const int m = q->m, R = p.replicas, s = d.s;
     DevPool &pool = r->pool;
     int64_t *dT = pool.alloc<int64_t>(T.size(), stream);
     uint32_t *dthr = pool.alloc<uint32_t>(T.size(), stream);
+    int64_t *dthr64 = pool.alloc<int64_t>(T.size(), stream);
     d.x = pool.alloc<uint64_t>((size_t)R * d.xrw, stream);
-    d.h = pool.alloc<int32_t>((size_t)R * 2 * m, stream);
+    d.h = pool.alloc<int64_t>((size_t)R * 2 * m, stream);
     d.st = pool.alloc<int64_t>((size_t)R * kStWords, stream);
     d.archE = pool.alloc<int64_t>((size_t)R * s * 2, stream);
     d.archX = pool.alloc<uint64_t>((size_t)R * s * d.xw, stream);
     d.nd = pool.alloc<uint8_t>((size_t)R * s, stream);
     d.trace = pool.alloc<int32_t>((size_t)std::max(1, p.trace_replicas) * (size_t)(p.trace_replicas ? p.steps : 1), stream);
     if (p.variant == MDA_VARIANT_PLAIN) d.pe = pool.alloc<int32_t>((size_t)R * 2 * d.ns_plain * 64, stream);
-    if (!dT || !dthr || !d.x || !d.h || !d.st || !d.archE || !d.archX || !d.nd || !d.trace ||
+    if (!dT || !dthr || !dthr64 || !d.x || !d.h || !d.st || !d.archE || !d.archX || !d.nd || !d.trace ||
         (p.variant == MDA_VARIANT_PLAIN && !d.pe))
         return fail(MDA_ENOMEM, "device allocation failed for the run (%lld bytes so far)", (long long)pool.total);
     HIP_TRY(hipMemcpyAsync(dT, T.data(), T.size() * sizeof(int64_t), hipMemcpyHostToDevice, stream));
-    HIP_TRY(hipMemcpyAsync(dthr, thrmax.data(), thrmax.size() * sizeof(uint32_t), hipMemcpyHostToDevice, stream));
+    HIP_TRY(hipMemcpyAsync(dthr, tab.thr32.data(), tab.thr32.size() * sizeof(uint32_t), hipMemcpyHostToDevice, stream));
+    HIP_TRY(hipMemcpyAsync(dthr64, tab.thr64.data(), tab.thr64.size() * sizeof(int64_t), hipMemcpyHostToDevice, stream));
     HIP_TRY(hipMemsetAsync(d.nd, 0, (size_t)R * s, stream));
     d.T = dT;
     d.thrmax = dthr;
+    d.thrmax64 = dthr64;
     q->refs++;
     r->q = q;
     *out = r.release();
@@ -809,7 +855,7 @@ namespace {
 // One persistent launch: the work items [off, off + cnt) of one register tile
 // and replica layout.
 struct Group {
-    int ns, wr, wc, off, cnt;
+    int ns, wr, wc, f64, off, cnt;
 };
 
 // Work list of a launch: runs grouped by register tile, largest tile first
@@ -825,6 +871,7 @@ void plan_work(const std::vector<RunDesc> &descs, std::vector<WorkItem> &work, s
         const RunDesc &x = descs[a], &y = descs[b];
         if (x.wr * x.wc != y.wr * y.wc) return x.wr * x.wc > y.wr * y.wc;
         if (x.wc != y.wc) return x.wc > y.wc;
+        if (x.f64 != y.f64) return x.f64 > y.f64;
         if (x.gns != y.gns) return x.gns > y.gns;
         return (int64_t)x.m * x.steps > (int64_t)y.m * y.steps;
     });
@@ -832,8 +879,9 @@ void plan_work(const std::vector<RunDesc> &descs, std::vector<WorkItem> &work, s
     groups.clear();
     for (int i : order) {
         const RunDesc &d = descs[i];
-        if (groups.empty() || groups.back().ns != d.gns || groups.back().wr != d.wr || groups.back().wc != d.wc)
-            groups.push_back(Group{d.gns, d.wr, d.wc, (int)work.size(), 0});
+        if (groups.empty() || groups.back().ns != d.gns || groups.back().wr != d.wr || groups.back().wc != d.wc ||
+            groups.back().f64 != d.f64)
+            groups.push_back(Group{d.gns, d.wr, d.wc, d.f64, (int)work.size(), 0});
         for (int rr = 0; rr < d.R; ++rr) work.push_back(WorkItem{i, rr});
         groups.back().cnt += d.R;
     }
@@ -856,17 +904,19 @@ int enqueue_anneal(const std::vector<Group> &groups, const RunDesc &first, bool 
             // one wave per SIMD when that holds every replica of the launch
             // at once, the two-wave build when more are waiting
             const int wpb = block / 64;
-            HIP_TRY(persistent_occupancy(g.ns, 1, block, &per_cu));
+            HIP_TRY(persistent_occupancy(g.ns, 1, g.f64, block, &per_cu));
             if (per_cu < 1) per_cu = 1;
-            const int occ = (int64_t)g.cnt > (int64_t)cus * per_cu * wpb ? 2 : 1;
+            // (the int64 build has one register budget only)
+            const int occ = !g.f64 && (int64_t)g.cnt > (int64_t)cus * per_cu * wpb ? 2 : 1;
             if (occ == 2) {
-                HIP_TRY(persistent_occupancy(g.ns, 2, block, &per_cu));
+                HIP_TRY(persistent_occupancy(g.ns, 2, 0, block, &per_cu));
                 if (per_cu < 1) per_cu = 1;
             }
             int grid = cus * per_cu;
             const int need = (g.cnt + wpb - 1) / wpb;
             if (grid > need) grid = need;
-            const hipError_t le = launch_persistent(g.ns, occ, ddesc, dwork + g.off, g.cnt, dlnt, grid, block, stream);
+            const hipError_t le =
+                launch_persistent(g.ns, occ, g.f64, ddesc, dwork + g.off, g.cnt, dlnt, grid, block, stream);
             if (le != hipSuccess)
                 return fail(MDA_EDEVICE, "persistent launch (ns %d, grid %d, block %d, %d blocks/CU) failed: %s", g.ns,
                             grid, block, per_cu, hipGetErrorString(le));
@@ -1066,7 +1116,7 @@ size_t align256(size_t b)
 // Byte offsets of the parts of the scratch area for R work items and ntab
 // table entries; returns the total.
 struct ScratchPlan {
-    size_t desc, work, lnt, T, thr, total;
+    size_t desc, work, lnt, T, thr, thr64, total;
 };
 
 ScratchPlan scratch_plan(int64_t R, int64_t ntab)
@@ -1077,7 +1127,8 @@ ScratchPlan scratch_plan(int64_t R, int64_t ntab)
     sp.lnt = sp.work + align256((size_t)R * sizeof(WorkItem));
     sp.T = sp.lnt + align256(4096 * sizeof(int32_t));
     sp.thr = sp.T + align256((size_t)ntab * sizeof(int64_t));
-    sp.total = sp.thr + align256((size_t)ntab * sizeof(uint32_t));
+    sp.thr64 = sp.thr + align256((size_t)ntab * sizeof(uint32_t));
+    sp.total = sp.thr64 + align256((size_t)ntab * sizeof(int64_t));
     return sp;
 }
 
@@ -1118,11 +1169,10 @@ extern "C" int da_run_layout(const mda_qubo *q, const mda_params *pin, mda_run_l
     if (!q || !pin || !out) return fail(MDA_EINVAL, "NULL argument");
     mda_params p;
     RunDesc d;
-    std::vector<int64_t> T;
-    std::vector<uint32_t> thrmax;
-    const int rc = resolve_run(q, pin, p, d, T, thrmax);
+    RunTables tab;
+    const int rc = resolve_run(q, pin, p, d, tab);
     if (rc) return rc;
-    return fill_layout(p, d, (int64_t)T.size(), out);
+    return fill_layout(p, d, (int64_t)tab.T.size(), out);
 }
 
 extern "C" int da_run_noalloc(const mda_qubo *q, const mda_params *pin, const mda_run_buffers *b)
@@ -1141,10 +1191,10 @@ extern "C" int da_run_noalloc(const mda_qubo *q, const mda_params *pin, const md
     }
     mda_params p;
     RunDesc d;
-    std::vector<int64_t> T;
-    std::vector<uint32_t> thrmax;
-    int rc = resolve_run(q, pin, p, d, T, thrmax);
+    RunTables tab;
+    int rc = resolve_run(q, pin, p, d, tab);
     if (rc) return rc;
+    const std::vector<int64_t> &T = tab.T;
     mda_run_layout lay;
     rc = fill_layout(p, d, (int64_t)T.size(), &lay);
     if (rc) return rc;
@@ -1158,6 +1208,7 @@ extern "C" int da_run_noalloc(const mda_qubo *q, const mda_params *pin, const md
     int32_t *dlnt = reinterpret_cast<int32_t *>(sb + sp.lnt);
     d.T = reinterpret_cast<const int64_t *>(sb + sp.T);
     d.thrmax = reinterpret_cast<const uint32_t *>(sb + sp.thr);
+    d.thrmax64 = reinterpret_cast<const int64_t *>(sb + sp.thr64);
     d.x = b->x;
     d.h = b->h;
     d.st = b->st;
@@ -1177,7 +1228,10 @@ extern "C" int da_run_noalloc(const mda_qubo *q, const mda_params *pin, const md
     HIP_TRY(hipMemcpyAsync(dwork, work.data(), work.size() * sizeof(WorkItem), hipMemcpyHostToDevice, stream));
     HIP_TRY(hipMemcpyAsync(dlnt, lnt, sizeof lnt, hipMemcpyHostToDevice, stream));
     HIP_TRY(hipMemcpyAsync(sb + sp.T, T.data(), T.size() * sizeof(int64_t), hipMemcpyHostToDevice, stream));
-    HIP_TRY(hipMemcpyAsync(sb + sp.thr, thrmax.data(), thrmax.size() * sizeof(uint32_t), hipMemcpyHostToDevice, stream));
+    HIP_TRY(hipMemcpyAsync(sb + sp.thr, tab.thr32.data(), tab.thr32.size() * sizeof(uint32_t), hipMemcpyHostToDevice,
+                           stream));
+    HIP_TRY(hipMemcpyAsync(sb + sp.thr64, tab.thr64.data(), tab.thr64.size() * sizeof(int64_t), hipMemcpyHostToDevice,
+                           stream));
     int dev = 0, cus = 0;
     HIP_TRY(hipGetDevice(&dev));
     HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
@@ -1258,8 +1312,8 @@ extern "C" int da_state_get(mda_run *r, int32_t replica, mda_state *out)
         for (int i = 0; i < n; ++i)
             for (int u = 0; u < n; ++u) out->x[i * n + u] = sol_bit(d, words.data(), i, u) ? 1 : 0;
     }
-    if (out->h1 && (rc = copy_d2h(out->h1, d.h + (size_t)replica * 2 * m, (size_t)m * 4, s))) return rc;
-    if (out->h2 && (rc = copy_d2h(out->h2, d.h + (size_t)replica * 2 * m + m, (size_t)m * 4, s))) return rc;
+    if (out->h1 && (rc = copy_d2h(out->h1, d.h + (size_t)replica * 2 * m, (size_t)m * 8, s))) return rc;
+    if (out->h2 && (rc = copy_d2h(out->h2, d.h + (size_t)replica * 2 * m + m, (size_t)m * 8, s))) return rc;
     if (out->trace) {
         if (replica >= d.trace_R) return fail(MDA_EINVAL, "replica %d was not traced", replica);
         rc = copy_d2h(out->trace, d.trace + (size_t)replica * d.steps, (size_t)d.steps * 4, s);
@@ -1482,8 +1536,8 @@ extern "C" int64_t mda_footprint(int32_t n, const mda_params *p, const mda_build
     const int G = group ? (p->waves_per_replica > 1 ? p->waves_per_replica : 2 * wc) : 1;
     const int64_t xw = group ? (int64_t)G * 64 : n, xrw = group ? (int64_t)G * 64 : 64;
     // run: x, fields, statistics, archive energies, solutions and flags, tables, trace
-    int64_t b = R * (xrw * 8 + 2 * m * 4 + kStWords * 8) + R * s * (16 + xw * 8 + 1);
-    b += steps * 12 + 65536;
+    int64_t b = R * (xrw * 8 + 2 * m * 8 + kStWords * 8) + R * s * (16 + xw * 8 + 1);
+    b += steps * 20 + 65536;
     if (p->trace_replicas > 0) b += (int64_t)p->trace_replicas * steps * 4;
     // QUBO: dense rows when the build will pick them, the per-lane operands
     const mda_build_opts o = bo ? *bo : mda_build_opts{MDA_PEN_2MAX, MDA_PATH_AUTO, 0};
@@ -1500,9 +1554,10 @@ extern "C" int64_t mda_footprint(int32_t n, const mda_params *p, const mda_build
 namespace {
 
 struct TuneKey {
-    int32_t n, path, kform, accept, rbucket;
+    int32_t n, path, kform, accept, rbucket, f64;
     bool operator<(const TuneKey &o) const
     {
+        if (f64 != o.f64) return f64 < o.f64;
         if (n != o.n) return n < o.n;
         if (path != o.path) return path < o.path;
         if (kform != o.kform) return kform < o.kform;
@@ -1526,7 +1581,7 @@ extern "C" int mda_autotune(const mda_qubo *q, const mda_params *pin, int64_t pr
     if (probe_replicas > 0 && probe_replicas < R) R = probe_replicas;
     int rb = 0;
     while ((1 << (rb + 1)) <= pin->replicas && rb < 30) ++rb;
-    const TuneKey key{n, q->path, q->kform, pin->accept, rb};
+    const TuneKey key{n, q->path, q->kform, pin->accept, rb, q->f64};
     {
         std::lock_guard<std::mutex> g(g_tune_mu);
         auto it = g_tune_cache.find(key);
@@ -1544,6 +1599,7 @@ extern "C" int mda_autotune(const mda_qubo *q, const mda_params *pin, int64_t pr
         for (int wpb : {1, 2, 4}) cand.push_back({1, wpb});
     const int wc = (n + 63) / 64;
     for (int g : {2, 4}) {
+        if (q->f64) break;   // int64 differences run one wave per replica
         const int wr = std::max(1, g / wc);
         if (wr * wc != g) continue;
         const int gns = (((n + wr - 1) / wr + 7) / 8) * 8;

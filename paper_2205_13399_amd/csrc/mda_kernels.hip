@@ -132,17 +132,21 @@ int ns_for(int n)
                                        const int32_t *lnt, int grid, int block, hipStream_t stream);       \
     hipError_t persistent_occupancy_ns##N(int occ, int block, int *blocks_per_cu);                        \
     hipError_t launch_plain_ns##N(const RunDesc *run, int R, uint32_t steps, const int32_t *lnt, int block, \
-                                  hipStream_t stream);
+                                  hipStream_t stream);                                                     \
+    hipError_t launch_persistent64_ns##N(const RunDesc *runs, const WorkItem *work, int nwork,             \
+                                         const int32_t *lnt, int grid, int block, hipStream_t stream);     \
+    hipError_t persistent64_occupancy_ns##N(int block, int *blocks_per_cu);
 MDA_NS_LIST(MDA_WAVE_DECL)
 #undef MDA_WAVE_DECL
 
-hipError_t launch_persistent(int ns, int occ, const RunDesc *runs, const WorkItem *work, int nwork,
+hipError_t launch_persistent(int ns, int occ, int f64, const RunDesc *runs, const WorkItem *work, int nwork,
                              const int32_t *lnt, int grid, int block, hipStream_t stream)
 {
     switch (ns) {
-#define X(N) \
-    case N:  \
-        return launch_persistent_ns##N(occ, runs, work, nwork, lnt, grid, block, stream);
+#define X(N)                                                                                       \
+    case N:                                                                                        \
+        return f64 ? launch_persistent64_ns##N(runs, work, nwork, lnt, grid, block, stream)       \
+                   : launch_persistent_ns##N(occ, runs, work, nwork, lnt, grid, block, stream);
         MDA_NS_LIST(X)
 #undef X
     default:
@@ -150,12 +154,13 @@ hipError_t launch_persistent(int ns, int occ, const RunDesc *runs, const WorkIte
     }
 }
 
-hipError_t persistent_occupancy(int ns, int occ, int block, int *blocks_per_cu)
+hipError_t persistent_occupancy(int ns, int occ, int f64, int block, int *blocks_per_cu)
 {
     switch (ns) {
-#define X(N) \
-    case N:  \
-        return persistent_occupancy_ns##N(occ, block, blocks_per_cu);
+#define X(N)                                                                     \
+    case N:                                                                      \
+        return f64 ? persistent64_occupancy_ns##N(block, blocks_per_cu)          \
+                   : persistent_occupancy_ns##N(occ, block, blocks_per_cu);
         MDA_NS_LIST(X)
 #undef X
     default:

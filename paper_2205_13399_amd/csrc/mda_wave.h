@@ -31,10 +31,12 @@ namespace mda {
 // for every other bit a, dE_k[a] += (x_a == x_j ? +1 : -1) * P_k[a][j];
 // dE_k(j) = -dE_k(j).  The per-slot code has no branch: the own-row penalty
 // of slot js and the new value of bit j enter through a per-slot select.
-template <int NS, int PV>
-__device__ __forceinline__ void flip(Desc *Dp, int n_, Replica<NS> &S, int js, int jl, int32_t d1, int32_t d2,
-                                     int lane_)
+// Column entries fit int32 (build-time bound); the differences are updated in
+// the unsigned counterpart UT of their type FT, where the additions wrap.
+template <int NS, int PV, class FT>
+__device__ __forceinline__ void flip(Desc *Dp, int n_, Replica<NS, FT> &S, int js, int jl, FT d1, FT d2, int lane_)
 {
+    using UT = typename Wide<FT>::U;
     const int n = opaque(n_);
     const int lane = opaque_lane(lane_);
     const bool live = lane < n;
@@ -47,8 +49,8 @@ __device__ __forceinline__ void flip(Desc *Dp, int n_, Replica<NS> &S, int js, i
         // Row j of P_k holds every column entry, penalty and diagonal included;
         // bit j itself gets -2 d - P_jj on top of P_jj.
         const int j = js * n + jl;
-        const uint32_t c1 = (lane == jl) ? (uint32_t)(-2 * d1) - (uint32_t)ro(D.diag1)[js * kLD + jl] : 0u;
-        const uint32_t c2 = (lane == jl) ? (uint32_t)(-2 * d2) - (uint32_t)ro(D.diag2)[js * kLD + jl] : 0u;
+        const UT c1 = (lane == jl) ? (UT)(-2 * d1) - (UT)(FT)ro(D.diag1)[js * kLD + jl] : (UT)0;
+        const UT c2 = (lane == jl) ? (UT)(-2 * d2) - (UT)(FT)ro(D.diag2)[js * kLD + jl] : (UT)0;
         const MDA_CONST int32_t *r1 = ro(D.P1) + (size_t)j * (size_t)(n * kLD);
         const MDA_CONST int32_t *r2 = ro(D.P2) + (size_t)j * (size_t)(n * kLD);
 #pragma unroll
@@ -65,12 +67,12 @@ __device__ __forceinline__ void flip(Desc *Dp, int n_, Replica<NS> &S, int js, i
 #pragma unroll
             for (int f = 0; f < 8; ++f) {
                 const int i = g + f;
-                const uint32_t b = (uint32_t)(xmx >> i) & 1u;
-                const uint32_t m = 0u - b;
-                const uint32_t u1 = t1[f] + ((i == js) ? c1 : 0u);
-                const uint32_t u2 = t2[f] + ((i == js) ? c2 : 0u);
-                S.e1[i] = (int32_t)((uint32_t)S.e1[i] + (u1 ^ m) + b);
-                S.e2[i] = (int32_t)((uint32_t)S.e2[i] + (u2 ^ m) + b);
+                const UT b = (UT)((xmx >> i) & 1ull);
+                const UT m = (UT)0 - b;
+                const UT u1 = (UT)(FT)(int32_t)t1[f] + ((i == js) ? c1 : (UT)0);
+                const UT u2 = (UT)(FT)(int32_t)t2[f] + ((i == js) ? c2 : (UT)0);
+                S.e1[i] = (FT)((UT)S.e1[i] + (u1 ^ m) + b);
+                S.e2[i] = (FT)((UT)S.e2[i] + (u2 ^ m) + b);
             }
         }
     } else {
@@ -86,29 +88,29 @@ __device__ __forceinline__ void flip(Desc *Dp, int n_, Replica<NS> &S, int js, i
         const int32_t fa2 = ro(D.KA2)[js * kLD + lane];
         const int32_t fb1 = (PV == kPvKronGen) ? ro(D.KB1)[js * kLD + lane] : 0;
         const int32_t fb2 = (PV == kPvKronGen) ? ro(D.KB2)[js * kLD + lane] : 0;
-        const uint32_t ta1 = (uint32_t)D.two_alpha1, ta2 = (uint32_t)D.two_alpha2;
+        const UT ta1 = (UT)(FT)D.two_alpha1, ta2 = (UT)(FT)D.two_alpha2;
         const bool atj = lane == jl;
-        const uint32_t q1 = atj ? ta1 : 0u, q2 = atj ? ta2 : 0u;
-        uint32_t own1 = (uint32_t)__mul24(rl(fa1, js), dv), own2 = (uint32_t)__mul24(rl(fa2, js), dv);
+        const UT q1 = atj ? ta1 : (UT)0, q2 = atj ? ta2 : (UT)0;
+        UT own1 = (UT)(FT)__mul24(rl(fa1, js), dv), own2 = (UT)(FT)__mul24(rl(fa2, js), dv);
         if (PV == kPvKronGen) {
-            own1 += (uint32_t)__mul24(rl(fb1, js), dw);
-            own2 += (uint32_t)__mul24(rl(fb2, js), dw);
+            own1 += (UT)(FT)__mul24(rl(fb1, js), dw);
+            own2 += (UT)(FT)__mul24(rl(fb2, js), dw);
         }
-        const uint32_t r1 = atj ? (uint32_t)(-2 * d1) - own1 : (live ? ta1 : 0u);
-        const uint32_t r2 = atj ? (uint32_t)(-2 * d2) - own2 : (live ? ta2 : 0u);
+        const UT r1 = atj ? (UT)(-2 * d1) - own1 : (live ? ta1 : (UT)0);
+        const UT r2 = atj ? (UT)(-2 * d2) - own2 : (live ? ta2 : (UT)0);
 #pragma unroll
         for (int i = 0; i < NS; ++i) {
-            // wrapping 32-bit arithmetic: the column entry itself fits int32
-            uint32_t t1 = (uint32_t)__mul24(rl(fa1, i), dv) + ((i == js) ? r1 : q1);
-            uint32_t t2 = (uint32_t)__mul24(rl(fa2, i), dv) + ((i == js) ? r2 : q2);
+            // wrapping arithmetic: each product and the column entry fit int32
+            UT t1 = (UT)(FT)__mul24(rl(fa1, i), dv) + ((i == js) ? r1 : q1);
+            UT t2 = (UT)(FT)__mul24(rl(fa2, i), dv) + ((i == js) ? r2 : q2);
             if (PV == kPvKronGen) {
-                t1 += (uint32_t)__mul24(rl(fb1, i), dw);
-                t2 += (uint32_t)__mul24(rl(fb2, i), dw);
+                t1 += (UT)(FT)__mul24(rl(fb1, i), dw);
+                t2 += (UT)(FT)__mul24(rl(fb2, i), dw);
             }
-            const uint32_t b = (uint32_t)(xmx >> i) & 1u;
-            const uint32_t m = 0u - b;
-            S.e1[i] = (int32_t)((uint32_t)S.e1[i] + (t1 ^ m) + b);
-            S.e2[i] = (int32_t)((uint32_t)S.e2[i] + (t2 ^ m) + b);
+            const UT b = (UT)((xmx >> i) & 1ull);
+            const UT m = (UT)0 - b;
+            S.e1[i] = (FT)((UT)S.e1[i] + (t1 ^ m) + b);
+            S.e2[i] = (FT)((UT)S.e2[i] + (t2 ^ m) + b);
         }
     }
     S.xm ^= (lane == jl) ? (1ull << js) : 0ull;
@@ -119,9 +121,10 @@ __device__ __forceinline__ void flip(Desc *Dp, int n_, Replica<NS> &S, int js, i
 // E_k = q_k + sum_{a in x} (d_k[a] + g_k[a]) / 2 (Eq. qubo).  The column sums
 // run over the set bits; the penalty part 2 alpha_k [(i == i') != (u == u')]
 // is counted from the row and column occupation of x.
-template <int NS, int PV>
-__device__ __forceinline__ void fields_from_scratch(Desc *Dp, Replica<NS> &S, int lane_)
+template <int NS, int PV, class FT>
+__device__ __forceinline__ void fields_from_scratch(Desc *Dp, Replica<NS, FT> &S, int lane_)
 {
+    using UT = typename Wide<FT>::U;
     const int lane = opaque_lane(lane_);
     Desc &D = *cold(Dp);
     const int n = opaque(D.n);
@@ -147,8 +150,8 @@ __device__ __forceinline__ void fields_from_scratch(Desc *Dp, Replica<NS> &S, in
 #pragma unroll
                 for (int f = 0; f < 8; ++f) {
                     const int i = g + f;
-                    S.e1[i] = (int32_t)((uint32_t)S.e1[i] + ((i < n) ? (uint32_t)r1[i * kLD + lane] : 0u));
-                    S.e2[i] = (int32_t)((uint32_t)S.e2[i] + ((i < n) ? (uint32_t)r2[i * kLD + lane] : 0u));
+                    S.e1[i] = (FT)((UT)S.e1[i] + ((i < n) ? (UT)(FT)r1[i * kLD + lane] : (UT)0));
+                    S.e2[i] = (FT)((UT)S.e2[i] + ((i < n) ? (UT)(FT)r2[i * kLD + lane] : (UT)0));
                 }
             }
         } else {
@@ -160,14 +163,14 @@ __device__ __forceinline__ void fields_from_scratch(Desc *Dp, Replica<NS> &S, in
             const int32_t fb2 = (PV == kPvKronGen) ? ro(D.KB2)[bi * kLD + lane] : 0;
 #pragma unroll
             for (int i = 0; i < NS; ++i) {
-                uint32_t t1 = (uint32_t)__mul24(rl(fa1, i), dv);
-                uint32_t t2 = (uint32_t)__mul24(rl(fa2, i), dv);
+                UT t1 = (UT)(FT)__mul24(rl(fa1, i), dv);
+                UT t2 = (UT)(FT)__mul24(rl(fa2, i), dv);
                 if (PV == kPvKronGen) {
-                    t1 += (uint32_t)__mul24(rl(fb1, i), dw);
-                    t2 += (uint32_t)__mul24(rl(fb2, i), dw);
+                    t1 += (UT)(FT)__mul24(rl(fb1, i), dw);
+                    t2 += (UT)(FT)__mul24(rl(fb2, i), dw);
                 }
-                S.e1[i] = (int32_t)((uint32_t)S.e1[i] + t1);
-                S.e2[i] = (int32_t)((uint32_t)S.e2[i] + t2);
+                S.e1[i] = (FT)((UT)S.e1[i] + t1);
+                S.e2[i] = (FT)((UT)S.e2[i] + t2);
             }
         }
         todo ^= (lane == bu) ? (1ull << bi) : 0ull;
@@ -175,7 +178,7 @@ __device__ __forceinline__ void fields_from_scratch(Desc *Dp, Replica<NS> &S, in
     // Self term, penalty counts, diagonal, sign; energies.
     const uint64_t xl = live ? S.xm : 0ull;
     const uint32_t cu = (uint32_t)__popcll(xl);   // bits set in this lane's column
-    const uint32_t ta1 = (uint32_t)D.two_alpha1, ta2 = (uint32_t)D.two_alpha2;
+    const UT ta1 = (UT)(FT)D.two_alpha1, ta2 = (UT)(FT)D.two_alpha2;
     const int32_t lslot = live ? 0 : 1;            // lanes beyond n
     int64_t acc1 = 0, acc2 = 0;
 #pragma unroll
@@ -183,36 +186,36 @@ __device__ __forceinline__ void fields_from_scratch(Desc *Dp, Replica<NS> &S, in
         const bool on = (xl >> i) & 1ull;
         const bool ok = live && i < n;
         const uint32_t ri = (uint32_t)__popcll(__ballot(on));   // bits set in row i
-        const uint32_t dg1 = (uint32_t)ro(D.diag1)[i * kLD + lane];   // padded: 0 beyond n
-        const uint32_t dg2 = (uint32_t)ro(D.diag2)[i * kLD + lane];
-        uint32_t g1 = (uint32_t)S.e1[i] + dg1, g2 = (uint32_t)S.e2[i] + dg2;
+        const UT dg1 = (UT)(FT)ro(D.diag1)[i * kLD + lane];   // padded: 0 beyond n
+        const UT dg2 = (UT)(FT)ro(D.diag2)[i * kLD + lane];
+        UT g1 = (UT)S.e1[i] + dg1, g2 = (UT)S.e2[i] + dg2;
         if (PV == kPvDense) {
             // the row of b = a added P_aa = d_a
-            g1 -= on ? dg1 : 0u;
-            g2 -= on ? dg2 : 0u;
+            g1 -= on ? dg1 : (UT)0;
+            g2 -= on ? dg2 : (UT)0;
         } else {
             // the Kronecker column of b = a added twice its cost part
             // C_aa = d_a + 2 alpha (both products of the off-diagonal form)
-            g1 -= on ? 2u * (dg1 + ta1) : 0u;
-            g2 -= on ? 2u * (dg2 + ta2) : 0u;
-            const uint32_t cnt = ri + cu - (on ? 2u : 0u);
+            g1 -= on ? (UT)2 * (dg1 + ta1) : (UT)0;
+            g2 -= on ? (UT)2 * (dg2 + ta2) : (UT)0;
+            const UT cnt = (UT)(ri + cu - (on ? 2u : 0u));
             g1 += cnt * ta1;
             g2 += cnt * ta2;
         }
-        acc1 += on ? (int64_t)(int32_t)g1 + (int32_t)dg1 : 0;
-        acc2 += on ? (int64_t)(int32_t)g2 + (int32_t)dg2 : 0;
-        const int32_t s1 = on ? -(int32_t)g1 : (int32_t)g1;
-        const int32_t s2 = on ? -(int32_t)g2 : (int32_t)g2;
-        S.e1[i] = ok ? s1 : (lslot ? INT_MAX : kDead);
-        S.e2[i] = ok ? s2 : (lslot ? INT_MAX : kDead);
+        acc1 += on ? (int64_t)(FT)g1 + (int64_t)(FT)dg1 : 0;
+        acc2 += on ? (int64_t)(FT)g2 + (int64_t)(FT)dg2 : 0;
+        const FT s1 = on ? -(FT)g1 : (FT)g1;
+        const FT s2 = on ? -(FT)g2 : (FT)g2;
+        S.e1[i] = ok ? s1 : (lslot ? Wide<FT>::kMax : Wide<FT>::kDeadV);
+        S.e2[i] = ok ? s2 : (lslot ? Wide<FT>::kMax : Wide<FT>::kDeadV);
     }
     S.E1 = D.q1 + wave_sum64(acc1) / 2;
     S.E2 = D.q2 + wave_sum64(acc2) / 2;
 }
 
 // Continue from archive member p (Algorithm 3, escape by restart).
-template <int NS, int PV>
-__device__ __forceinline__ void restart_from(Desc *Dp, int n, Replica<NS> &S, int r, int p, int lane)
+template <int NS, int PV, class FT>
+__device__ __forceinline__ void restart_from(Desc *Dp, int n, Replica<NS, FT> &S, int r, int p, int lane)
 {
     Desc &D = *cold(Dp);
     const MDA_GLOBAL uint64_t *ax = rw(D.archX) + ((size_t)r * D.s + p) * (size_t)n;
@@ -221,8 +224,8 @@ __device__ __forceinline__ void restart_from(Desc *Dp, int n, Replica<NS> &S, in
 }
 
 // Archive update after a move: Algorithm 4 (explore) or 5 (exploit).
-template <int NS>
-__device__ __forceinline__ void archive_update(Desc *Dp, int n, Replica<NS> &S, int r, uint32_t t, int lane_,
+template <int NS, class FT>
+__device__ __forceinline__ void archive_update(Desc *Dp, int n, Replica<NS, FT> &S, int r, uint32_t t, int lane_,
                                                uint32_t key0, uint32_t key1)
 {
     const int lane = opaque_lane(lane_);
@@ -316,8 +319,8 @@ __device__ __forceinline__ void archive_update(Desc *Dp, int n, Replica<NS> &S, 
 
 // Random start (Algorithm 3): bit (i, u) is bit i of the 64-bit word
 // (o.x, o.y) of Philox block (0, u); fields and energies from scratch.
-template <int NS, int PV>
-__device__ __forceinline__ void init_replica(Desc *Dp, Replica<NS> &S, int r, int lane)
+template <int NS, int PV, class FT>
+__device__ __forceinline__ void init_replica(Desc *Dp, Replica<NS, FT> &S, int r, int lane)
 {
     Desc &D = *cold(Dp);
     const int n = opaque(D.n);
@@ -331,12 +334,12 @@ __device__ __forceinline__ void init_replica(Desc *Dp, Replica<NS> &S, int r, in
 }
 
 // Least combined difference of every group of 8 slots (see Replica::gmin).
-template <int NS, int AM>
-__device__ __forceinline__ void group_minima(Replica<NS> &S)
+template <int NS, int AM, class FT>
+__device__ __forceinline__ void group_minima(Replica<NS, FT> &S)
 {
 #pragma unroll
     for (int g = 0; g < NS; g += 8) {
-        int32_t gm = INT_MAX;
+        FT gm = Wide<FT>::kMax;
 #pragma unroll
         for (int f = 0; f < 8; ++f)
             gm = min(gm, AM == kAmStrict ? max(S.e1[g + f], S.e2[g + f]) : min(S.e1[g + f], S.e2[g + f]));
@@ -346,26 +349,30 @@ __device__ __forceinline__ void group_minima(Replica<NS> &S)
 
 // One annealing step t of replica r whose largest acceptance threshold
 // (T_t * LNT[0]) >> 24 is thrmax.  Returns the flipped bit or -1.
-template <int NS, int PV, int AM, class LP>
-__device__ __forceinline__ int anneal_step(Desc *Dp, const Hot &H, Replica<NS> &S, int r, uint32_t t, int lane_,
-                                           LP lnt, uint32_t thrmax)
+template <int NS, int PV, int AM, class FT, class LP>
+__device__ __forceinline__ int anneal_step(Desc *Dp, const Hot &H, Replica<NS, FT> &S, int r, uint32_t t, int lane_,
+                                           LP lnt, int64_t thrmax)
 {
     constexpr bool strict = AM == kAmStrict;
+    constexpr bool wide = sizeof(FT) == 8;
+    using UT = typename Wide<FT>::U;
     const int lane = lane_;
     const int n = H.n;
     const uint64_t actmask = (n >= 64) ? ~0ull : ((1ull << n) - 1ull);
     const uint32_t ti = table_index(t, H.ntab);
-    // Every real dE is at most 2^31 - 2 (build-time bound), so capping the
-    // offset and the largest threshold at 2^31 - 2 keeps all comparisons exact
-    // while slots and lanes beyond n, which hold INT_MAX, never qualify.
-    const int32_t EoC = (int32_t)(S.Eoff < (int64_t)(INT_MAX - 1) ? S.Eoff : (int64_t)(INT_MAX - 1));
-    const int64_t Xl = (int64_t)EoC + (int64_t)thrmax;
-    const int32_t X = (int32_t)(Xl < (int64_t)(INT_MAX - 1) ? Xl : (int64_t)(INT_MAX - 1));
+    // int32 differences: every real dE is at most 2^31 - 2 (build-time bound),
+    // so capping the offset and the largest threshold at 2^31 - 2 keeps all
+    // comparisons exact while slots and lanes beyond n, which hold INT_MAX,
+    // never qualify.  int64 differences: the offset (at most steps * beta) and
+    // the threshold (below 2^39) stay far below the dead values (2^60 and up).
+    const FT EoC = wide ? (FT)S.Eoff : (FT)(S.Eoff < (int64_t)(INT_MAX - 1) ? S.Eoff : (int64_t)(INT_MAX - 1));
+    const int64_t Xl = (int64_t)EoC + thrmax;
+    const FT X = wide ? (FT)Xl : (FT)(Xl < (int64_t)(INT_MAX - 1) ? Xl : (int64_t)(INT_MAX - 1));
 
     // 1. can any bit be accepted?  The minimum is kept per group of 8 slots so
     // that step 2 passes over groups in which no lane comes within reach.
-    const int32_t *gmin = S.gmin;
-    int32_t mn = INT_MAX;
+    const FT *gmin = S.gmin;
+    FT mn = Wide<FT>::kMax;
 #pragma unroll
     for (int g = 0; g < NS / 8; ++g) mn = min(mn, gmin[g]);
     const uint64_t cand = __ballot(mn <= X) & actmask;
@@ -376,9 +383,10 @@ __device__ __forceinline__ int anneal_step(Desc *Dp, const Hot &H, Replica<NS> &
         const int lane = opaque_lane(lane_);
         // 2. exact acceptance, 8 facilities per random block.  The threshold
         // (T * LNT[k]) >> 24 is formed exactly: with T = Th 2^24 + Tl (T < 2^43,
-        // so Th < 2^19; LNT < 2^20) it equals Th LNT + ((Tl LNT) >> 24).  Each
-        // statistic is at most 2^32 - 4 (two parts below 2^31 - 1), so a
-        // threshold saturated at 2^32 - 2 takes the same decisions.
+        // so Th < 2^19; LNT < 2^20) it equals Th LNT + ((Tl LNT) >> 24).  With
+        // int32 differences each statistic is at most 2^32 - 4 (two parts below
+        // 2^31 - 1), so a threshold saturated at 2^32 - 2 takes the same
+        // decisions; int64 ones compare with the threshold as it is.
         const int64_t T = H.T[ti];
         const uint32_t Th = (uint32_t)((uint64_t)T >> 24), Tl = (uint32_t)T & 0xFFFFFFu;
         uint64_t acc = 0;
@@ -396,7 +404,7 @@ __device__ __forceinline__ int anneal_step(Desc *Dp, const Hot &H, Replica<NS> &
                     const int i = g + f;
                     // the statistic S is 0 exactly when the combined difference is at
                     // most the offset, and above every threshold when it exceeds X
-                    const int32_t v = strict ? max(S.e1[i], S.e2[i]) : min(S.e1[i], S.e2[i]);
+                    const FT v = strict ? max(S.e1[i], S.e2[i]) : min(S.e1[i], S.e2[i]);
                     const bool sure = v <= EoC;
                     const bool near = v <= X;
                     certain |= sure ? (1u << f) : 0u;
@@ -421,15 +429,15 @@ __device__ __forceinline__ int anneal_step(Desc *Dp, const Hot &H, Replica<NS> &
 #pragma unroll
                     for (int f = 0; f < 8; ++f) {
                         const int i = g + f;
-                        // u_k = max(0, dE_k - E_offset) < 2^31 for a real bit, so the
-                        // strict sum stays below 2^32
-                        const uint32_t u1 = (uint32_t)(max(S.e1[i], EoC) - EoC);
-                        const uint32_t u2 = (uint32_t)(max(S.e2[i], EoC) - EoC);
-                        const uint32_t Sx = strict ? (u1 + u2) : (u1 < u2 ? u1 : u2);
+                        // u_k = max(0, dE_k - E_offset) < 2^31 for a real int32 bit, so
+                        // the strict sum stays below 2^32
+                        const UT u1 = (UT)(max(S.e1[i], EoC) - EoC);
+                        const UT u2 = (UT)(max(S.e2[i], EoC) - EoC);
+                        const UT Sx = strict ? (u1 + u2) : (u1 < u2 ? u1 : u2);
                         const uint32_t L = Lv[f] & 0xFFFFFu;
                         const uint64_t low = (uint64_t)Tl * (uint64_t)L;   // 24 x 20 bits
                         const uint64_t t64 = (uint64_t)Th * (uint64_t)L + (low >> 24);
-                        const uint32_t thr = t64 < 0xFFFFFFFEull ? (uint32_t)t64 : 0xFFFFFFFEu;
+                        const UT thr = wide ? (UT)t64 : (UT)(t64 < 0xFFFFFFFEull ? t64 : 0xFFFFFFFEull);
                         certain |= (((maybe >> f) & 1u) && Sx <= thr) ? (1u << f) : 0u;
                     }
                 }
@@ -453,18 +461,18 @@ __device__ __forceinline__ int anneal_step(Desc *Dp, const Hot &H, Replica<NS> &
             const int js = uni(lo);
             k -= (js == 0) ? 0 : wave_sum_small<7>(__popcll(acc & ((1ull << js) - 1ull)));
             const int jl = kth_lane(__ballot((acc >> js) & 1ull), k, lane);
-            int32_t v1 = 0, v2 = 0;
+            FT v1 = 0, v2 = 0;
 #pragma unroll
             for (int i = 0; i < NS; ++i) {
                 v1 = (i == js) ? S.e1[i] : v1;
                 v2 = (i == js) ? S.e2[i] : v2;
             }
-            const int32_t d1 = rl(v1, jl), d2 = rl(v2, jl);
+            const FT d1 = rlf(v1, jl), d2 = rlf(v2, jl);
             // 4. move, 5. archive
             flip<NS, PV>(Dp, n, S, js, jl, d1, d2, lane);
             group_minima<NS, AM>(S);
             S.moves++;
-            archive_update<NS>(Dp, n, S, r, t, lane, H.key0, H.key1);
+            archive_update<NS, FT>(Dp, n, S, r, t, lane, H.key0, H.key1);
             j = js * n + jl;
         }
     }
@@ -484,25 +492,25 @@ __device__ __forceinline__ int anneal_step(Desc *Dp, const Hot &H, Replica<NS> &
 }
 
 // Final state of replica r: x, canonical local fields h_k = sign * dE_k - d_k, scalars.
-template <int NS>
-__device__ __forceinline__ void export_replica(Desc *Dp, const Replica<NS> &S, int r, int lane)
+template <int NS, class FT>
+__device__ __forceinline__ void export_replica(Desc *Dp, const Replica<NS, FT> &S, int r, int lane)
 {
     Desc &D = *cold(Dp);
     const int n = opaque(D.n);
     const int m = D.m;
     rw(D.x)[(size_t)r * 64 + lane] = (lane < n) ? S.xm : 0ull;
     if (lane < n) {
-        MDA_GLOBAL int32_t *h1 = rw(D.h) + (size_t)r * 2 * m;
-        MDA_GLOBAL int32_t *h2 = h1 + m;
+        MDA_GLOBAL int64_t *h1 = rw(D.h) + (size_t)r * 2 * m;
+        MDA_GLOBAL int64_t *h2 = h1 + m;
 #pragma unroll
         for (int i = 0; i < NS; ++i) {
             if (i < n) {
                 const int a = i * n + lane;
                 const bool on = (S.xm >> i) & 1ull;
-                const int32_t g1 = on ? -S.e1[i] : S.e1[i];
-                const int32_t g2 = on ? -S.e2[i] : S.e2[i];
-                h1[a] = g1 - ro(D.diag1)[i * kLD + lane];
-                h2[a] = g2 - ro(D.diag2)[i * kLD + lane];
+                const FT g1 = on ? -S.e1[i] : S.e1[i];
+                const FT g2 = on ? -S.e2[i] : S.e2[i];
+                h1[a] = (int64_t)g1 - ro(D.diag1)[i * kLD + lane];
+                h2[a] = (int64_t)g2 - ro(D.diag2)[i * kLD + lane];
             }
         }
     }
@@ -521,19 +529,27 @@ __device__ __forceinline__ void export_replica(Desc *Dp, const Replica<NS> &S, i
 
 // ---------------------------------------------------------------- kernels
 
+// Largest threshold of table entry k: the saturated 32-bit table for int32
+// differences, the int64 one for int64 differences.
+template <class FT>
+__device__ __forceinline__ int64_t thr_entry(const Hot &H, uint32_t k)
+{
+    return sizeof(FT) == 8 ? H.thrmax64[k] : (int64_t)H.thrmax[k];
+}
+
 // All steps of one replica with its state in registers.
-template <int NS, int PV, int AM>
+template <int NS, int PV, int AM, class FT>
 __device__ __forceinline__ void run_replica(Desc *Dp, int r, int lane, const MDA_LDS int32_t *lnt)
 {
-    Replica<NS> S;
+    Replica<NS, FT> S;
     init_replica<NS, PV>(Dp, S, r, lane);
     group_minima<NS, AM>(S);
     const Hot H = load_hot(Dp);
     // the next step's threshold is loaded one step ahead
-    uint32_t thr = H.thrmax[0];
+    int64_t thr = thr_entry<FT>(H, 0);
     for (uint32_t t = 1; t <= H.steps; ++t) {
         // entry of step t + 1: min(t + 1, ntab) - 1 = min(t, ntab - 1), ntab >= 1
-        const uint32_t thr_next = H.thrmax[(t < H.ntab - 1u) ? t : H.ntab - 1u];
+        const int64_t thr_next = thr_entry<FT>(H, (t < H.ntab - 1u) ? t : H.ntab - 1u);
         anneal_step<NS, PV, AM>(Dp, H, S, r, t, lane, lnt, thr);
         thr = thr_next;
     }
@@ -553,10 +569,12 @@ __device__ __forceinline__ void run_replica(Desc *Dp, int r, int lane, const MDA
 // when a launch has more replicas than one wave per SIMD can hold at once
 // (n = 50 benchmark launch: 2.45 s -> 1.69 s; three waves spill the step's
 // own state and are slower).
-template <int NS, int OCC>
+// F64 = 1: the int64-difference build (one wave per SIMD).
+template <int NS, int OCC, int F64>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(OCC))) k_persistent(const RunDesc *runs, const WorkItem *work, int nwork,
                                                     const int32_t *lnt_)
 {
+    using FT = typename std::conditional<F64 != 0, int64_t, int32_t>::type;
     // the -ln table, read at random by the exact acceptance test, lives in LDS
     __shared__ int32_t lnt_lds[4096];
     for (int k = (int)threadIdx.x; k < 4096; k += (int)blockDim.x) lnt_lds[k] = ((const MDA_GLOBAL int32_t *)lnt_)[k];
@@ -573,7 +591,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(OCC)))
         switch (step_variant(Dp)) {
 #define X(PV, AM)                                        \
     case PV * 2 + AM:                                    \
-        run_replica<NS, PV, AM>(Dp, r, lane, lnt); \
+        run_replica<NS, PV, AM, FT>(Dp, r, lane, lnt); \
         break;
             MDA_STEP_VARIANTS(X)
 #undef X

@@ -20,6 +20,7 @@ LIB_PATH = os.path.join(HERE, "libmda.so")
 MDA_OK, MDA_EINVAL, MDA_EOVERFLOW, MDA_ENOMEM, MDA_EDEVICE, MDA_ERANGE, MDA_EBUSY = 0, -1, -2, -3, -4, -5, -6
 PEN_2MAX, PEN_VL = 0, 1
 NORM_NONE, NORM_AUTO = 0, -1   # normalise: or L in [1, 30] for max|C_k| = 2^L
+FIELDS_AUTO, FIELDS_32, FIELDS_64 = 0, 32, 64   # width of the energy differences
 PATH_AUTO, PATH_DENSE, PATH_KRON = 0, 1, 2
 STRICT, LENIENT = 0, 1
 EXPLORE, EXPLOIT = 0, 1
@@ -38,14 +39,14 @@ class MdaError(RuntimeError):
 
 class BuildOpts(C.Structure):
     _fields_ = [("penalty", C.c_int32), ("path", C.c_int32), ("dense_budget", C.c_int64),
-                ("normalise_log2", C.c_int32), ("reserved", C.c_int32)]
+                ("normalise_log2", C.c_int32), ("fields", C.c_int32)]
 
 
 class QuboInfo(C.Structure):
     _fields_ = [("n", C.c_int32), ("m", C.c_int32), ("path", C.c_int32), ("symmetric", C.c_int32),
                 ("alpha1", C.c_int64), ("alpha2", C.c_int64), ("q1", C.c_int64), ("q2", C.c_int64),
                 ("maxabs_c", C.c_int64), ("device_bytes", C.c_int64), ("normalise_log2", C.c_int32),
-                ("reserved", C.c_int32), ("scale1", C.c_double), ("scale2", C.c_double)]
+                ("fields", C.c_int32), ("scale1", C.c_double), ("scale2", C.c_double)]
 
 
 class Params(C.Structure):
@@ -277,7 +278,8 @@ class Qubo:
     """qubo_build_bqap: the penalised QUBOs Y, Z of one bi-objective QAP instance."""
 
     def __init__(self, F1, F2, D, penalty: int = PEN_2MAX, path: int = PATH_AUTO,
-                 dense_budget: int = 0, stream: Optional[int] = None, normalise: int = NORM_NONE):
+                 dense_budget: int = 0, stream: Optional[int] = None, normalise: int = NORM_NONE,
+                 fields: int = FIELDS_AUTO):
         F1 = np.ascontiguousarray(F1, np.int32)
         F2 = np.ascontiguousarray(F2, np.int32)
         D = np.ascontiguousarray(D, np.int32)
@@ -285,7 +287,7 @@ class Qubo:
         if F1.shape != (n, n) or F2.shape != (n, n) or D.shape != (n, n):
             raise ValueError("F1, F2, D must be n x n")
         self._h = C.c_void_p()
-        opts = BuildOpts(int(penalty), int(path), int(dense_budget), int(normalise), 0)
+        opts = BuildOpts(int(penalty), int(path), int(dense_budget), int(normalise), int(fields))
         s = current_stream_handle() if stream is None else stream
         _check(lib().qubo_build_bqap(n, _ptr(F1), _ptr(F2), _ptr(D), C.byref(opts),
                                      C.c_void_p(s) if s else None, C.byref(self._h)))
@@ -417,8 +419,8 @@ class Run:
     def state(self, replica: int, trace: bool = False) -> dict:
         m = self.qubo.m
         x = np.zeros(m, np.uint8)
-        h1 = np.zeros(m, np.int32)
-        h2 = np.zeros(m, np.int32)
+        h1 = np.zeros(m, np.int64)
+        h2 = np.zeros(m, np.int64)
         tr = np.zeros(int(self.params.steps), np.int32) if trace else None
         st = State(_ptr(x).value, _ptr(h1).value, _ptr(h2).value, 0, 0, 0, 0, 0, 0,
                    _ptr(tr).value if trace else None)
@@ -506,13 +508,13 @@ class Server:
         self._n = {}            # ticket -> n of the submitted instance
 
     def submit(self, F1, F2, D, params: Params, path: int = PATH_AUTO, penalty: int = PEN_2MAX,
-               dense_budget: int = 0, normalise: int = NORM_NONE) -> int:
+               dense_budget: int = 0, normalise: int = NORM_NONE, fields: int = FIELDS_AUTO) -> int:
         F1 = np.ascontiguousarray(F1, np.int32)
         F2 = np.ascontiguousarray(F2, np.int32)
         D = np.ascontiguousarray(D, np.int32)
         n = int(D.shape[0])
         t = C.c_int64()
-        bo = BuildOpts(int(penalty), int(path), int(dense_budget), int(normalise), 0)
+        bo = BuildOpts(int(penalty), int(path), int(dense_budget), int(normalise), int(fields))
         _check(lib().mda_server_submit(self._h, n, _ptr(F1), _ptr(F2), _ptr(D), C.byref(bo), C.byref(params),
                                        C.byref(t)))
         self._n[int(t.value)] = n

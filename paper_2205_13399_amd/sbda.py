@@ -62,7 +62,8 @@ def normalised_qubos(F1, F2, D, normalise: int, weights: Sequence[int] = WEIGHTS
                      path: int = mda.PATH_KRON, stream: Optional[int] = None):
     """The aggregated QUBOs of normalised R and S: L = normalise, or with
     NORM_AUTO the largest L <= 23 for which the normalisation and every
-    aggregated QUBO pass the library's int32 bounds.  Returns (qubos, L)."""
+    aggregated QUBO pass the library's bounds (int64 fields where the int32
+    ones fail).  Returns (qubos, L)."""
     for L in ([normalise] if normalise > 0 else range(23, 0, -1)):
         try:
             q = mda.Qubo(F1, F2, D, penalty=penalty, path=path, stream=stream, normalise=L)

@@ -56,9 +56,11 @@ def test_automatic_target(mda, n, rho, k):
     L = _check(mda, inst, 4, 2000, 12 + n, mda.NORM_AUTO)
     assert 1 <= L <= 23
     if L < 23:
+        # one power more does not fit int32 fields (it runs on int64 ones)
         with pytest.raises(mda.MdaError) as e:
-            mda.Qubo(inst.F1, inst.F2, inst.D, path=2, normalise=L + 1)
+            mda.Qubo(inst.F1, inst.F2, inst.D, path=2, normalise=L + 1, fields=32)
         assert e.value.code == mda.MDA_EOVERFLOW
+        assert mda.Qubo(inst.F1, inst.F2, inst.D, path=2, normalise=L + 1).info().fields == 64
 
 
 def test_unbalanced_objectives_are_equalised(mda):

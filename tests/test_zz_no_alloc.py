@@ -30,7 +30,7 @@ def _noalloc(mda, q, p):
     lay = mda.run_layout(q, p)
     assert 0 < lay.scratch_bytes <= mda.NOALLOC_SCRATCH_BYTES
     dev = torch.device("cuda")
-    spec = dict(x=(lay.n_x, torch.int64), h=(lay.n_h, torch.int32), st=(lay.n_st, torch.int64),
+    spec = dict(x=(lay.n_x, torch.int64), h=(lay.n_h, torch.int64), st=(lay.n_st, torch.int64),
                 arch_e=(lay.n_arch_e, torch.int64), arch_x=(lay.n_arch_x, torch.int64),
                 nd=(lay.n_nd, torch.uint8), trace=(max(1, lay.n_trace), torch.int32))
     bufs = {k: torch.full((cnt,), 0x5A, dtype=dt, device=dev) for k, (cnt, dt) in spec.items()}
