@@ -513,3 +513,293 @@ int orc_mda_replica(const orc_qubo *q, const orc_params *p, int32_t r, orc_repli
     free(dE1); free(dE2); free(acc); free(field);
     return 0;
 }
+
+/* ---------------- K objectives on a generic QUBO (readings G1-G3) ---------------- */
+
+int orc_gbuild(int32_t m, int32_t K, const int32_t *Q, const int64_t *q, orc_gqubo *g)
+{
+    int64_t mm = (int64_t)m * m;
+    memset(g, 0, sizeof(*g));
+    g->m = m;
+    g->K = K;
+    g->P = (int64_t *)malloc((size_t)(K * mm) * sizeof(int64_t));
+    g->q = (int64_t *)malloc((size_t)K * sizeof(int64_t));
+    if (!g->P || !g->q) {
+        orc_gfree(g);
+        return -1;
+    }
+    for (int32_t k = 0; k < K; ++k) {
+        const int32_t *Qk = Q + k * mm;
+        int64_t *Pk = g->P + k * mm;
+        g->q[k] = q ? q[k] : 0;
+        /* the symmetric form of Eq. (cale), reading R2 */
+        for (int32_t a = 0; a < m; ++a) {
+            for (int32_t b = 0; b < m; ++b) {
+                int64_t v = (a == b) ? (int64_t)Qk[(int64_t)a * m + a]
+                                     : (int64_t)Qk[(int64_t)a * m + b] + Qk[(int64_t)b * m + a];
+                Pk[(int64_t)a * m + b] = v;
+                if (a <= b) {
+                    int64_t av = v < 0 ? -v : v;
+                    if (av > g->maxabs_c) g->maxabs_c = av;
+                }
+            }
+        }
+        for (int32_t a = 0; a < m; ++a) {
+            int64_t sum = 0;
+            for (int32_t b = 0; b < m; ++b) {
+                int64_t v = Pk[(int64_t)a * m + b];
+                sum += v < 0 ? -v : v;
+            }
+            if (sum > INT32_LIMIT) g->overflow = 1;
+        }
+    }
+    return 0;
+}
+
+void orc_gfree(orc_gqubo *g)
+{
+    free(g->P);
+    free(g->q);
+    g->P = 0;
+    g->q = 0;
+}
+
+int orc_gdominates(int32_t K, const int64_t *p, const int64_t *q)
+{
+    int equal = 1;
+    for (int32_t k = 0; k < K; ++k) {
+        if (p[k] > q[k]) return 0;
+        if (p[k] != q[k]) equal = 0;
+    }
+    return !equal;
+}
+
+int orc_gaccept(int32_t K, const int64_t *dE, int64_t Eoff, int64_t T, int32_t lnt_k, int32_t mode)
+{
+    /* Reading G1: per objective max(0, D_k); strict sums them (the product of
+     * the K probabilities), lenient takes the least (the largest probability). */
+    int64_t S = 0;
+    for (int32_t k = 0; k < K; ++k) {
+        int64_t d = dE[k] - Eoff;
+        int64_t p = d > 0 ? d : 0;
+        if (mode == ORC_LENIENT) S = (k == 0 || p < S) ? p : S;
+        else S += p;
+    }
+    int64_t thr = (T * (int64_t)lnt_k) >> 24;
+    return S <= thr;
+}
+
+static void garchive_put(orc_garchive *A, int32_t slot, const int64_t *e, const uint8_t *x)
+{
+    memcpy(A->e + (int64_t)slot * A->K, e, (size_t)A->K * sizeof(int64_t));
+    memcpy(A->x + (int64_t)slot * A->m, x, (size_t)A->m);
+}
+
+int32_t orc_garchive_explore(orc_garchive *A, const int64_t *e, const uint8_t *x)
+{
+    /* Algorithm 4: replace the first member that x dominates, else append. */
+    for (int32_t i = 0; i < A->size; ++i) {
+        if (orc_gdominates(A->K, e, A->e + (int64_t)i * A->K)) {
+            garchive_put(A, i, e, x);
+            return i;
+        }
+    }
+    if (A->size < A->cap) {
+        garchive_put(A, A->size, e, x);
+        return A->size++;
+    }
+    return -1;
+}
+
+int32_t orc_garchive_exploit(orc_garchive *A, const int64_t *e, const uint8_t *x, uint32_t w)
+{
+    /* Algorithm 5: only when no member dominates x; a random member of
+     * B = {y : x dominates y} is replaced, else x is appended. */
+    for (int32_t i = 0; i < A->size; ++i)
+        if (orc_gdominates(A->K, A->e + (int64_t)i * A->K, e)) return -1;
+    int32_t nb = 0;
+    for (int32_t i = 0; i < A->size; ++i)
+        if (orc_gdominates(A->K, e, A->e + (int64_t)i * A->K)) ++nb;
+    if (nb > 0) {
+        int32_t pick = (int32_t)mulhi32(w, (uint32_t)nb);
+        for (int32_t i = 0; i < A->size; ++i) {
+            if (orc_gdominates(A->K, e, A->e + (int64_t)i * A->K)) {
+                if (pick == 0) {
+                    garchive_put(A, i, e, x);
+                    return i;
+                }
+                --pick;
+            }
+        }
+    }
+    if (A->size < A->cap) {
+        garchive_put(A, A->size, e, x);
+        return A->size++;
+    }
+    return -1;
+}
+
+/* Eq. (qubo) from the symmetric form: q + sum_{a in x} P_aa + sum_{a<b in x} P_ab. */
+static int64_t genergy(int32_t m, const int64_t *P, int64_t q, const uint8_t *x)
+{
+    int64_t e = q;
+    for (int32_t a = 0; a < m; ++a) {
+        if (!x[a]) continue;
+        e += P[(int64_t)a * m + a];
+        for (int32_t b = a + 1; b < m; ++b)
+            if (x[b]) e += P[(int64_t)a * m + b];
+    }
+    return e;
+}
+
+static void gfields(int32_t m, const int64_t *P, const uint8_t *x, int64_t *h)
+{
+    for (int32_t a = 0; a < m; ++a) {
+        int64_t s = 0;
+        for (int32_t b = 0; b < m; ++b)
+            if (b != a && x[b]) s += P[(int64_t)a * m + b];
+        h[a] = s;
+    }
+}
+
+int orc_gmda_replica(const orc_gqubo *g, const orc_params *p, int32_t r, orc_greplica_out *out)
+{
+    int32_t m = g->m, K = g->K;
+    int32_t s = p->archive_size > 0 ? p->archive_size : m;
+    int64_t mm = (int64_t)m * m;
+    if (p->steps < 0 || p->steps > 0xFFFFFFFFLL || r < 0 || K < 1) return -1;
+    uint32_t key[2] = {(uint32_t)p->seed, (uint32_t)(p->seed >> 32)};
+    int32_t lnt[4096];
+    orc_lnt(lnt);
+
+    uint8_t *x = out->x;
+    int64_t *h = out->h;
+    int64_t *dE = (int64_t *)malloc((size_t)(K * (int64_t)m) * sizeof(int64_t));
+    int64_t *E = (int64_t *)malloc((size_t)K * sizeof(int64_t));
+    int64_t *dEa = (int64_t *)malloc((size_t)K * sizeof(int64_t));
+    uint8_t *acc = (uint8_t *)malloc((size_t)m);
+    uint32_t *field = (uint32_t *)malloc((size_t)m * sizeof(uint32_t));
+    orc_garchive A;
+    A.size = 0;
+    A.cap = s;
+    A.m = m;
+    A.K = K;
+    A.e = (int64_t *)malloc((size_t)s * (size_t)K * sizeof(int64_t));
+    A.x = out->arch_x;
+    if (!dE || !E || !dEa || !acc || !field || !A.e) {
+        free(dE); free(E); free(dEa); free(acc); free(field); free(A.e);
+        return -3;
+    }
+
+    /* Algorithm 3 starts from a random binary solution (reading G3). */
+    for (int32_t a = 0; a < m; ++a) {
+        uint32_t ctr[4] = {(uint32_t)(a >> 7), 0u, (uint32_t)r, ORC_TAG_INIT};
+        uint32_t o[4];
+        orc_philox4x32_10(ctr, key, o);
+        x[a] = (uint8_t)((o[(a >> 5) & 3] >> (a & 31)) & 1u);
+    }
+    for (int32_t k = 0; k < K; ++k) {
+        gfields(m, g->P + k * mm, x, h + (int64_t)k * m);
+        E[k] = genergy(m, g->P + k * mm, g->q[k], x);
+    }
+    int64_t Eoff = 0, moves = 0;
+
+    double delta = p->delta0;
+    for (int64_t t = 1; t <= p->steps; ++t) {
+        /* Algorithm 3: cooling at the top of each iteration, unless the
+         * schedule is given as data. */
+        int64_t T;
+        if (p->temp_table) {
+            T = p->temp_table[t - 1];
+        } else {
+            if (delta > p->deltaf) delta = delta * (1.0 - p->xi);
+            T = (int64_t)floor(delta * 256.0);
+        }
+
+        /* Eq. (cale) for every bit and objective. */
+        for (int32_t k = 0; k < K; ++k) {
+            const int64_t *Pk = g->P + k * mm;
+            for (int32_t a = 0; a < m; ++a) {
+                int64_t sgn = 1 - 2 * (int64_t)x[a];
+                dE[(int64_t)k * m + a] = sgn * (Pk[(int64_t)a * m + a] + h[(int64_t)k * m + a]);
+            }
+        }
+
+        /* One 12-bit index per bit (reading G3). */
+        for (int32_t a = 0; a < m; ++a) {
+            uint32_t ctr[4] = {(uint32_t)(a >> 3), (uint32_t)t, (uint32_t)r, ORC_TAG_ACC};
+            uint32_t o[4];
+            orc_philox4x32_10(ctr, key, o);
+            int32_t f = a & 7;
+            field[a] = (o[f >> 1] >> (16 * (f & 1) + 4)) & 0xFFFu;
+        }
+
+        /* Parallel acceptance test of every bit (reading G1). */
+        int64_t c = 0;
+        for (int32_t a = 0; a < m; ++a) {
+            for (int32_t k = 0; k < K; ++k) dEa[k] = dE[(int64_t)k * m + a];
+            acc[a] = (uint8_t)orc_gaccept(K, dEa, Eoff, T, lnt[field[a]], p->accept);
+            c += acc[a];
+        }
+
+        if (c > 0) {
+            /* Uniform choice among the accepted flips, move, archive. */
+            uint32_t ctr[4] = {0u, (uint32_t)t, (uint32_t)r, ORC_TAG_SEL};
+            uint32_t o[4];
+            orc_philox4x32_10(ctr, key, o);
+            int64_t kk = mulhi32(o[0], (uint32_t)c);
+            int32_t j = -1;
+            for (int32_t a = 0; a < m; ++a) {
+                if (!acc[a]) continue;
+                if (kk == 0) { j = a; break; }
+                --kk;
+            }
+            int64_t sg = x[j] ? -1 : 1;
+            for (int32_t k = 0; k < K; ++k) {
+                const int64_t *Pk = g->P + k * mm;
+                E[k] += dE[(int64_t)k * m + j];
+                for (int32_t a = 0; a < m; ++a) {
+                    if (a == j) continue;
+                    h[(int64_t)k * m + a] += sg * Pk[(int64_t)a * m + j];
+                }
+            }
+            x[j] ^= 1u;
+            Eoff = 0;   /* Algorithm 1: the offset is cleared after a move */
+            ++moves;
+            if (p->archive == ORC_EXPLOIT) {
+                uint32_t ca[4] = {0u, (uint32_t)t, (uint32_t)r, ORC_TAG_ARC};
+                uint32_t oa[4];
+                orc_philox4x32_10(ca, key, oa);
+                orc_garchive_exploit(&A, E, x, oa[0]);
+            } else {
+                orc_garchive_explore(&A, E, x);
+            }
+            if (out->trace) out->trace[t - 1] = j;
+        } else {
+            if (out->trace) out->trace[t - 1] = -1;
+            if (p->escape == ORC_ESC_OFFSET) {
+                Eoff += p->beta;   /* Algorithm 1: raise the offset */
+            } else if (A.size > 0) {
+                /* Algorithm 3 (escape): continue from a random archive member. */
+                uint32_t ca[4] = {0u, (uint32_t)t, (uint32_t)r, ORC_TAG_ARC};
+                uint32_t oa[4];
+                orc_philox4x32_10(ca, key, oa);
+                int32_t pick = (int32_t)mulhi32(oa[1], (uint32_t)A.size);
+                memcpy(x, A.x + (int64_t)pick * m, (size_t)m);
+                for (int32_t k = 0; k < K; ++k) {
+                    gfields(m, g->P + k * mm, x, h + (int64_t)k * m);
+                    E[k] = genergy(m, g->P + k * mm, g->q[k], x);
+                }
+            }
+        }
+    }
+
+    for (int32_t k = 0; k < K; ++k) out->state[k] = E[k];
+    out->state[K] = Eoff;
+    out->state[K + 1] = moves;
+    *out->arch_size = A.size;
+    memcpy(out->arch_e, A.e, (size_t)A.size * (size_t)K * sizeof(int64_t));
+    free(A.e);
+    free(dE); free(E); free(dEa); free(acc); free(field);
+    return 0;
+}

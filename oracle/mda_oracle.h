@@ -164,6 +164,67 @@ typedef struct {
 /* Runs replica r of one MDA run. Returns 0, or a negative value on bad input. */
 int orc_mda_replica(const orc_qubo *q, const orc_params *p, int32_t r, orc_replica_out *out);
 
+/* ---------------- K objectives on a generic QUBO ---------------- */
+/*
+ * The extension to more than two objectives named as future work in the
+ * paper's Conclusion, on any QUBO (Eq. qubo), not only the bQAP's.  K
+ * objectives x^T Q_k x + q_k (k = 1..K, K >= 1) over m bits, every other step
+ * of Algorithm 3 as above, with readings:
+ *  G1 acceptance with K objectives: strict S = sum_k max(0, D_k) (the product
+ *     of the K probabilities of Eq. pacceptms), lenient S = min_k max(0, D_k)
+ *     (the largest of them, Eq. pacceptml), D_k = dE_k - E_offset; accept iff
+ *     S <= (T * LNT[idx]) >> 24 as in R3;
+ *  G2 dominance: p dominates q when p_k <= q_k for every k and p != q
+ *     (Section 3.3 with K objectives);
+ *  G3 random numbers by bit index a, eight consecutive bits per block:
+ *     start bit a = bit (a & 31) of word ((a >> 5) & 3) of the block
+ *     (a >> 7, 0, r, INIT); acceptance index of bit a = bits 4..15 of the
+ *     16-bit half (a & 1) of word (a & 7) >> 1 of the block (a >> 3, t, r, ACC);
+ *     the choice, exploit and restart words as in R6 and Algorithm 5.
+ */
+typedef struct {
+    int32_t m, K;
+    int64_t *P;             /* K*m*m: P_k[a][b] = Q_k[a][b] + Q_k[b][a] (a != b), P_k[a][a] = Q_k[a][a] */
+    int64_t *q;             /* K constants */
+    int64_t maxabs_c;       /* max over k and a <= b of |C_k[a][b]|, C the upper-triangular form */
+    int32_t overflow;       /* 1 when some row bound |P_aa| + sum_b |P_ab| exceeds 2^31 - 1 */
+} orc_gqubo;
+
+/* Q: K*m*m int32 row-major (Q_k[a][b] at (k*m + a)*m + b); q: K constants or
+ * NULL for zeros.  Returns 0, or -1 on allocation failure. */
+int orc_gbuild(int32_t m, int32_t K, const int32_t *Q, const int64_t *q, orc_gqubo *g);
+void orc_gfree(orc_gqubo *g);
+
+/* Reading G2. */
+int orc_gdominates(int32_t K, const int64_t *p, const int64_t *q);
+
+/* Reading G1 on the K differences dE. */
+int orc_gaccept(int32_t K, const int64_t *dE, int64_t Eoff, int64_t T, int32_t lnt_k, int32_t mode);
+
+typedef struct {
+    int32_t size, cap, m, K;
+    int64_t *e;         /* cap*K energies */
+    uint8_t *x;         /* cap*m bits */
+} orc_garchive;
+
+/* Algorithms 4 and 5 with K-way dominance; same returns as the K = 2 forms. */
+int32_t orc_garchive_explore(orc_garchive *A, const int64_t *e, const uint8_t *x);
+int32_t orc_garchive_exploit(orc_garchive *A, const int64_t *e, const uint8_t *x, uint32_t w);
+
+typedef struct {
+    uint8_t *x;          /* m */
+    int64_t *h;          /* K*m local fields h_k[a] = sum_{b != a} P_k[a][b] x_b */
+    int64_t *state;      /* K + 2: E_1..E_K, E_offset, number of moves */
+    int32_t *arch_size;  /* 1 */
+    int64_t *arch_e;     /* archive_size * K */
+    uint8_t *arch_x;     /* archive_size * m */
+    int32_t *trace;      /* steps entries (flipped bit or -1), may be NULL */
+} orc_greplica_out;
+
+/* Replica r of the K-objective MDA (Algorithm 3, readings G1-G3).  Returns 0,
+ * or a negative value on bad input. */
+int orc_gmda_replica(const orc_gqubo *g, const orc_params *p, int32_t r, orc_greplica_out *out);
+
 #ifdef __cplusplus
 }
 #endif

@@ -18,6 +18,7 @@ __all__ = [
     "philox", "lnt", "temperature", "accept", "dominates", "Archive", "Qubo", "run_replica",
     "default_schedule", "STRICT", "LENIENT", "EXPLORE", "EXPLOIT", "ESC_OFFSET",
     "ESC_ARCHIVE", "PEN_2MAX", "PEN_VL", "nondominated",
+    "GQubo", "run_greplica", "gaccept", "gdominates", "GArchive", "gdefault_schedule", "gnondominated",
 ]
 
 STRICT, LENIENT = 0, 1
@@ -75,6 +76,21 @@ class _ReplicaOut(C.Structure):
     ]
 
 
+class _GQubo(C.Structure):
+    _fields_ = [("m", C.c_int32), ("K", C.c_int32), ("P", C.c_void_p), ("q", C.c_void_p),
+                ("maxabs_c", C.c_int64), ("overflow", C.c_int32)]
+
+
+class _GArchive(C.Structure):
+    _fields_ = [("size", C.c_int32), ("cap", C.c_int32), ("m", C.c_int32), ("K", C.c_int32),
+                ("e", C.c_void_p), ("x", C.c_void_p)]
+
+
+class _GReplicaOut(C.Structure):
+    _fields_ = [("x", C.c_void_p), ("h", C.c_void_p), ("state", C.c_void_p), ("arch_size", C.c_void_p),
+                ("arch_e", C.c_void_p), ("arch_x", C.c_void_p), ("trace", C.c_void_p)]
+
+
 class _Archive(C.Structure):
     _fields_ = [("size", C.c_int32), ("cap", C.c_int32), ("m", C.c_int32),
                 ("e1", C.c_void_p), ("e2", C.c_void_p), ("x", C.c_void_p)]
@@ -128,6 +144,21 @@ def lib():
         L.orc_mda_replica.restype = C.c_int
         L.orc_mda_replica.argtypes = [C.POINTER(_Qubo), C.POINTER(_Params), C.c_int32,
                                       C.POINTER(_ReplicaOut)]
+        L.orc_gbuild.restype = C.c_int
+        L.orc_gbuild.argtypes = [C.c_int32, C.c_int32, _i32p, C.c_void_p, C.POINTER(_GQubo)]
+        L.orc_gfree.restype = None
+        L.orc_gfree.argtypes = [C.POINTER(_GQubo)]
+        L.orc_gdominates.restype = C.c_int
+        L.orc_gdominates.argtypes = [C.c_int32, _i64p, _i64p]
+        L.orc_gaccept.restype = C.c_int
+        L.orc_gaccept.argtypes = [C.c_int32, _i64p, C.c_int64, C.c_int64, C.c_int32, C.c_int32]
+        L.orc_garchive_explore.restype = C.c_int32
+        L.orc_garchive_explore.argtypes = [C.POINTER(_GArchive), _i64p, _u8p]
+        L.orc_garchive_exploit.restype = C.c_int32
+        L.orc_garchive_exploit.argtypes = [C.POINTER(_GArchive), _i64p, _u8p, C.c_uint32]
+        L.orc_gmda_replica.restype = C.c_int
+        L.orc_gmda_replica.argtypes = [C.POINTER(_GQubo), C.POINTER(_Params), C.c_int32,
+                                       C.POINTER(_GReplicaOut)]
         _lib = L
     return _lib
 
@@ -370,5 +401,124 @@ def nondominated(e1, e2):
                 dominated = True
                 break
         if not dominated:
+            keep.append(i)
+    return keep
+
+
+# ---------------------------------------------------------------- K objectives on a generic QUBO
+
+class GQubo:
+    """K objectives x^T Q_k x + q_k over m bits (readings G1-G3 of the C header)."""
+
+    def __init__(self, Q, q=None):
+        Q = np.ascontiguousarray(Q, np.int32)
+        if Q.ndim != 3 or Q.shape[1] != Q.shape[2]:
+            raise ValueError("Q must be K x m x m")
+        self.K, self.m = int(Q.shape[0]), int(Q.shape[1])
+        self.Q = Q
+        self.q0 = np.zeros(self.K, np.int64) if q is None else np.ascontiguousarray(q, np.int64)
+        self._g = _GQubo()
+        rc = lib().orc_gbuild(self.m, self.K, Q, self.q0.ctypes.data, C.byref(self._g))
+        if rc != 0:
+            raise MemoryError("oracle generic QUBO build failed")
+
+    def __del__(self):
+        try:
+            lib().orc_gfree(C.byref(self._g))
+        except Exception:
+            pass
+
+    @property
+    def maxabs_c(self):
+        return int(self._g.maxabs_c)
+
+    @property
+    def overflow(self):
+        return bool(self._g.overflow)
+
+    def P(self, k: int) -> np.ndarray:
+        """Copy of the symmetric form P_k (k = 0..K-1)."""
+        m = self.m
+        buf = (C.c_int64 * (self.K * m * m)).from_address(self._g.P)
+        return np.frombuffer(buf, dtype=np.int64).reshape(self.K, m, m)[k].copy()
+
+
+def gdefault_schedule(maxabs_c: int, steps: int):
+    """Table (param) scaled by max|C| / 2^23, as for the bQAP."""
+    return default_schedule(maxabs_c, steps)
+
+
+def gdominates(p, q) -> bool:
+    p = np.ascontiguousarray(p, np.int64)
+    q = np.ascontiguousarray(q, np.int64)
+    return bool(lib().orc_gdominates(len(p), p, q))
+
+
+def gaccept(dE, Eoff, T, lnt_k, mode=STRICT) -> bool:
+    dE = np.ascontiguousarray(dE, np.int64)
+    return bool(lib().orc_gaccept(len(dE), dE, int(Eoff), int(T), int(lnt_k), int(mode)))
+
+
+class GArchive:
+    """A fixed-capacity K-objective archive driven through the oracle's rules."""
+
+    def __init__(self, cap: int, m: int, K: int):
+        self.e = np.zeros((cap, K), np.int64)
+        self.x = np.zeros((cap, m), np.uint8)
+        self.K = K
+        self._s = _GArchive(0, cap, m, K, self.e.ctypes.data, self.x.ctypes.data)
+
+    @property
+    def size(self) -> int:
+        return int(self._s.size)
+
+    def explore(self, e, x) -> int:
+        return int(lib().orc_garchive_explore(C.byref(self._s), np.ascontiguousarray(e, np.int64), _u8(x)))
+
+    def exploit(self, e, x, w) -> int:
+        return int(lib().orc_garchive_exploit(C.byref(self._s), np.ascontiguousarray(e, np.int64), _u8(x),
+                                              int(w) & 0xFFFFFFFF))
+
+    def entries(self):
+        return [tuple(int(v) for v in self.e[i]) for i in range(self.size)]
+
+
+def run_greplica(g: GQubo, r: int, steps: int, delta0: float, deltaf: float, xi: float, beta: int, seed: int,
+                 accept: int = STRICT, archive: int = EXPLORE, escape: int = ESC_OFFSET, archive_size: int = 0,
+                 trace: bool = False, temp_table=None) -> dict:
+    """Replica r of the K-objective MDA; returns its final state and raw archive."""
+    m, K = g.m, g.K
+    s = archive_size if archive_size > 0 else m
+    x = np.zeros(m, np.uint8)
+    h = np.zeros((K, m), np.int64)
+    state = np.zeros(K + 2, np.int64)
+    asz = np.zeros(1, np.int32)
+    ae = np.zeros((s, K), np.int64)
+    ax = np.zeros((s, m), np.uint8)
+    tr = np.zeros(int(steps), np.int32) if trace else None
+    tt = None
+    if temp_table is not None:
+        tt = np.ascontiguousarray(temp_table, np.int64)
+    out = _GReplicaOut(x.ctypes.data, h.ctypes.data, state.ctypes.data, asz.ctypes.data, ae.ctypes.data,
+                       ax.ctypes.data, tr.ctypes.data if trace else None)
+    p = _Params(int(steps), float(delta0), float(deltaf), float(xi), int(beta), accept, archive,
+                escape, int(archive_size), int(seed) & 0xFFFFFFFFFFFFFFFF, tt.ctypes.data if tt is not None else None)
+    rc = lib().orc_gmda_replica(C.byref(g._g), C.byref(p), int(r), C.byref(out))
+    if rc != 0:
+        raise ValueError("oracle run failed: %d" % rc)
+    k = int(asz[0])
+    res = dict(x=x, h=h, E=[int(v) for v in state[:K]], Eoff=int(state[K]), moves=int(state[K + 1]),
+               arch_size=k, arch_e=ae[:k].copy(), arch_x=ax[:k].copy())
+    if trace:
+        res["trace"] = tr
+    return res
+
+
+def gnondominated(E):
+    """Indices of rows of E (N x K) that no other row dominates, ascending."""
+    E = np.asarray(E, np.int64)
+    keep = []
+    for i in range(len(E)):
+        if not any(j != i and gdominates(E[j], E[i]) for j in range(len(E))):
             keep.append(i)
     return keep
