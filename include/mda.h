@@ -399,6 +399,71 @@ typedef struct {
  * schedule that keeps cooling), MDA_EOVERFLOW, MDA_EDEVICE. */
 int da_run_noalloc(const mda_qubo *q, const mda_params *p, const mda_run_buffers *b);
 
+/* ---------------- K objectives on a generic QUBO ----------------
+ *
+ * The extension beyond two objectives that the paper's Conclusion names, on any
+ * QUBO (Eq. qubo): K objectives E_k(x) = x^T Q_k x + q_k over m bits, the MDA of
+ * Algorithm 3 with the strict rule (Eq. pacceptms) summing max(0, dE_k -
+ * E_offset) over the K objectives and the lenient rule (Eq. pacceptml) taking
+ * their least, and K-way dominance (Section 3.3) in the archive updates
+ * (Algorithms 4 and 5).  Bits carry no (facility, location) structure: the
+ * random numbers go by bit index, eight consecutive bits per Philox block (bit
+ * a: start bit (a & 31) of word (a >> 5) & 3 of block (a >> 7, 0, replica,
+ * INIT); acceptance index bits 4..15 of half (a & 1) of word (a & 7) >> 1 of
+ * block (a >> 3, step, replica, ACC)).  Dense rows of the symmetric form only.
+ */
+typedef struct mda_gqubo mda_gqubo;   /* K generic objective QUBOs on the device */
+typedef struct mda_grun mda_grun;     /* one K-objective run: replica state and archives */
+
+/*
+ * Builds the K objectives.
+ *   m      bits, 2 <= m <= 4096 / K rounded down to 1024, 2048 or 4096
+ *          (K = 1: 4096, K = 2: 2048, K = 3 or 4: 1024): a replica's K m
+ *          differences stay in one wave's registers
+ *   K      objectives, 1 <= K <= 4
+ *   Q      host int32, K * m * m, row-major: Q_k[a][b] at (k * m + a) * m + b;
+ *          any matrix (only Q + Q^T off the diagonal and Q_aa on it matter)
+ *   q      host int64 constants q_k, K of them, or NULL for zeros
+ *   stream hipStream_t for the uploads (NULL = default stream)
+ * Errors: MDA_EINVAL (sizes, NULL arrays), MDA_EOVERFLOW (some bit's
+ * |P_aa| + sum_b |P_ab| beyond 2^31 - 2, P = the symmetric form), MDA_ENOMEM,
+ * MDA_EDEVICE.
+ */
+int gqubo_build(int32_t m, int32_t K, const int32_t *Q, const int64_t *q, void *stream, mda_gqubo **out);
+/* Sizes and the largest |C_k[a][b]| over k and a <= b (C the upper-triangular
+ * form; the default schedule scales with it). */
+int gqubo_info(const mda_gqubo *g, int32_t *m, int32_t *K, int64_t *maxabs_c);
+void gqubo_free(mda_gqubo *g);
+
+/* Runs p->replicas replicas, one wave each (asynchronous on p->stream; the
+ * run holds a reference to g, which may be freed before the run).  The fields
+ * of p are those of da_run, with variant MDA_VARIANT_AUTO or
+ * MDA_VARIANT_PERSISTENT, graph 0 and waves_per_replica 0 or 1.  Errors: as
+ * da_run, and MDA_EINVAL for the unsupported fields. */
+int gda_run(const mda_gqubo *g, const mda_params *p, mda_grun **out);
+/* p as resolved (steps, schedule, beta, archive size). */
+int gda_params_get(const mda_grun *r, mda_params *out);
+/* Device time of the annealing kernel (synchronises). */
+int gda_kernel_ms(mda_grun *r, double *ms);
+/* Final state of one replica (synchronises): x (m bytes), h (K * m fields,
+ * objective-major), E (K energies), offset, moves, trace (resolved steps,
+ * needs trace_replicas); each may be NULL. */
+int gda_state_get(mda_grun *r, int32_t replica, uint8_t *x, int64_t *h, int64_t *E, int64_t *e_offset,
+                  int64_t *moves, int32_t *trace);
+/*
+ * Archives (synchronises).  replica >= 0 with raw = 1: that replica's archive
+ * in slot order; raw = 0: the non-dominated entries of that replica's archive
+ * (replica >= 0) or of the union over all replicas (replica = -1), equal
+ * energy vectors reduced to the lowest (replica, slot), sorted
+ * lexicographically by (E_1, ..., E_K, replica, slot).  e receives cap * K
+ * energies; rep, slot and xbits (cap * ceil(m / 32) words, bit a of word
+ * a / 32) may be NULL; e == NULL is a size query; *count gets the entries.
+ * Errors: MDA_EINVAL, MDA_ERANGE (cap too small), MDA_EDEVICE.
+ */
+int garchive_get(mda_grun *r, int32_t replica, int32_t raw, int64_t cap, int64_t *e, int32_t *rep, int32_t *slot,
+                 uint32_t *xbits, int64_t *count);
+void gda_run_free(mda_grun *r);
+
 /* Debug/verification exports: the library's own host tables.
  * mda_temperature_table errors: MDA_EINVAL (NULL T, steps < 1), MDA_EOVERFLOW
  * (delta0 above 2^35, the largest starting temperature a run accepts). */

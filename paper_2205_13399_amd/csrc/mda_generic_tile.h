@@ -1,0 +1,47 @@
+// mda_generic_tile.h -- launchers of the K-objective kernels for one K
+// (MDA_GK), every slot count S with K * S <= 64 (register resident); included by the translation
+// unit of that K so that the K compile in parallel.
+#pragma once
+
+#include "mda_generic.h"
+
+namespace mda {
+
+#define MDA_GCAT2(a, b) a##b
+#define MDA_GCAT(a, b) MDA_GCAT2(a, b)
+
+hipError_t MDA_GCAT(launch_generic_k, MDA_GK)(int S, const GRunDesc *run, const int32_t *lnt, int grid, int block,
+                                             hipStream_t stream, int R)
+{
+    const int nd_grid = (R * 64 + 255) / 256;
+    switch (S) {
+#define GX(SS)                                                                                               \
+    case SS:                                                                                                 \
+        if (MDA_GK * SS > 64) return hipErrorInvalidValue;                                                  \
+        hipLaunchKernelGGL((k_generic<MDA_GK, (MDA_GK * SS <= 64 ? SS : 8)>), dim3(grid), dim3(block), 0,   \
+                           stream, run, lnt);                                                                \
+        break;
+        GX(8) GX(16) GX(32) GX(64)
+#undef GX
+    default:
+        return hipErrorInvalidValue;
+    }
+    hipLaunchKernelGGL((k_gnondominated<MDA_GK>), dim3(nd_grid), dim3(256), 0, stream, run);
+    return hipGetLastError();
+}
+
+hipError_t MDA_GCAT(generic_occupancy_k, MDA_GK)(int S, int block, int *blocks_per_cu)
+{
+    switch (S) {
+#define GX(SS)                                                                                                 \
+    case SS:                                                                                                   \
+        return hipOccupancyMaxActiveBlocksPerMultiprocessor(                                                   \
+            blocks_per_cu, k_generic<MDA_GK, (MDA_GK * SS <= 64 ? SS : 8)>, block, 0);
+        GX(8) GX(16) GX(32) GX(64)
+#undef GX
+    default:
+        return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace mda

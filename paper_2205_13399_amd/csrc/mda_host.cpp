@@ -17,6 +17,7 @@
 
 #include "mda.h"
 #include "mda_desc.h"
+#include "mda_host_common.h"
 #include "mda_internal.h"
 
 namespace mda {
@@ -46,7 +47,9 @@ using namespace mda;
 
 static thread_local std::string g_err;
 
-static int fail(int code, const char *fmt, ...)
+namespace mda {
+
+int fail(int code, const char *fmt, ...)
 {
     char buf[512];
     va_list ap;
@@ -57,12 +60,7 @@ static int fail(int code, const char *fmt, ...)
     return code;
 }
 
-#define HIP_TRY(expr)                                                                 \
-    do {                                                                              \
-        hipError_t e_ = (expr);                                                       \
-        if (e_ != hipSuccess)                                                         \
-            return fail(MDA_EDEVICE, "%s failed: %s", #expr, hipGetErrorString(e_)); \
-    } while (0)
+}  // namespace mda
 
 extern "C" const char *mda_last_error(void)
 {
@@ -84,75 +82,53 @@ extern "C" int mda_set_allocator(mda_alloc_fn alloc, mda_free_fn release, void *
     return MDA_OK;
 }
 
-namespace {
-
 // Allocation mode of the calling thread: the serving engine's scheduler
 // allocates stream-ordered (hipMallocAsync), so that releasing one request's
 // memory never waits for the other requests' work on the device.
 static thread_local bool tl_stream_ordered = false;
 
-struct DevBuf {
+namespace mda {
+
+void *DevPool::alloc_bytes(size_t bytes, hipStream_t stream)
+{
+    if (bytes == 0) bytes = 256;
+    bytes = (bytes + 255) & ~(size_t)255;
     void *p = nullptr;
-    size_t bytes = 0;
-    hipStream_t stream = nullptr;
-    mda_free_fn release = nullptr;
-    void *ctx = nullptr;
-    bool async = false;
-};
-
-struct DevPool {
-    std::vector<DevBuf> bufs;
-    int64_t total = 0;
-
-    template <class T>
-    T *alloc(size_t count, hipStream_t stream)
-    {
-        size_t bytes = count * sizeof(T);
-        if (bytes == 0) bytes = 256;
-        bytes = (bytes + 255) & ~(size_t)255;
-        void *p = nullptr;
-        DevBuf b;
-        if (tl_stream_ordered) {
-            if (hipMallocAsync(&p, bytes, stream) != hipSuccess) p = nullptr;
-            b.async = true;
-        } else if (g_alloc) {
-            p = g_alloc(bytes, (void *)stream, g_ctx);
-            b.release = g_release;
-            b.ctx = g_ctx;
-        } else if (hipMalloc(&p, bytes) != hipSuccess) {
-            p = nullptr;
-        }
-        if (!p) return nullptr;
-        b.p = p;
-        b.bytes = bytes;
-        b.stream = stream;
-        bufs.push_back(b);
-        total += (int64_t)bytes;
-        return static_cast<T *>(p);
+    DevBuf b;
+    if (tl_stream_ordered) {
+        if (hipMallocAsync(&p, bytes, stream) != hipSuccess) p = nullptr;
+        b.async = true;
+    } else if (g_alloc) {
+        p = g_alloc(bytes, (void *)stream, g_ctx);
+        b.release = g_release;
+        b.ctx = g_ctx;
+    } else if (hipMalloc(&p, bytes) != hipSuccess) {
+        p = nullptr;
     }
+    if (!p) return nullptr;
+    b.p = p;
+    b.bytes = bytes;
+    b.stream = stream;
+    bufs.push_back(b);
+    total += (int64_t)bytes;
+    return p;
+}
 
-    void release_all()
-    {
-        for (auto &b : bufs) {
-            if (b.async) (void)hipFreeAsync(b.p, b.stream);
-            else if (b.release) b.release(b.p, b.bytes, (void *)b.stream, b.ctx);
-            else (void)hipFree(b.p);
-        }
-        bufs.clear();
-        total = 0;
+void DevPool::release_all()
+{
+    for (auto &b : bufs) {
+        if (b.async) (void)hipFreeAsync(b.p, b.stream);
+        else if (b.release) b.release(b.p, b.bytes, (void *)b.stream, b.ctx);
+        else (void)hipFree(b.p);
     }
-};
+    bufs.clear();
+    total = 0;
+}
 
-// Quantised -ln(u): LNT[k] = round(-ln((k + 1/2) / 4096) * 2^16).
 void threshold_table(int32_t *lnt)
 {
     for (int k = 0; k < 4096; ++k) lnt[k] = (int32_t)std::llround(-std::log((k + 0.5) / 4096.0) * 65536.0);
 }
-
-// Geometric cooling evaluated at the top of every step; T_t = floor(256 delta_t).
-// Returns the number of entries until the temperature stops changing.
-// Largest scaled temperature T = floor(256 delta) a run accepts.
-constexpr double kMaxTemp = (double)((int64_t)1 << 43);
 
 int64_t temperature_table(double delta0, double deltaf, double xi, int64_t steps, std::vector<int64_t> &T)
 {
@@ -170,7 +146,7 @@ int64_t temperature_table(double delta0, double deltaf, double xi, int64_t steps
     return (int64_t)T.size();
 }
 
-}  // namespace
+}  // namespace mda
 
 extern "C" int mda_threshold_table(int32_t *lnt4096)
 {

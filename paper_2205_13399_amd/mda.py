@@ -185,6 +185,24 @@ def lib():
     L.mda_server_stats.restype = C.c_int
     L.mda_server_destroy.argtypes = [vp]
     L.mda_server_destroy.restype = None
+    L.gqubo_build.argtypes = [i32, i32, vp, vp, vp, C.POINTER(vp)]
+    L.gqubo_build.restype = C.c_int
+    L.gqubo_info.argtypes = [vp, C.POINTER(i32), C.POINTER(i32), C.POINTER(i64)]
+    L.gqubo_info.restype = C.c_int
+    L.gqubo_free.argtypes = [vp]
+    L.gqubo_free.restype = None
+    L.gda_run.argtypes = [vp, C.POINTER(Params), C.POINTER(vp)]
+    L.gda_run.restype = C.c_int
+    L.gda_params_get.argtypes = [vp, C.POINTER(Params)]
+    L.gda_params_get.restype = C.c_int
+    L.gda_kernel_ms.argtypes = [vp, C.POINTER(C.c_double)]
+    L.gda_kernel_ms.restype = C.c_int
+    L.gda_state_get.argtypes = [vp, i32, vp, vp, vp, vp, vp, vp]
+    L.gda_state_get.restype = C.c_int
+    L.garchive_get.argtypes = [vp, i32, i32, i64, vp, vp, vp, vp, C.POINTER(i64)]
+    L.garchive_get.restype = C.c_int
+    L.gda_run_free.argtypes = [vp]
+    L.gda_run_free.restype = None
     _lib = L
     return L
 
@@ -193,7 +211,8 @@ EXPORTED = ["qubo_build_bqap", "qubo_flows", "qubo_info", "qubo_free", "mda_para
             "da_sync", "da_elapsed_ms", "da_kernel_ms", "archive_get", "da_state_get", "da_params_get", "da_stats", "da_run_free",
             "mda_set_allocator", "mda_last_error", "mda_threshold_table", "mda_temperature_table",
             "mda_autotune", "mda_footprint", "da_run_layout", "da_run_noalloc", "mda_server_create", "mda_server_submit", "mda_server_wait", "mda_server_stats",
-            "mda_server_destroy"]
+            "mda_server_destroy", "gqubo_build", "gqubo_info", "gqubo_free", "gda_run", "gda_params_get", "gda_kernel_ms",
+            "gda_state_get", "garchive_get", "gda_run_free"]
 
 
 def _check(rc: int):
@@ -464,6 +483,117 @@ def da_run_batch(qs: Sequence[Qubo], params: Sequence[Params]) -> list:
     outs = (C.c_void_p * k)()
     _check(lib().da_run_batch(harr, parr, k, outs))
     return [Run(C.c_void_p(outs[i]), qs[i]) for i in range(k)]
+
+
+class GQubo:
+    """gqubo_build: K objectives x^T Q_k x + q_k on m bits (a generic QUBO)."""
+
+    def __init__(self, Q, q=None, stream: Optional[int] = None):
+        Q = np.ascontiguousarray(Q, np.int32)
+        if Q.ndim == 2:
+            Q = Q[None]
+        if Q.ndim != 3 or Q.shape[1] != Q.shape[2]:
+            raise ValueError("Q must be K x m x m")
+        K, m = int(Q.shape[0]), int(Q.shape[1])
+        qq = np.zeros(K, np.int64) if q is None else np.ascontiguousarray(q, np.int64)
+        if qq.shape != (K,):
+            raise ValueError("q needs K entries")
+        self._h = C.c_void_p()
+        s = current_stream_handle() if stream is None else stream
+        _check(lib().gqubo_build(m, K, _ptr(Q), _ptr(qq), C.c_void_p(s) if s else None, C.byref(self._h)))
+        self.m, self.K = m, K
+
+    @property
+    def handle(self):
+        return self._h
+
+    def info(self) -> dict:
+        m, K, mx = C.c_int32(), C.c_int32(), C.c_int64()
+        _check(lib().gqubo_info(self._h, C.byref(m), C.byref(K), C.byref(mx)))
+        return dict(m=int(m.value), K=int(K.value), maxabs_c=int(mx.value))
+
+    def close(self):
+        if self._h:
+            lib().gqubo_free(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+@dataclass
+class GArchiveResult:
+    e: np.ndarray               # count x K energies
+    replica: np.ndarray
+    slot: np.ndarray
+    xbits: Optional[np.ndarray]
+
+    def __len__(self):
+        return len(self.e)
+
+
+class GRun:
+    """One gda_run: K-objective replicas on a generic QUBO."""
+
+    def __init__(self, handle: C.c_void_p, g: GQubo):
+        self._h = handle
+        self.qubo = g
+        self.params = Params()
+        _check(lib().gda_params_get(self._h, C.byref(self.params)))
+
+    def kernel_ms(self) -> float:
+        ms = C.c_double()
+        _check(lib().gda_kernel_ms(self._h, C.byref(ms)))
+        return float(ms.value)
+
+    def sync(self):
+        self.kernel_ms()
+
+    def state(self, replica: int, trace: bool = False) -> dict:
+        m, K = self.qubo.m, self.qubo.K
+        x = np.zeros(m, np.uint8)
+        h = np.zeros((K, m), np.int64)
+        E = np.zeros(K, np.int64)
+        eo, mv = C.c_int64(), C.c_int64()
+        tr = np.zeros(int(self.params.steps), np.int32) if trace else None
+        _check(lib().gda_state_get(self._h, int(replica), _ptr(x), _ptr(h), _ptr(E), C.byref(eo), C.byref(mv),
+                                   _ptr(tr) if trace else None))
+        res = dict(x=x, h=h, E=[int(v) for v in E], Eoff=int(eo.value), moves=int(mv.value))
+        if trace:
+            res["trace"] = tr
+        return res
+
+    def archive(self, replica: int = -1, raw: bool = False, bits: bool = True) -> GArchiveResult:
+        cnt = C.c_int64()
+        _check(lib().garchive_get(self._h, int(replica), int(raw), 0, None, None, None, None, C.byref(cnt)))
+        k, K, m = int(cnt.value), self.qubo.K, self.qubo.m
+        e = np.zeros((k, K), np.int64)
+        rep = np.zeros(k, np.int32)
+        slot = np.zeros(k, np.int32)
+        xb = np.zeros((k, (m + 31) // 32), np.uint32) if bits else None
+        _check(lib().garchive_get(self._h, int(replica), int(raw), k, _ptr(e), _ptr(rep), _ptr(slot),
+                                  _ptr(xb) if bits else None, C.byref(cnt)))
+        return GArchiveResult(e, rep, slot, xb)
+
+    def close(self):
+        if self._h:
+            lib().gda_run_free(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def gda_run(g: GQubo, params: Params) -> GRun:
+    h = C.c_void_p()
+    _check(lib().gda_run(g.handle, C.byref(params), C.byref(h)))
+    return GRun(h, g)
 
 
 def run_layout(q: Qubo, params: Params) -> RunLayout:
