@@ -49,6 +49,13 @@ WORKLOADS = {
                           structured=False),
 }
 
+# K objectives on a generic QUBO (the extension beyond two objectives): K dense
+# upper-triangular matrices from synth.make_gqubo, default schedule scaled to
+# max|C|, one wave per replica, one persistent launch
+GENERIC = {
+    "gqubo-k3-m1024": dict(K=3, m=1024, density=0.05, rho=0.0, seed=3, replicas=1024, steps=200_000),
+}
+
 # Peak of plain 32-bit integer VALU work: 256 CUs x 4 SIMDs x 16 lanes per clock
 # x 2.4 GHz (a wave64 VALU instruction occupies a 16-lane SIMD for 4 clocks).
 ALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
@@ -468,6 +475,130 @@ def leg_batch(mda, opm, steps_timed, warmup):
     return out
 
 
+def _goracle_job(args):
+    import oracle
+    (K, m, Qb, qb, r, steps, seed) = args
+    g = oracle.GQubo(np.frombuffer(Qb, np.int32).reshape(K, m, m), np.frombuffer(qb, np.int64))
+    d0, df, xi, beta = oracle.gdefault_schedule(g.maxabs_c, steps)
+    t0 = time.perf_counter()
+    res = oracle.run_greplica(g, r, steps, d0, df, xi, beta, seed)
+    dt = time.perf_counter() - t0
+    return r, dt, (tuple(res["E"]), res["Eoff"], res["moves"], res["arch_size"], res["arch_e"].tobytes())
+
+
+def generic_measure(mda, opm, name, steps_timed, warmup, cpu_replicas=2):
+    """K objectives on a generic QUBO: timed persistent launches (each with the
+    merged K-way front copied to the host), the ALU roofline of the kernel,
+    and the oracle on a bounded sample (the first replicas of the workload,
+    checked bit for bit against the last timed launch)."""
+    import multiprocessing as mp
+    import torch
+    w = GENERIC[name]
+    K, m, R, steps = w["K"], w["m"], w["replicas"], w["steps"]
+    Q, q = synth.make_gqubo(K, m, seed=w["seed"], density=w["density"], rho=w["rho"])
+    g = mda.GQubo(Q, q)
+    params = mda.make_params(R, steps, w["seed"])
+
+    def one_step():
+        run = mda.gda_run(g, params)
+        front = run.archive(-1, bits=False)
+        return run, front
+
+    for k in range(warmup):
+        run, _ = one_step()
+        _log("%s warmup %d: kernel %.1f ms" % (name, k, run.kernel_ms()))
+        run.close()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    kms, run, front, last = [], None, None, None
+    for k in range(steps_timed):
+        if last is not None:
+            last.close()
+        run, front = one_step()
+        kms.append(run.kernel_ms())
+        last = run
+        _log("%s step %d: kernel %.1f ms" % (name, k, kms[-1]))
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    st = run.stats()
+    bt = R * m * steps
+    kernel_ms = float(np.mean(kms))
+    go = opm["generic"]
+    ops = (go["per_bit_trial_per_objective"] * K * bt + go["per_move_bit_per_objective"] * K * m * st["moves"]
+           + go["per_random_block"] * 64 * st["rng_blocks"])
+    achieved = ops / (kernel_ms * 1e-3) / 1e12
+    nbytes = go["breakdown"]["hbm_bytes_per_move_bit_per_objective"] * K * m * st["moves"]
+    roof = {"bound": "alu", "achieved": round(achieved, 3), "peak": round(ALU_PEAK_TOPS, 2), "unit": "TOP/s",
+            "frac": round(achieved / ALU_PEAK_TOPS, 4), "traffic": None, "kernel": "k_generic<%d,%d>" % (K, _slots(m, K)),
+            "kernel_ms": round(kernel_ms, 3), "ops_per_launch": int(ops), "opmodel_version": opm["version"],
+            "hbm": {"algorithmic_bytes_per_launch": int(nbytes),
+                    "achieved_GBs": round(nbytes / (kernel_ms * 1e-3) / 1e9, 2), "peak_GBs": HBM_PEAK_GBS,
+                    "note": "rows of P_k streamed per move; P_1..P_K hold %.1f MB and stay in the L2 caches and MALL"
+                            % (K * m * 64 * _slots(m, K) * 4 / 1e6)}}
+    out = {"value": bt * steps_timed / wall, "unit": "bit-trials/s", "steps": steps_timed, "warmup": warmup,
+           "ms_per_step": round(wall * 1e3 / steps_timed, 3),
+           "config": {"workload": name, "K": K, "m": m, "density": w["density"], "replicas": R, "anneal_steps": steps,
+                      "launch": "persistent, one wave per replica", "bit_trials_per_step": bt},
+           "roofline": roof, "p_move": st["moves"] / (R * steps), "front_size": int(len(front))}
+    if cpu_replicas > 0:
+        ncpu = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
+        cores = max(1, min(cpu_replicas, ncpu, 16))
+        jobs = [(K, m, Q.tobytes(), q.tobytes(), r, steps, w["seed"]) for r in range(cpu_replicas)]
+        ctx = mp.get_context("spawn")
+        avail = sorted(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else list(range(ncpu))
+        counter = ctx.Value("i", 0)
+        t1 = time.perf_counter()
+        with ctx.Pool(cores, initializer=_pin_worker, initargs=(avail[:cores], counter)) as pool:
+            res = pool.map(_goracle_job, jobs, chunksize=1)
+        cw = time.perf_counter() - t1
+        exact = True
+        for r, dt, o in res:
+            s_ = run.state(r)
+            a = run.archive(r, raw=True, bits=False)
+            exact &= (tuple(s_["E"]), s_["Eoff"], s_["moves"], len(a), a.e.tobytes()) == o
+        out["cpu_baseline"] = {"value": cpu_replicas * m * steps / cw, "unit": "bit-trials/s", "cores": cores,
+                               "kind": "oracle",
+                               "sample": "replicas 0..%d of the workload (%d annealing steps each), one process per "
+                                         "replica, each pinned to its own core, %.1f s wall"
+                                         % (cpu_replicas - 1, steps, cw),
+                               "bit_exact_vs_gpu": bool(exact)}
+    run.close()
+    return out
+
+
+def _slots(m, K):
+    for S in (8, 16, 32, 64):
+        if 64 * S >= m and K * S <= 64:
+            return S
+    return 0
+
+
+def copy_calibration():
+    """A 1 GiB fill, then a 1 GiB device-to-device copy: known bytes for
+    scaling the HBM counters."""
+    import torch
+    a = torch.empty(1 << 28, dtype=torch.int32, device="cuda")
+    b = torch.empty_like(a)
+    a.fill_(1)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    return {"read": a.numel() * 4, "write": b.numel() * 4}
+
+
+def generic_bench(args, mda):
+    name = args.workload
+    opm = load_opmodel()
+    leg = generic_measure(mda, opm, name, args.steps, args.warmup,
+                          cpu_replicas=2 if args.cpu_replicas > 0 else 0)
+    out = {"metric": "bit-trials/s", "value": leg["value"], "unit": "bit-trials/s", "n_gpus": 1,
+           "steps": args.steps, "warmup": args.warmup, "ms_per_step": leg["ms_per_step"], "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "int32", "data": "synthetic"}
+    out.update({k: v for k, v in leg.items() if k not in ("value", "unit", "steps", "warmup", "ms_per_step")})
+    if args.copy_calibration:
+        out["copy_calibration_bytes"] = copy_calibration()
+    print(json.dumps(out), flush=True)
+
+
 # ---------------------------------------------------------------- SB-DA vs MDA
 
 def sbda_vs_mda(args, mda):
@@ -569,7 +700,7 @@ def main():
     ap.add_argument("--steps", type=int, default=2, help="timed bench steps")
     ap.add_argument("--warmup", type=int, default=1, help="untimed bench steps")
     ap.add_argument("--workload", default="bqap-n50-x3-kron",
-                    choices=sorted(WORKLOADS) + ["bqap-serve-n10-100", "sbda-vs-mda-n20"])
+                    choices=sorted(WORKLOADS) + sorted(GENERIC) + ["bqap-serve-n10-100", "sbda-vs-mda-n20"])
     ap.add_argument("--anneal-steps", type=int, default=0, help="override the workload's annealing steps")
     ap.add_argument("--replicas", type=int, default=0, help="override the workload's replicas")
     ap.add_argument("--plain", type=int, default=1, help="plain-form comparison runs (0 = none)")
@@ -601,6 +732,11 @@ def main():
         torch.cuda.set_device(0)
         mda.use_torch_allocator()
         serve_bench(args, mda)
+        return
+    if args.workload in GENERIC:
+        torch.cuda.set_device(0)
+        mda.use_torch_allocator()
+        generic_bench(args, mda)
         return
     if args.workload == "sbda-vs-mda-n20":
         torch.cuda.set_device(0)
@@ -689,12 +825,7 @@ def main():
         out["vs_plain"] = round(value / pv, 3)
 
     if args.copy_calibration:
-        a = torch.empty(1 << 28, dtype=torch.int32, device="cuda")
-        b = torch.empty_like(a)
-        a.fill_(1)
-        b.copy_(a)
-        torch.cuda.synchronize()
-        out["copy_calibration_bytes"] = {"read": a.numel() * 4, "write": b.numel() * 4}
+        out["copy_calibration_bytes"] = copy_calibration()
 
     # the oracle on a bounded sample, on host cores (rank 0, one GPU)
     if args.cpu_replicas > 0:
@@ -734,6 +865,10 @@ def main():
                 legs[name] = leg_single(mda, opm, name, args.leg_steps, 1)
         _log("leg batch")
         legs["bqap-batch-n10-60-x256"] = leg_batch(mda, opm, args.leg_steps, 1)
+        for name in GENERIC:
+            _log("leg %s" % name)
+            legs[name] = generic_measure(mda, opm, name, args.leg_steps, 1,
+                                         cpu_replicas=2 if args.cpu_replicas > 0 else 0)
         _log("leg serving")
         sw = dict(SERVE)
         rates, sinsts = serving_measure(mda, sw, factors=(0.9,))

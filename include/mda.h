@@ -462,6 +462,10 @@ int gda_state_get(mda_grun *r, int32_t replica, uint8_t *x, int64_t *h, int64_t 
  */
 int garchive_get(mda_grun *r, int32_t replica, int32_t raw, int64_t cap, int64_t *e, int32_t *rep, int32_t *slot,
                  uint32_t *xbits, int64_t *count);
+/* Run statistics summed over replicas, as da_stats: moves, archive entries
+ * compared, random blocks drawn (one per wave-level draw), archive entries
+ * (synchronises); each may be NULL. */
+int gda_stats(mda_grun *r, int64_t *moves, int64_t *scanned, int64_t *rng_blocks, int64_t *archived);
 void gda_run_free(mda_grun *r);
 
 /* Debug/verification exports: the library's own host tables.

@@ -520,4 +520,204 @@ __global__ void __launch_bounds__(256) k_gnondominated(const GRunDesc *run)
     if (lane == 0) rw(D.st)[(size_t)r * kGWords + kGNd] = count;
 }
 
+// ---- merged non-dominated front of several replicas (K-way, Section 3.3) ----
+
+struct GFrontEntry {
+    int64_t e[kMaxK];
+    int32_t rep, slot;
+};
+
+// One wave per replica r0 + k: its flagged (non-dominated within its archive)
+// entries appended at offs[k] in slot order (offs has nr + 1 entries: the host
+// prefix of the flag counts), and its entry of least energy sum (lowest slot
+// on ties) as a reference point, or an entry of INT64_MAX energies if none.
+template <int K>
+__global__ void __launch_bounds__(256) k_ggather(const GRunDesc *run, int r0, int nr, const int64_t *offs,
+                                                 GFrontEntry *out, GFrontEntry *ref)
+{
+    const int lane = __lane_id();
+    const int k = uni((int)((blockIdx.x * blockDim.x + threadIdx.x) >> 6));
+    if (k >= nr) return;
+    GDesc &D = *ro(run);
+    const int r = r0 + k, s = D.s;
+    int asz = uni((int)ro(D.st)[(size_t)r * kGWords + kGArch]);
+    asz = asz < 0 ? 0 : (asz > s ? s : asz);
+    const MDA_CONST int64_t *AE = ro(D.archE) + (size_t)r * s * K;
+    const MDA_CONST uint8_t *nd = ro(D.nd) + (size_t)r * s;
+    const int64_t base = offs[k], lim = offs[k + 1];
+    const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    int64_t run_n = 0;
+    int64_t bsum = INT64_MAX;
+    int bslot = INT_MAX;
+    for (int b = 0; b < asz; b += 64) {
+        const int e = b + lane;
+        const bool flag = e < asz && nd[e] != 0;
+        const uint64_t M = __ballot(flag);
+        const int64_t pos = base + run_n + __popcll(M & below);
+        if (flag) {
+            int64_t sum = 0;
+            GFrontEntry g;
+#pragma unroll
+            for (int q = 0; q < kMaxK; ++q) g.e[q] = 0;
+#pragma unroll
+            for (int q = 0; q < K; ++q) {
+                g.e[q] = AE[(size_t)e * K + q];
+                sum += g.e[q];
+            }
+            g.rep = r;
+            g.slot = e;
+            if (pos < lim) out[pos] = g;
+            if (sum < bsum) {
+                bsum = sum;
+                bslot = e;
+            }
+        }
+        run_n += __popcll(M);
+    }
+    // least (sum, slot) over the wave
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+        const int64_t os = __shfl_xor(bsum, off);
+        const int oslot = __shfl_xor(bslot, off);
+        if (os < bsum || (os == bsum && oslot < bslot)) {
+            bsum = os;
+            bslot = oslot;
+        }
+    }
+    if (lane == 0) {
+        GFrontEntry g;
+#pragma unroll
+        for (int q = 0; q < kMaxK; ++q) g.e[q] = INT64_MAX;
+        if (bslot != INT_MAX) {
+#pragma unroll
+            for (int q = 0; q < K; ++q) g.e[q] = AE[(size_t)bslot * K + q];
+        }
+        g.rep = bslot != INT_MAX ? r : -1;
+        g.slot = bslot != INT_MAX ? bslot : -1;
+        ref[k] = g;
+    }
+}
+
+// Pre-filter: candidates that a reference point dominates are dropped (a
+// dominated entry is never in the merged front); the rest are appended to keep
+// in arbitrary order.  One thread per candidate, reference points staged
+// through LDS 256 at a time; the block stops once all its candidates are out.
+template <int K>
+__global__ void __launch_bounds__(256) k_gfilter(const GFrontEntry *cand, int64_t n, const GFrontEntry *ref, int nref,
+                                                 GFrontEntry *keep, unsigned long long *nkeep)
+{
+    __shared__ int64_t tile[256 * K];
+    const int tid = (int)threadIdx.x;
+    const int64_t i = (int64_t)blockIdx.x * 256 + tid;
+    bool alive = i < n;
+    int64_t c[K];
+#pragma unroll
+    for (int q = 0; q < K; ++q) c[q] = alive ? cand[i].e[q] : 0;
+    for (int t0 = 0; t0 < nref; t0 += 256) {
+        if (!__syncthreads_or(alive)) break;
+        const int j = t0 + tid;
+#pragma unroll
+        for (int q = 0; q < K; ++q) tile[tid * K + q] = j < nref ? ref[j].e[q] : INT64_MAX;
+        __syncthreads();
+        const int cnt = min(256, nref - t0);
+        if (alive) {
+            for (int t = 0; t < cnt; ++t) {
+                bool le = true, eq = true;
+#pragma unroll
+                for (int q = 0; q < K; ++q) {
+                    const int64_t v = tile[t * K + q];
+                    le = le && v <= c[q];
+                    eq = eq && v == c[q];
+                }
+                if (le && !eq) {
+                    alive = false;
+                    break;
+                }
+            }
+        }
+    }
+    if (alive) {
+        const unsigned long long at = atomicAdd(nkeep, 1ull);
+        keep[at] = cand[i];
+    }
+}
+
+// Exact pass over the survivors: an entry stays unless another survivor
+// dominates it or has the same energies and a lower (replica, slot).
+template <int K>
+__global__ void __launch_bounds__(256) k_gexact(const GFrontEntry *cand, int64_t n, GFrontEntry *front,
+                                                unsigned long long *nfront)
+{
+    __shared__ int64_t tile[256 * K];
+    __shared__ int64_t tkey[256];
+    const int tid = (int)threadIdx.x;
+    const int64_t i = (int64_t)blockIdx.x * 256 + tid;
+    bool alive = i < n;
+    int64_t c[K];
+    int64_t ckey = 0;
+    if (alive) {
+#pragma unroll
+        for (int q = 0; q < K; ++q) c[q] = cand[i].e[q];
+        ckey = ((int64_t)cand[i].rep << 32) | (int64_t)(uint32_t)cand[i].slot;
+    } else {
+#pragma unroll
+        for (int q = 0; q < K; ++q) c[q] = 0;
+    }
+    for (int64_t t0 = 0; t0 < n; t0 += 256) {
+        if (!__syncthreads_or(alive)) break;
+        const int64_t j = t0 + tid;
+        if (j < n) {
+#pragma unroll
+            for (int q = 0; q < K; ++q) tile[tid * K + q] = cand[j].e[q];
+            tkey[tid] = ((int64_t)cand[j].rep << 32) | (int64_t)(uint32_t)cand[j].slot;
+        }
+        __syncthreads();
+        const int cnt = (int)min((int64_t)256, n - t0);
+        if (alive) {
+            for (int t = 0; t < cnt; ++t) {
+                bool le = true, eq = true;
+#pragma unroll
+                for (int q = 0; q < K; ++q) {
+                    const int64_t v = tile[t * K + q];
+                    le = le && v <= c[q];
+                    eq = eq && v == c[q];
+                }
+                if (le && (!eq || tkey[t] < ckey)) {
+                    alive = false;
+                    break;
+                }
+            }
+        }
+    }
+    if (alive) {
+        const unsigned long long at = atomicAdd(nfront, 1ull);
+        front[at] = cand[i];
+    }
+}
+
+// Stored solutions of n (replica, slot) pairs, packed (replica << 32 | slot),
+// into out (n x nl words): one thread per word.
+#ifdef MDA_GX_HOME
+__global__ void __launch_bounds__(256) k_gxgather(const int64_t *at, int64_t n, const uint64_t *archX, int s, int nl,
+                                                  uint64_t *out)
+{
+    const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (t >= n * nl) return;
+    const int64_t i = t / nl;
+    const int w = (int)(t - i * nl);
+    const int64_t key = at[i];
+    const int64_t rep = key >> 32, slot = key & 0xFFFFFFFFll;
+    out[t] = archX[((size_t)rep * s + slot) * nl + w];
+}
+
+hipError_t launch_gxgather(const int64_t *at, int64_t n, const uint64_t *archX, int s, int nl, uint64_t *out,
+                           hipStream_t stream)
+{
+    if (n > 0)
+        hipLaunchKernelGGL(k_gxgather, dim3((unsigned)((n * nl + 255) / 256)), dim3(256), 0, stream, at, n, archX, s, nl,
+                           out);
+    return hipGetLastError();
+}
+#endif
+
 }  // namespace mda

@@ -19,7 +19,17 @@ namespace mda {
     hipError_t launch_generic_k##K(int S, const GRunDesc *run, const int32_t *lnt, int grid, int block,     \
                                    hipStream_t stream, int R);                                              \
     hipError_t generic_occupancy_k##K(int S, int block, int *blocks_per_cu);
+#define MDA_GF_DECL(K)                                                                                      \
+    hipError_t launch_gfront_k##K(const GRunDesc *run, int r0, int nr, const int64_t *offs, int64_t total,      \
+                                  GFrontEntry *cand, GFrontEntry *ref, GFrontEntry *keep, unsigned long long *nkeep, \
+                                  hipStream_t stream);                                                          \
+    hipError_t launch_gexact_k##K(const GFrontEntry *keep, int64_t n, GFrontEntry *front, unsigned long long *nfront, \
+                                  hipStream_t stream);
 MDA_GK_DECL(1) MDA_GK_DECL(2) MDA_GK_DECL(3) MDA_GK_DECL(4)
+MDA_GF_DECL(1) MDA_GF_DECL(2) MDA_GF_DECL(3) MDA_GF_DECL(4)
+#undef MDA_GF_DECL
+hipError_t launch_gxgather(const int64_t *at, int64_t n, const uint64_t *archX, int s, int nl, uint64_t *out,
+                           hipStream_t stream);
 #undef MDA_GK_DECL
 }  // namespace mda
 
@@ -115,11 +125,19 @@ extern "C" void gqubo_free(mda_gqubo *g)
     gqubo_release(g);
 }
 
+struct GEntryH {
+    int64_t e[kMaxK];
+    int32_t rep, slot;
+};
+
 struct mda_grun {
     mda_gqubo *g = nullptr;
     mda_params p{};
     GRunDesc h{};
+    GRunDesc *ddesc = nullptr;
     DevPool pool;
+    std::vector<GEntryH> merged;   // merged front of all replicas, once computed
+    bool merged_ok = false;
     hipStream_t stream = nullptr;
     hipEvent_t ek0 = nullptr, ek1 = nullptr;
     ~mda_grun()
@@ -219,6 +237,7 @@ extern "C" int gda_run(const mda_gqubo *gc, const mda_params *pin, mda_grun **ou
         return fail(MDA_ENOMEM, "device allocation failed for the run (%lld bytes so far)", (long long)pool.total);
     d.T = dT;
     d.thrmax = dthr;
+    r->ddesc = ddesc;
     HIP_TRY(hipMemcpyAsync(dT, T.data(), T.size() * sizeof(int64_t), hipMemcpyHostToDevice, stream));
     HIP_TRY(hipMemcpyAsync(dthr, thr.data(), thr.size() * sizeof(int64_t), hipMemcpyHostToDevice, stream));
     HIP_TRY(hipMemcpyAsync(dlnt, lnt, sizeof lnt, hipMemcpyHostToDevice, stream));
@@ -312,45 +331,76 @@ extern "C" int gda_state_get(mda_grun *r, int32_t replica, uint8_t *x, int64_t *
 
 namespace {
 
-struct GEntry {
-    int64_t e[kMaxK];
-    int32_t rep, slot;
+struct TmpPool {
+    DevPool pool;
+    ~TmpPool() { pool.release_all(); }
 };
 
-bool gdom_host(const GEntry &p, const GEntry &q, int K)
+bool lex_less(const GEntryH &a, const GEntryH &b, int K)
 {
-    bool le = true, eq = true;
-    for (int k = 0; k < K; ++k) {
-        le = le && p.e[k] <= q.e[k];
-        eq = eq && p.e[k] == q.e[k];
-    }
-    return le && !eq;
+    for (int k = 0; k < K; ++k)
+        if (a.e[k] != b.e[k]) return a.e[k] < b.e[k];
+    if (a.rep != b.rep) return a.rep < b.rep;
+    return a.slot < b.slot;
 }
 
-// Non-dominated subset of cand (Section 3.3), equal energy vectors reduced to
-// the lowest (replica, slot), in lexicographic order of (E, replica, slot).
-// A dominating entry precedes the entry it dominates in that order, so each
-// entry is compared with the front built so far.
-std::vector<GEntry> front_of(std::vector<GEntry> cand, int K)
+// Non-dominated entries of the archives of replicas [r0, r0 + nr) (Section
+// 3.3), equal energy vectors reduced to the lowest (replica, slot), sorted by
+// (E, replica, slot).  The device gathers the flagged entries, drops those a
+// replica's least-sum entry dominates and keeps the survivors that no other
+// survivor dominates; the host sorts what is left.
+int merged_front(mda_grun *r, int r0, int nr, const std::vector<int64_t> &st, std::vector<GEntryH> &out)
 {
-    std::sort(cand.begin(), cand.end(), [K](const GEntry &a, const GEntry &b) {
-        for (int k = 0; k < K; ++k)
-            if (a.e[k] != b.e[k]) return a.e[k] < b.e[k];
-        if (a.rep != b.rep) return a.rep < b.rep;
-        return a.slot < b.slot;
-    });
-    std::vector<GEntry> front;
-    for (const GEntry &c : cand) {
-        if (!front.empty() && std::equal(c.e, c.e + K, front.back().e)) continue;   // an equal vector kept already
-        bool dominated = false;
-        for (const GEntry &f : front)
-            if (gdom_host(f, c, K)) {
-                dominated = true;
-                break;
-            }
-        if (!dominated) front.push_back(c);
+    const GRunDesc &d = r->h;
+    const int K = d.K;
+    hipStream_t s = r->stream;
+    out.clear();
+    std::vector<int64_t> offs((size_t)nr + 1, 0);
+    for (int k = 0; k < nr; ++k) offs[k + 1] = offs[k] + std::max<int64_t>(0, st[(size_t)k * kGWords + kGNd]);
+    const int64_t total = offs[nr];
+    if (total == 0) return MDA_OK;
+    TmpPool tmp;
+    int64_t *doffs = tmp.pool.alloc<int64_t>(offs.size(), s);
+    GFrontEntry *cand = tmp.pool.alloc<GFrontEntry>((size_t)total, s);
+    GFrontEntry *ref = tmp.pool.alloc<GFrontEntry>((size_t)nr, s);
+    GFrontEntry *keep = tmp.pool.alloc<GFrontEntry>((size_t)total, s);
+    GFrontEntry *front = tmp.pool.alloc<GFrontEntry>((size_t)total, s);
+    unsigned long long *cnt = tmp.pool.alloc<unsigned long long>(2, s);
+    if (!doffs || !cand || !ref || !keep || !front || !cnt)
+        return fail(MDA_ENOMEM, "device allocation failed for %lld front candidates", (long long)total);
+    HIP_TRY(hipMemcpyAsync(doffs, offs.data(), offs.size() * sizeof(int64_t), hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemsetAsync(cnt, 0, 2 * sizeof(unsigned long long), s));
+    hipError_t e = hipErrorInvalidValue;
+    switch (K) {
+    case 1: e = launch_gfront_k1(r->ddesc, r0, nr, doffs, total, cand, ref, keep, cnt, s); break;
+    case 2: e = launch_gfront_k2(r->ddesc, r0, nr, doffs, total, cand, ref, keep, cnt, s); break;
+    case 3: e = launch_gfront_k3(r->ddesc, r0, nr, doffs, total, cand, ref, keep, cnt, s); break;
+    default: e = launch_gfront_k4(r->ddesc, r0, nr, doffs, total, cand, ref, keep, cnt, s); break;
     }
-    return front;
+    if (e != hipSuccess) return fail(MDA_EDEVICE, "front gather failed: %s", hipGetErrorString(e));
+    unsigned long long nk = 0, nf = 0;
+    int rc = gcopy(&nk, cnt, sizeof nk, s);
+    if (rc) return rc;
+    if ((int64_t)nk > total) return fail(MDA_EDEVICE, "front filter kept %llu of %lld", nk, (long long)total);
+    switch (K) {
+    case 1: e = launch_gexact_k1(keep, (int64_t)nk, front, cnt + 1, s); break;
+    case 2: e = launch_gexact_k2(keep, (int64_t)nk, front, cnt + 1, s); break;
+    case 3: e = launch_gexact_k3(keep, (int64_t)nk, front, cnt + 1, s); break;
+    default: e = launch_gexact_k4(keep, (int64_t)nk, front, cnt + 1, s); break;
+    }
+    if (e != hipSuccess) return fail(MDA_EDEVICE, "front pass failed: %s", hipGetErrorString(e));
+    if ((rc = gcopy(&nf, cnt + 1, sizeof nf, s))) return rc;
+    if (nf > nk) return fail(MDA_EDEVICE, "front pass kept %llu of %llu", nf, nk);
+    std::vector<GFrontEntry> fe((size_t)nf);
+    if ((rc = gcopy(fe.data(), front, fe.size() * sizeof(GFrontEntry), s))) return rc;
+    out.resize(fe.size());
+    for (size_t i = 0; i < fe.size(); ++i) {
+        std::memcpy(out[i].e, fe[i].e, sizeof out[i].e);
+        out[i].rep = fe[i].rep;
+        out[i].slot = fe[i].slot;
+    }
+    std::sort(out.begin(), out.end(), [K](const GEntryH &a, const GEntryH &b) { return lex_less(a, b, K); });
+    return MDA_OK;
 }
 
 }  // namespace
@@ -365,48 +415,93 @@ extern "C" int garchive_get(mda_grun *r, int32_t replica, int32_t raw, int64_t c
     if (replica < 0 && raw) return fail(MDA_EINVAL, "the raw archive is per replica");
     hipStream_t st_ = r->stream;
     HIP_TRY(hipEventSynchronize(r->ek1));
-    const int r0 = replica < 0 ? 0 : replica, nr = replica < 0 ? d.R : 1;
-    std::vector<int64_t> st((size_t)nr * kGWords);
     int rc;
-    if ((rc = gcopy(st.data(), d.st + (size_t)r0 * kGWords, st.size() * 8, st_))) return rc;
-    std::vector<int64_t> E((size_t)nr * s * K);
-    if ((rc = gcopy(E.data(), d.archE + (size_t)r0 * s * K, E.size() * 8, st_))) return rc;
-    std::vector<uint8_t> nd;
-    if (!raw) {
-        nd.resize((size_t)nr * s);
-        if ((rc = gcopy(nd.data(), d.nd + (size_t)r0 * s, nd.size(), st_))) return rc;
-    }
-    std::vector<GEntry> ent;
-    for (int k = 0; k < nr; ++k) {
-        const int asz = (int)std::min<int64_t>(std::max<int64_t>(st[(size_t)k * kGWords + kGArch], 0), s);
-        for (int q = 0; q < asz; ++q) {
-            if (!raw && !nd[(size_t)k * s + q]) continue;
-            GEntry g{};
-            for (int kk = 0; kk < K; ++kk) g.e[kk] = E[((size_t)k * s + q) * K + kk];
-            g.rep = r0 + k;
-            g.slot = q;
-            ent.push_back(g);
+    std::vector<GEntryH> local;
+    const std::vector<GEntryH> *src = &local;
+    if (replica < 0 && r->merged_ok) {
+        src = &r->merged;
+    } else {
+        const int r0 = replica < 0 ? 0 : replica, nr = replica < 0 ? d.R : 1;
+        std::vector<int64_t> st((size_t)nr * kGWords);
+        if ((rc = gcopy(st.data(), d.st + (size_t)r0 * kGWords, st.size() * 8, st_))) return rc;
+        if (raw) {
+            const int asz = (int)std::min<int64_t>(std::max<int64_t>(st[kGArch], 0), s);
+            std::vector<int64_t> E((size_t)asz * K);
+            if ((rc = gcopy(E.data(), d.archE + (size_t)replica * s * K, E.size() * 8, st_))) return rc;
+            local.resize((size_t)asz);
+            for (int q = 0; q < asz; ++q) {
+                GEntryH g{};
+                for (int kk = 0; kk < K; ++kk) g.e[kk] = E[(size_t)q * K + kk];
+                g.rep = replica;
+                g.slot = q;
+                local[q] = g;
+            }
+        } else {
+            if ((rc = merged_front(r, r0, nr, st, local))) return rc;
+            if (replica < 0) {
+                r->merged = local;
+                r->merged_ok = true;
+                src = &r->merged;
+            }
         }
     }
-    if (!raw) ent = front_of(std::move(ent), K);
+    const std::vector<GEntryH> &ent = *src;
     *count = (int64_t)ent.size();
     if (!e) return MDA_OK;
     if (cap < (int64_t)ent.size()) return fail(MDA_ERANGE, "capacity %lld < %zu entries", (long long)cap, ent.size());
     const int words = (d.m + 31) / 32;
-    std::vector<uint64_t> xw((size_t)d.nl);
+    std::vector<uint64_t> xw;
+    if (xbits && !ent.empty()) {
+        // stored solutions of the returned entries: one contiguous copy of a
+        // raw archive, else gathered on the device and copied once
+        xw.resize(ent.size() * (size_t)d.nl);
+        if (raw) {
+            if ((rc = gcopy(xw.data(), d.archX + (size_t)replica * s * d.nl, xw.size() * 8, st_))) return rc;
+        } else {
+            std::vector<int64_t> at(ent.size());
+            for (size_t i = 0; i < ent.size(); ++i) at[i] = ((int64_t)ent[i].rep << 32) | (int64_t)ent[i].slot;
+            TmpPool tmp;
+            int64_t *dat = tmp.pool.alloc<int64_t>(at.size(), st_);
+            uint64_t *dx = tmp.pool.alloc<uint64_t>(xw.size(), st_);
+            if (!dat || !dx) return fail(MDA_ENOMEM, "device allocation failed for %zu solutions", ent.size());
+            HIP_TRY(hipMemcpyAsync(dat, at.data(), at.size() * 8, hipMemcpyHostToDevice, st_));
+            HIP_TRY(launch_gxgather(dat, (int64_t)at.size(), d.archX, s, d.nl, dx, st_));
+            if ((rc = gcopy(xw.data(), dx, xw.size() * 8, st_))) return rc;
+        }
+    }
     for (size_t i = 0; i < ent.size(); ++i) {
         for (int k = 0; k < K; ++k) e[i * K + k] = ent[i].e[k];
         if (rep) rep[i] = ent[i].rep;
         if (slot) slot[i] = ent[i].slot;
         if (xbits) {
-            if ((rc = gcopy(xw.data(), d.archX + ((size_t)ent[i].rep * s + ent[i].slot) * d.nl, xw.size() * 8, st_)))
-                return rc;
+            const uint64_t *xs = xw.data() + i * d.nl;
             uint32_t *o = xbits + i * words;
             std::memset(o, 0, (size_t)words * 4);
             for (int a = 0; a < d.m; ++a)
-                if ((xw[a / d.S] >> (a % d.S)) & 1ull) o[a >> 5] |= 1u << (a & 31);
+                if ((xs[a / d.S] >> (a % d.S)) & 1ull) o[a >> 5] |= 1u << (a & 31);
         }
     }
+    return MDA_OK;
+}
+
+extern "C" int gda_stats(mda_grun *r, int64_t *moves, int64_t *scanned, int64_t *rng_blocks, int64_t *archived)
+{
+    if (!r) return fail(MDA_EINVAL, "NULL run");
+    const GRunDesc &d = r->h;
+    std::vector<int64_t> st((size_t)d.R * kGWords);
+    int rc = gcopy(st.data(), d.st, st.size() * sizeof(int64_t), r->stream);
+    if (rc) return rc;
+    int64_t mv = 0, sc = 0, rb = 0, ar = 0;
+    for (int i = 0; i < d.R; ++i) {
+        mv += st[(size_t)i * kGWords + kGMoves];
+        sc += st[(size_t)i * kGWords + kGScanned];
+        rb += st[(size_t)i * kGWords + kGRng];
+        ar += st[(size_t)i * kGWords + kGArch];
+    }
+    if (moves) *moves = mv;
+    if (scanned) *scanned = sc;
+    if (rng_blocks) *rng_blocks = rb;
+    if (archived) *archived = ar;
     return MDA_OK;
 }
 

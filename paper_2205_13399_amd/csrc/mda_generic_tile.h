@@ -44,4 +44,23 @@ hipError_t MDA_GCAT(generic_occupancy_k, MDA_GK)(int S, int block, int *blocks_p
     }
 }
 
+hipError_t MDA_GCAT(launch_gfront_k, MDA_GK)(const GRunDesc *run, int r0, int nr, const int64_t *offs, int64_t total,
+                                            GFrontEntry *cand, GFrontEntry *ref, GFrontEntry *keep,
+                                            unsigned long long *nkeep, hipStream_t stream)
+{
+    hipLaunchKernelGGL((k_ggather<MDA_GK>), dim3((nr + 3) / 4), dim3(256), 0, stream, run, r0, nr, offs, cand, ref);
+    hipLaunchKernelGGL((k_gfilter<MDA_GK>), dim3((unsigned)((total + 255) / 256)), dim3(256), 0, stream, cand, total,
+                       ref, nr, keep, nkeep);
+    return hipGetLastError();
+}
+
+hipError_t MDA_GCAT(launch_gexact_k, MDA_GK)(const GFrontEntry *keep, int64_t n, GFrontEntry *front,
+                                            unsigned long long *nfront, hipStream_t stream)
+{
+    if (n > 0)
+        hipLaunchKernelGGL((k_gexact<MDA_GK>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, stream, keep, n, front,
+                           nfront);
+    return hipGetLastError();
+}
+
 }  // namespace mda

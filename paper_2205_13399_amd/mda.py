@@ -201,6 +201,8 @@ def lib():
     L.gda_state_get.restype = C.c_int
     L.garchive_get.argtypes = [vp, i32, i32, i64, vp, vp, vp, vp, C.POINTER(i64)]
     L.garchive_get.restype = C.c_int
+    L.gda_stats.argtypes = [vp, C.POINTER(i64), C.POINTER(i64), C.POINTER(i64), C.POINTER(i64)]
+    L.gda_stats.restype = C.c_int
     L.gda_run_free.argtypes = [vp]
     L.gda_run_free.restype = None
     _lib = L
@@ -212,7 +214,7 @@ EXPORTED = ["qubo_build_bqap", "qubo_flows", "qubo_info", "qubo_free", "mda_para
             "mda_set_allocator", "mda_last_error", "mda_threshold_table", "mda_temperature_table",
             "mda_autotune", "mda_footprint", "da_run_layout", "da_run_noalloc", "mda_server_create", "mda_server_submit", "mda_server_wait", "mda_server_stats",
             "mda_server_destroy", "gqubo_build", "gqubo_info", "gqubo_free", "gda_run", "gda_params_get", "gda_kernel_ms",
-            "gda_state_get", "garchive_get", "gda_run_free"]
+            "gda_state_get", "garchive_get", "gda_stats", "gda_run_free"]
 
 
 def _check(rc: int):
@@ -565,6 +567,11 @@ class GRun:
         if trace:
             res["trace"] = tr
         return res
+
+    def stats(self) -> dict:
+        a, b, c, d = C.c_int64(), C.c_int64(), C.c_int64(), C.c_int64()
+        _check(lib().gda_stats(self._h, C.byref(a), C.byref(b), C.byref(c), C.byref(d)))
+        return dict(moves=int(a.value), scanned=int(b.value), rng_blocks=int(c.value), archived=int(d.value))
 
     def archive(self, replica: int = -1, raw: bool = False, bits: bool = True) -> GArchiveResult:
         cnt = C.c_int64()

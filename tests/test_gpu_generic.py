@@ -6,7 +6,8 @@ objectives) on the GPU, bit for bit against the oracle's K-objective MDA.
     archive methods and both escapes, at sizes from m = 2 to the largest each K
     takes, every slot count, ragged last lanes;
   * the merged non-dominated front over all replicas and each replica's own
-    front against the front of the oracle's archives;
+    front against the front of the oracle's archives, and at scale (256
+    replicas) against its definition over every raw archive entry;
   * a temperature table given as data;
   * properties at the largest sizes: energies of the final states and of every
     archived solution from Eq. (qubo) directly; the lenient rule with K copies
@@ -138,6 +139,45 @@ def test_generic_fronts(mda, K, accept, archive):
     X = decode_bits(f.xbits, m)
     for i in range(len(f)):
         assert _energies(Q, q, X[i]) == list(got[i][0])
+
+
+@pytest.mark.parametrize("K", [2, 3, 4])
+def test_generic_merged_front_at_scale(mda, K):
+    """The merged front of many replicas against its definition over every raw
+    archive entry: no entry dominates a front entry, every entry is dominated
+    by or equal to a front entry, equal energy vectors appear once with their
+    lowest (replica, slot), sorted lexicographically."""
+    m, R, steps = 512, 256, 20000
+    Q, q = synth.make_gqubo(K, m, seed=600 + K, density=0.1, rho=-0.4)
+    g = mda.GQubo(Q, q)
+    print("generic front K=%d m=%d R=%d steps=%d" % (K, m, R, steps), flush=True)
+    run = mda.gda_run(g, mda.make_params(R, steps, 17, xi=0.002, delta0=0.0))
+    run.sync()
+    E, key = [], []
+    for r in range(R):
+        a = run.archive(r, raw=True, bits=False)
+        E.append(a.e)
+        key.append(np.stack([np.full(len(a), r), np.arange(len(a))], axis=1))
+    E = np.concatenate(E)
+    key = np.concatenate(key)
+    f = run.archive(-1)
+    F = f.e
+    assert len(F) > 10
+    for i in range(len(F)):
+        dom = np.all(E <= F[i], axis=1) & np.any(E < F[i], axis=1)
+        assert not dom.any(), i
+        same = np.all(E == F[i], axis=1)
+        lowest = min(tuple(k) for k in key[same])
+        assert (int(f.replica[i]), int(f.slot[i])) == lowest, i
+    covered = np.zeros(len(E), bool)
+    for i in range(len(F)):
+        covered |= np.all(F[i] <= E, axis=1)
+    assert covered.all()
+    rows = [tuple(v) + (int(f.replica[i]), int(f.slot[i])) for i, v in enumerate(F.tolist())]
+    assert rows == sorted(rows) and len({tuple(v) for v in F.tolist()}) == len(F)
+    X = decode_bits(f.xbits, m)
+    for i in range(0, len(F), max(1, len(F) // 16)):
+        assert _energies(Q, q, X[i]) == [int(v) for v in F[i]]
 
 
 def test_generic_temp_table(mda):
