@@ -438,8 +438,11 @@ void gqubo_free(mda_gqubo *g);
 /* Runs p->replicas replicas, one wave each (asynchronous on p->stream; the
  * run holds a reference to g, which may be freed before the run).  The fields
  * of p are those of da_run, with variant MDA_VARIANT_AUTO or
- * MDA_VARIANT_PERSISTENT, graph 0 and waves_per_replica 0 or 1.  Errors: as
- * da_run, and MDA_EINVAL for the unsupported fields. */
+ * MDA_VARIANT_PERSISTENT, graph 0 and waves_per_replica 0 or 1.  Each wave
+ * keeps its replica's archive energies in LDS: archive_size * K is at most
+ * 18432 (the default archive_size = m always fits; waves_per_block shrinks
+ * until the block's archives fit).  Errors: as da_run, and MDA_EINVAL for the
+ * unsupported fields and a larger archive. */
 int gda_run(const mda_gqubo *g, const mda_params *p, mda_grun **out);
 /* p as resolved (steps, schedule, beta, archive size). */
 int gda_params_get(const mda_grun *r, mda_params *out);

@@ -179,8 +179,12 @@ __device__ __forceinline__ void g_init(GDesc *Dp, GRep<K, S> &G, int r, int lane
 }
 
 // Archive update after a move: Algorithm 4 (explore) or 5 (exploit), K-way.
+// The scans read the wave's copy of the archive energies in LDS (objective
+// k of member e at AL[k s + e]); an insertion writes both that copy and the
+// archive in HBM.
 template <int K, int S>
-__device__ __forceinline__ void g_archive(GDesc *Dp, GRep<K, S> &G, int r, uint32_t t, int lane_)
+__device__ __forceinline__ void g_archive(GDesc *Dp, GRep<K, S> &G, int r, uint32_t t, int lane_,
+                                          MDA_LDS int64_t *AL)
 {
     const int lane = opaque_lane(lane_);
     GDesc &D = *gcold(Dp);
@@ -203,7 +207,7 @@ __device__ __forceinline__ void g_archive(GDesc *Dp, GRep<K, S> &G, int r, uint3
                 const int ec = e < asz ? e : asz - 1;
                 int64_t a[K];
 #pragma unroll
-                for (int k = 0; k < K; ++k) a[k] = AE[(size_t)ec * K + k];
+                for (int k = 0; k < K; ++k) a[k] = AL[k * s + ec];
                 M[q] = __ballot(e < asz && gdom<K>(E, a));
             }
             int q = -1;
@@ -229,7 +233,7 @@ __device__ __forceinline__ void g_archive(GDesc *Dp, GRep<K, S> &G, int r, uint3
             if (e < asz) {
                 int64_t a[K];
 #pragma unroll
-                for (int k = 0; k < K; ++k) a[k] = AE[(size_t)e * K + k];
+                for (int k = 0; k < K; ++k) a[k] = AL[k * s + e];
                 z = gdom<K>(a, E);
                 y = gdom<K>(E, a);
             }
@@ -250,7 +254,7 @@ __device__ __forceinline__ void g_archive(GDesc *Dp, GRep<K, S> &G, int r, uint3
                 if (e < asz) {
                     int64_t a[K];
 #pragma unroll
-                    for (int kk = 0; kk < K; ++kk) a[kk] = AE[(size_t)e * K + kk];
+                    for (int kk = 0; kk < K; ++kk) a[kk] = AL[kk * s + e];
                     y = gdom<K>(E, a);
                 }
                 const uint64_t M = __ballot(y);
@@ -274,6 +278,7 @@ __device__ __forceinline__ void g_archive(GDesc *Dp, GRep<K, S> &G, int r, uint3
 #pragma unroll
             for (int k = 1; k < K; ++k) v = (lane == k) ? E[k] : v;
             AE[(size_t)slot * K + lane] = v;
+            AL[lane * s + slot] = v;
         }
         if (lane < nl) AX[(size_t)slot * nl + lane] = G.xm;
     }
@@ -283,7 +288,7 @@ __device__ __forceinline__ void g_archive(GDesc *Dp, GRep<K, S> &G, int r, uint3
 // G1-G3).  Returns the flipped bit or -1.
 template <int K, int S, int AM>
 __device__ __forceinline__ int g_step(GDesc *Dp, GRep<K, S> &G, int r, uint32_t t, int lane_,
-                                      const MDA_LDS int32_t *lnt, int64_t thrmax)
+                                      const MDA_LDS int32_t *lnt, int64_t thrmax, MDA_LDS int64_t *AL)
 {
     constexpr bool strict = AM == kAmStrict;
     GDesc &Dh = *Dp;
@@ -343,7 +348,7 @@ __device__ __forceinline__ int g_step(GDesc *Dp, GRep<K, S> &G, int r, uint32_t 
                         const uint32_t L = Lv[f] & 0xFFFFFu;
                         const uint64_t low = (uint64_t)Tl * (uint64_t)L;
                         const uint64_t thr = (uint64_t)Th * (uint64_t)L + (low >> 24);
-                        certain |= (((maybe >> f) & 1u) && Sx <= thr) ? (1u << f) : 0u;
+                        certain |= ((maybe >> f) & (Sx <= thr ? 1u : 0u)) << f;
                     }
                 }
                 acc |= (uint64_t)certain << g;
@@ -394,7 +399,7 @@ __device__ __forceinline__ int g_step(GDesc *Dp, GRep<K, S> &G, int r, uint32_t 
             G.xm ^= atj ? (1ull << js) : 0ull;
             g_minima<K, S, AM>(G);
             G.moves++;
-            g_archive<K, S>(Dp, G, r, t, lane);
+            g_archive<K, S>(Dp, G, r, t, lane, AL);
         }
     }
     const bool moved = j >= 0;
@@ -447,7 +452,7 @@ __device__ __forceinline__ void g_export(GDesc *Dp, const GRep<K, S> &G, int r, 
 }
 
 template <int K, int S, int AM>
-__device__ __forceinline__ void g_run(GDesc *Dp, int r, int lane, const MDA_LDS int32_t *lnt)
+__device__ __forceinline__ void g_run(GDesc *Dp, int r, int lane, const MDA_LDS int32_t *lnt, MDA_LDS int64_t *AL)
 {
     GRep<K, S> G;
     g_init<K, S>(Dp, G, r, lane);
@@ -457,17 +462,19 @@ __device__ __forceinline__ void g_run(GDesc *Dp, int r, int lane, const MDA_LDS 
     int64_t thr = thrmax[0];
     for (uint32_t t = 1; t <= steps; ++t) {
         const int64_t thr_next = thrmax[(t < ntab - 1u) ? t : ntab - 1u];
-        g_step<K, S, AM>(Dp, G, r, t, lane, lnt, thr);
+        g_step<K, S, AM>(Dp, G, r, t, lane, lnt, thr, AL);
         thr = thr_next;
     }
     g_export<K, S>(Dp, G, r, lane);
 }
 
 // Persistent form: wave w of the grid runs replicas w, w + W, ... of one run.
+// Dynamic LDS: s * K int64 archive energies per wave of the block.
 template <int K, int S>
 __global__ void __launch_bounds__(256) k_generic(const GRunDesc *run, const int32_t *lnt_)
 {
     __shared__ int32_t lnt_lds[4096];
+    extern __shared__ int64_t garch_lds[];
     for (int k = (int)threadIdx.x; k < 4096; k += (int)blockDim.x) lnt_lds[k] = ((const MDA_GLOBAL int32_t *)lnt_)[k];
     __syncthreads();
     const MDA_LDS int32_t *lnt = (const MDA_LDS int32_t *)lnt_lds;
@@ -478,9 +485,10 @@ __global__ void __launch_bounds__(256) k_generic(const GRunDesc *run, const int3
     GDesc *Dp = ro(run);
     const int R = Dp->R;
     const bool strict = Dp->accept == 0;
+    MDA_LDS int64_t *AL = (MDA_LDS int64_t *)(garch_lds + (size_t)(threadIdx.x >> 6) * Dp->s * K);
     for (int r = wave; r < R; r += nwaves) {
-        if (strict) g_run<K, S, kAmStrict>(Dp, r, lane, lnt);
-        else g_run<K, S, kAmLenient>(Dp, r, lane, lnt);
+        if (strict) g_run<K, S, kAmStrict>(Dp, r, lane, lnt, AL);
+        else g_run<K, S, kAmLenient>(Dp, r, lane, lnt, AL);
     }
 }
 

@@ -17,8 +17,8 @@
 namespace mda {
 #define MDA_GK_DECL(K)                                                                                      \
     hipError_t launch_generic_k##K(int S, const GRunDesc *run, const int32_t *lnt, int grid, int block,     \
-                                   hipStream_t stream, int R);                                              \
-    hipError_t generic_occupancy_k##K(int S, int block, int *blocks_per_cu);
+                                   size_t dyn_lds, hipStream_t stream, int R);                              \
+    hipError_t generic_occupancy_k##K(int S, int block, size_t dyn_lds, int *blocks_per_cu);
 #define MDA_GF_DECL(K)                                                                                      \
     hipError_t launch_gfront_k##K(const GRunDesc *run, int r0, int nr, const int64_t *offs, int64_t total,      \
                                   GFrontEntry *cand, GFrontEntry *ref, GFrontEntry *keep, unsigned long long *nkeep, \
@@ -34,6 +34,9 @@ hipError_t launch_gxgather(const int64_t *at, int64_t n, const uint64_t *archX, 
 }  // namespace mda
 
 using namespace mda;
+
+// LDS of one workgroup on gfx950 and the part the -ln table takes
+constexpr size_t kLdsBytes = 160 * 1024, kLntBytes = 4096 * sizeof(int32_t);
 
 struct mda_gqubo {
     int32_t m = 0, K = 0, S = 0, nl = 0;
@@ -170,6 +173,12 @@ extern "C" int gda_run(const mda_gqubo *gc, const mda_params *pin, mda_grun **ou
     if (p.archive != MDA_EXPLORE && p.archive != MDA_EXPLOIT) return fail(MDA_EINVAL, "archive = %d", p.archive);
     if (p.escape != MDA_ESC_OFFSET && p.escape != MDA_ESC_ARCHIVE) return fail(MDA_EINVAL, "escape = %d", p.escape);
     if (p.archive_size < 0) return fail(MDA_EINVAL, "archive_size = %d", p.archive_size);
+    {
+        const int64_t s_ = p.archive_size > 0 ? p.archive_size : m;
+        if (s_ * K * (int64_t)sizeof(int64_t) > (int64_t)(kLdsBytes - kLntBytes))
+            return fail(MDA_EINVAL, "archive_size %lld x %d objectives exceeds the %d entries a wave keeps in LDS",
+                        (long long)s_, K, (int)((kLdsBytes - kLntBytes) / sizeof(int64_t)));
+    }
     if (p.trace_replicas < 0 || p.trace_replicas > p.replicas)
         return fail(MDA_EINVAL, "trace_replicas = %d", p.trace_replicas);
     if (p.delta0 <= 0.0) {
@@ -248,13 +257,19 @@ extern "C" int gda_run(const mda_gqubo *gc, const mda_params *pin, mda_grun **ou
     int dev = 0, cus = 0, per_cu = 0;
     HIP_TRY(hipGetDevice(&dev));
     HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
-    const int block = 64 * ((p.waves_per_block >= 1 && p.waves_per_block <= 4) ? p.waves_per_block : 4);
+    // each wave keeps its replica's archive energies in LDS beside the 16 KB
+    // -ln table: as many waves per block as fit (up to the requested count)
+    const size_t per_wave = (size_t)s * K * sizeof(int64_t);
+    int wpb = (p.waves_per_block >= 1 && p.waves_per_block <= 4) ? p.waves_per_block : 4;
+    while (wpb > 1 && kLdsBytes - kLntBytes < wpb * per_wave) --wpb;
+    const int block = 64 * wpb;
+    const size_t dyn = wpb * per_wave;
     hipError_t oe = hipErrorInvalidValue;
     switch (K) {
-    case 1: oe = generic_occupancy_k1(g->S, block, &per_cu); break;
-    case 2: oe = generic_occupancy_k2(g->S, block, &per_cu); break;
-    case 3: oe = generic_occupancy_k3(g->S, block, &per_cu); break;
-    default: oe = generic_occupancy_k4(g->S, block, &per_cu); break;
+    case 1: oe = generic_occupancy_k1(g->S, block, dyn, &per_cu); break;
+    case 2: oe = generic_occupancy_k2(g->S, block, dyn, &per_cu); break;
+    case 3: oe = generic_occupancy_k3(g->S, block, dyn, &per_cu); break;
+    default: oe = generic_occupancy_k4(g->S, block, dyn, &per_cu); break;
     }
     if (oe != hipSuccess) return fail(MDA_EDEVICE, "occupancy query failed: %s", hipGetErrorString(oe));
     if (per_cu < 1) per_cu = 1;
@@ -264,10 +279,10 @@ extern "C" int gda_run(const mda_gqubo *gc, const mda_params *pin, mda_grun **ou
     HIP_TRY(hipEventRecord(r->ek0, stream));
     hipError_t le = hipErrorInvalidValue;
     switch (K) {
-    case 1: le = launch_generic_k1(g->S, ddesc, dlnt, grid, block, stream, R); break;
-    case 2: le = launch_generic_k2(g->S, ddesc, dlnt, grid, block, stream, R); break;
-    case 3: le = launch_generic_k3(g->S, ddesc, dlnt, grid, block, stream, R); break;
-    default: le = launch_generic_k4(g->S, ddesc, dlnt, grid, block, stream, R); break;
+    case 1: le = launch_generic_k1(g->S, ddesc, dlnt, grid, block, dyn, stream, R); break;
+    case 2: le = launch_generic_k2(g->S, ddesc, dlnt, grid, block, dyn, stream, R); break;
+    case 3: le = launch_generic_k3(g->S, ddesc, dlnt, grid, block, dyn, stream, R); break;
+    default: le = launch_generic_k4(g->S, ddesc, dlnt, grid, block, dyn, stream, R); break;
     }
     if (le != hipSuccess)
         return fail(MDA_EDEVICE, "generic launch (K %d, S %d, grid %d) failed: %s", K, g->S, grid, hipGetErrorString(le));

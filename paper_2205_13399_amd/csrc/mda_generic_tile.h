@@ -11,16 +11,20 @@ namespace mda {
 #define MDA_GCAT(a, b) MDA_GCAT2(a, b)
 
 hipError_t MDA_GCAT(launch_generic_k, MDA_GK)(int S, const GRunDesc *run, const int32_t *lnt, int grid, int block,
-                                             hipStream_t stream, int R)
+                                             size_t dyn_lds, hipStream_t stream, int R)
 {
     const int nd_grid = (R * 64 + 255) / 256;
     switch (S) {
 #define GX(SS)                                                                                               \
-    case SS:                                                                                                 \
-        if (MDA_GK * SS > 64) return hipErrorInvalidValue;                                                  \
-        hipLaunchKernelGGL((k_generic<MDA_GK, (MDA_GK * SS <= 64 ? SS : 8)>), dim3(grid), dim3(block), 0,   \
-                           stream, run, lnt);                                                                \
-        break;
+    case SS: {                                                                                               \
+        if (MDA_GK * SS > 64) return hipErrorInvalidValue;                                                   \
+        auto kern = k_generic<MDA_GK, (MDA_GK * SS <= 64 ? SS : 8)>;                                         \
+        const hipError_t ea = hipFuncSetAttribute((const void *)kern,                                        \
+                                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)dyn_lds); \
+        if (ea != hipSuccess) return ea;                                                                     \
+        hipLaunchKernelGGL(kern, dim3(grid), dim3(block), dyn_lds, stream, run, lnt);                        \
+        break;                                                                                               \
+    }
         GX(8) GX(16) GX(32) GX(64)
 #undef GX
     default:
@@ -30,13 +34,17 @@ hipError_t MDA_GCAT(launch_generic_k, MDA_GK)(int S, const GRunDesc *run, const 
     return hipGetLastError();
 }
 
-hipError_t MDA_GCAT(generic_occupancy_k, MDA_GK)(int S, int block, int *blocks_per_cu)
+hipError_t MDA_GCAT(generic_occupancy_k, MDA_GK)(int S, int block, size_t dyn_lds, int *blocks_per_cu)
 {
     switch (S) {
 #define GX(SS)                                                                                                 \
-    case SS:                                                                                                   \
-        return hipOccupancyMaxActiveBlocksPerMultiprocessor(                                                   \
-            blocks_per_cu, k_generic<MDA_GK, (MDA_GK * SS <= 64 ? SS : 8)>, block, 0);
+    case SS: {                                                                                                 \
+        auto kern = k_generic<MDA_GK, (MDA_GK * SS <= 64 ? SS : 8)>;                                           \
+        const hipError_t ea = hipFuncSetAttribute((const void *)kern,                                          \
+                                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)dyn_lds);   \
+        if (ea != hipSuccess) return ea;                                                                       \
+        return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, kern, block, dyn_lds);              \
+    }
         GX(8) GX(16) GX(32) GX(64)
 #undef GX
     default:

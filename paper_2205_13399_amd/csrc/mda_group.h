@@ -408,22 +408,26 @@ __device__ __forceinline__ void g_step(Desc *Dp, const Hot &H, Replica<NS> &S, i
                     S.rngb++;
                     const U4 o = philox10(((uint32_t)((g.i0 + gg) >> 3) << 16) | (uint32_t)g.u, t, (uint32_t)r,
                                           kTagAcc, H.key0, H.key1);
+                    // all eight lookups first, then every slot tested without a
+                    // branch; slots that are not undecided keep their decision
+                    uint32_t Lv[8];
 #pragma unroll
                     for (int f = 0; f < 8; ++f) {
-                        if ((maybe >> f) & 1u) {
-                            const int s = gg + f;
-                            const uint32_t w = (f < 2) ? o.x : (f < 4) ? o.y : (f < 6) ? o.z : o.w;
-                            const uint32_t idx = (w >> (16 * (f & 1))) & 0xFFFu;
-                            const uint32_t u1 = (uint32_t)(max(S.e1[s], EoC) - EoC);
-                            const uint32_t u2 = (uint32_t)(max(S.e2[s], EoC) - EoC);
-                            const uint32_t Sx = strict ? (u1 + u2) : (u1 < u2 ? u1 : u2);
-                            const uint32_t Lk = (uint32_t)L.lnt[idx] & 0xFFFFFu;
-                            const uint64_t low = (uint64_t)Tl * (uint64_t)Lk;
-                            // saturated at 2^32 - 2, above every statistic
-                            const uint64_t t64 = (uint64_t)Th * (uint64_t)Lk + (low >> 24);
-                            const uint32_t thr = t64 < 0xFFFFFFFEull ? (uint32_t)t64 : 0xFFFFFFFEu;
-                            if (Sx <= thr) certain |= (1u << f);
-                        }
+                        const uint32_t w = (f < 2) ? o.x : (f < 4) ? o.y : (f < 6) ? o.z : o.w;
+                        Lv[f] = (uint32_t)L.lnt[(w >> (16 * (f & 1))) & 0xFFFu];
+                    }
+#pragma unroll
+                    for (int f = 0; f < 8; ++f) {
+                        const int s = gg + f;
+                        const uint32_t u1 = (uint32_t)(max(S.e1[s], EoC) - EoC);
+                        const uint32_t u2 = (uint32_t)(max(S.e2[s], EoC) - EoC);
+                        const uint32_t Sx = strict ? (u1 + u2) : (u1 < u2 ? u1 : u2);
+                        const uint32_t Lk = Lv[f] & 0xFFFFFu;
+                        const uint64_t low = (uint64_t)Tl * (uint64_t)Lk;
+                        // the exact threshold, compared in 64 bits
+                        const uint64_t t64 = (uint64_t)Th * (uint64_t)Lk + (low >> 24);
+                        const uint32_t ok = (uint64_t)Sx <= t64 ? 1u : 0u;
+                        certain |= ((maybe >> f) & ok) << f;
                     }
                 }
                 acc |= (uint64_t)certain << gg;

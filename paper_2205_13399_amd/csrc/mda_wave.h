@@ -383,10 +383,8 @@ __device__ __forceinline__ int anneal_step(Desc *Dp, const Hot &H, Replica<NS, F
         const int lane = opaque_lane(lane_);
         // 2. exact acceptance, 8 facilities per random block.  The threshold
         // (T * LNT[k]) >> 24 is formed exactly: with T = Th 2^24 + Tl (T < 2^43,
-        // so Th < 2^19; LNT < 2^20) it equals Th LNT + ((Tl LNT) >> 24).  With
-        // int32 differences each statistic is at most 2^32 - 4 (two parts below
-        // 2^31 - 1), so a threshold saturated at 2^32 - 2 takes the same
-        // decisions; int64 ones compare with the threshold as it is.
+        // so Th < 2^19; LNT < 2^20) it equals Th LNT + ((Tl LNT) >> 24), and the
+        // statistic is compared with it in 64 bits.
         const int64_t T = H.T[ti];
         const uint32_t Th = (uint32_t)((uint64_t)T >> 24), Tl = (uint32_t)T & 0xFFFFFFu;
         uint64_t acc = 0;
@@ -417,9 +415,10 @@ __device__ __forceinline__ int anneal_step(Desc *Dp, const Hot &H, Replica<NS, F
                     const U4 o = philox10(((uint32_t)(g >> 3) << 16) | (uint32_t)lane, t, (uint32_t)r,
                                           kTagAcc, H.key0, H.key1);
                     // the eight -ln lookups are issued together (one LDS wait
-                    // per block, not one per slot) and every slot is decided
-                    // without a branch; slots that are not undecided keep
-                    // their decision through the mask
+                    // per block, not one per slot) and all eight slots are
+                    // tested without a branch (no exec-mask switching per
+                    // slot); slots that are not undecided keep their decision
+                    // through the mask
                     uint32_t Lv[8];
 #pragma unroll
                     for (int f = 0; f < 8; ++f) {
@@ -437,8 +436,8 @@ __device__ __forceinline__ int anneal_step(Desc *Dp, const Hot &H, Replica<NS, F
                         const uint32_t L = Lv[f] & 0xFFFFFu;
                         const uint64_t low = (uint64_t)Tl * (uint64_t)L;   // 24 x 20 bits
                         const uint64_t t64 = (uint64_t)Th * (uint64_t)L + (low >> 24);
-                        const UT thr = wide ? (UT)t64 : (UT)(t64 < 0xFFFFFFFEull ? t64 : 0xFFFFFFFEull);
-                        certain |= (((maybe >> f) & 1u) && Sx <= thr) ? (1u << f) : 0u;
+                        const uint32_t ok = (uint64_t)Sx <= t64 ? 1u : 0u;
+                        certain |= ((maybe >> f) & ok) << f;
                     }
                 }
                 acc |= (uint64_t)certain << g;
