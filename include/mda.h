@@ -440,7 +440,7 @@ void gqubo_free(mda_gqubo *g);
  * of p are those of da_run, with variant MDA_VARIANT_AUTO or
  * MDA_VARIANT_PERSISTENT, graph 0 and waves_per_replica 0 or 1.  Each wave
  * keeps its replica's archive energies in LDS: archive_size * K is at most
- * 18432 (the default archive_size = m always fits; waves_per_block shrinks
+ * 16384 (the default archive_size = m always fits; waves_per_block shrinks
  * until the block's archives fit).  Errors: as da_run, and MDA_EINVAL for the
  * unsupported fields and a larger archive. */
 int gda_run(const mda_gqubo *g, const mda_params *p, mda_grun **out);

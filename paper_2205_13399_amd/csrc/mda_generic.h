@@ -285,8 +285,10 @@ __device__ __forceinline__ void g_archive(GDesc *Dp, GRep<K, S> &G, int r, uint3
 }
 
 // One annealing step t (Algorithm 3 with the offset of Algorithm 1, readings
-// G1-G3).  Returns the flipped bit or -1.
-template <int K, int S, int AM>
+// G1-G3).  Returns the flipped bit or -1.  With THR (steps at the schedule's
+// final, constant temperature) lnt holds the thresholds (T * LNT[k]) >> 24
+// themselves, each below 2^32 - 1.
+template <int K, int S, int AM, bool THR = false>
 __device__ __forceinline__ int g_step(GDesc *Dp, GRep<K, S> &G, int r, uint32_t t, int lane_,
                                       const MDA_LDS int32_t *lnt, int64_t thrmax, MDA_LDS int64_t *AL)
 {
@@ -309,7 +311,7 @@ __device__ __forceinline__ int g_step(GDesc *Dp, GRep<K, S> &G, int r, uint32_t 
     if (cand) {
         G.detailed++;
         const int lane = opaque_lane(lane_);
-        const int64_t T = ro(Dh.T)[ti];
+        const int64_t T = THR ? 0 : ro(Dh.T)[ti];
         const uint32_t Th = (uint32_t)((uint64_t)T >> 24), Tl = (uint32_t)T & 0xFFFFFFu;
         uint64_t acc = 0;
 #pragma unroll
@@ -345,9 +347,14 @@ __device__ __forceinline__ int g_step(GDesc *Dp, GRep<K, S> &G, int r, uint32_t 
                             const uint64_t u = (uint64_t)(uint32_t)(max(G.e[k][g + f], EoC) - EoC);
                             Sx = strict ? Sx + u : (k == 0 ? u : (u < Sx ? u : Sx));
                         }
-                        const uint32_t L = Lv[f] & 0xFFFFFu;
-                        const uint64_t low = (uint64_t)Tl * (uint64_t)L;
-                        const uint64_t thr = (uint64_t)Th * (uint64_t)L + (low >> 24);
+                        uint64_t thr;
+                        if (THR) {
+                            thr = (uint64_t)Lv[f];
+                        } else {
+                            const uint32_t L = Lv[f] & 0xFFFFFu;
+                            const uint64_t low = (uint64_t)Tl * (uint64_t)L;
+                            thr = (uint64_t)Th * (uint64_t)L + (low >> 24);
+                        }
                         certain |= ((maybe >> f) & (Sx <= thr ? 1u : 0u)) << f;
                     }
                 }
@@ -451,8 +458,11 @@ __device__ __forceinline__ void g_export(GDesc *Dp, const GRep<K, S> &G, int r, 
     }
 }
 
+// thrt: the block's thresholds at the final temperature, or NULL when some
+// would not fit 32 bits (then every step forms its thresholds from lnt).
 template <int K, int S, int AM>
-__device__ __forceinline__ void g_run(GDesc *Dp, int r, int lane, const MDA_LDS int32_t *lnt, MDA_LDS int64_t *AL)
+__device__ __forceinline__ void g_run(GDesc *Dp, int r, int lane, const MDA_LDS int32_t *lnt,
+                                      const MDA_LDS int32_t *thrt, MDA_LDS int64_t *AL)
 {
     GRep<K, S> G;
     g_init<K, S>(Dp, G, r, lane);
@@ -460,11 +470,14 @@ __device__ __forceinline__ void g_run(GDesc *Dp, int r, int lane, const MDA_LDS 
     const uint32_t steps = Dp->steps, ntab = Dp->ntab;
     const MDA_CONST int64_t *thrmax = ro(Dp->thrmax);
     int64_t thr = thrmax[0];
-    for (uint32_t t = 1; t <= steps; ++t) {
+    const uint32_t cool = (thrt == nullptr || ntab - 1u > steps) ? steps : ntab - 1u;
+    uint32_t t = 1;
+    for (; t <= cool; ++t) {
         const int64_t thr_next = thrmax[(t < ntab - 1u) ? t : ntab - 1u];
         g_step<K, S, AM>(Dp, G, r, t, lane, lnt, thr, AL);
         thr = thr_next;
     }
+    for (; t <= steps; ++t) g_step<K, S, AM, true>(Dp, G, r, t, lane, thrt, thr, AL);
     g_export<K, S>(Dp, G, r, lane);
 }
 
@@ -474,10 +487,20 @@ template <int K, int S>
 __global__ void __launch_bounds__(256) k_generic(const GRunDesc *run, const int32_t *lnt_)
 {
     __shared__ int32_t lnt_lds[4096];
+    __shared__ int32_t thr_lds[4096];
     extern __shared__ int64_t garch_lds[];
-    for (int k = (int)threadIdx.x; k < 4096; k += (int)blockDim.x) lnt_lds[k] = ((const MDA_GLOBAL int32_t *)lnt_)[k];
+    // every wave of the launch runs the same schedule: the thresholds of the
+    // final temperature, (T * LNT[k]) >> 24, are formed once per block
+    const uint64_t Tf = (uint64_t)ro(run)->T[ro(run)->ntab - 1u];
+    const bool use_thr = ((Tf * (uint64_t)(((const MDA_GLOBAL int32_t *)lnt_)[0] & 0xFFFFF)) >> 24) < 0xFFFFFFFFull;
+    for (int k = (int)threadIdx.x; k < 4096; k += (int)blockDim.x) {
+        const int32_t L = ((const MDA_GLOBAL int32_t *)lnt_)[k];
+        lnt_lds[k] = L;
+        thr_lds[k] = (int32_t)(uint32_t)((Tf * (uint64_t)(L & 0xFFFFF)) >> 24);
+    }
     __syncthreads();
     const MDA_LDS int32_t *lnt = (const MDA_LDS int32_t *)lnt_lds;
+    const MDA_LDS int32_t *thrt = use_thr ? (const MDA_LDS int32_t *)thr_lds : nullptr;
     const int lane = __lane_id();
     const int wpb = (int)(blockDim.x >> 6);
     const int wave = uni((int)(blockIdx.x * wpb + (threadIdx.x >> 6)));
@@ -487,8 +510,8 @@ __global__ void __launch_bounds__(256) k_generic(const GRunDesc *run, const int3
     const bool strict = Dp->accept == 0;
     MDA_LDS int64_t *AL = (MDA_LDS int64_t *)(garch_lds + (size_t)(threadIdx.x >> 6) * Dp->s * K);
     for (int r = wave; r < R; r += nwaves) {
-        if (strict) g_run<K, S, kAmStrict>(Dp, r, lane, lnt, AL);
-        else g_run<K, S, kAmLenient>(Dp, r, lane, lnt, AL);
+        if (strict) g_run<K, S, kAmStrict>(Dp, r, lane, lnt, thrt, AL);
+        else g_run<K, S, kAmLenient>(Dp, r, lane, lnt, thrt, AL);
     }
 }
 

@@ -35,8 +35,9 @@ hipError_t launch_gxgather(const int64_t *at, int64_t n, const uint64_t *archX, 
 
 using namespace mda;
 
-// LDS of one workgroup on gfx950 and the part the -ln table takes
-constexpr size_t kLdsBytes = 160 * 1024, kLntBytes = 4096 * sizeof(int32_t);
+// LDS of one workgroup on gfx950 and the part the two 4096-entry tables take
+// (the -ln table and the thresholds at the final temperature)
+constexpr size_t kLdsBytes = 160 * 1024, kLntBytes = 2 * 4096 * sizeof(int32_t);
 
 struct mda_gqubo {
     int32_t m = 0, K = 0, S = 0, nl = 0;
@@ -257,8 +258,8 @@ extern "C" int gda_run(const mda_gqubo *gc, const mda_params *pin, mda_grun **ou
     int dev = 0, cus = 0, per_cu = 0;
     HIP_TRY(hipGetDevice(&dev));
     HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
-    // each wave keeps its replica's archive energies in LDS beside the 16 KB
-    // -ln table: as many waves per block as fit (up to the requested count)
+    // each wave keeps its replica's archive energies in LDS beside the two
+    // 16 KB tables: as many waves per block as fit (up to the requested count)
     const size_t per_wave = (size_t)s * K * sizeof(int64_t);
     int wpb = (p.waves_per_block >= 1 && p.waves_per_block <= 4) ? p.waves_per_block : 4;
     while (wpb > 1 && kLdsBytes - kLntBytes < wpb * per_wave) --wpb;

@@ -348,8 +348,11 @@ __device__ __forceinline__ void group_minima(Replica<NS, FT> &S)
 }
 
 // One annealing step t of replica r whose largest acceptance threshold
-// (T_t * LNT[0]) >> 24 is thrmax.  Returns the flipped bit or -1.
-template <int NS, int PV, int AM, class FT, class LP>
+// (T_t * LNT[0]) >> 24 is thrmax.  Returns the flipped bit or -1.  lnt is the
+// -ln table; with THR (int32 differences at the schedule's final, constant
+// temperature) it holds the thresholds (T * LNT[k]) >> 24 themselves,
+// saturated at 2^32 - 1 (above every statistic, so the decisions are the same).
+template <int NS, int PV, int AM, class FT, class LP, bool THR = false>
 __device__ __forceinline__ int anneal_step(Desc *Dp, const Hot &H, Replica<NS, FT> &S, int r, uint32_t t, int lane_,
                                            LP lnt, int64_t thrmax)
 {
@@ -385,7 +388,7 @@ __device__ __forceinline__ int anneal_step(Desc *Dp, const Hot &H, Replica<NS, F
         // (T * LNT[k]) >> 24 is formed exactly: with T = Th 2^24 + Tl (T < 2^43,
         // so Th < 2^19; LNT < 2^20) it equals Th LNT + ((Tl LNT) >> 24), and the
         // statistic is compared with it in 64 bits.
-        const int64_t T = H.T[ti];
+        const int64_t T = THR ? 0 : H.T[ti];
         const uint32_t Th = (uint32_t)((uint64_t)T >> 24), Tl = (uint32_t)T & 0xFFFFFFu;
         uint64_t acc = 0;
         const int ng = opaque(n);
@@ -433,10 +436,15 @@ __device__ __forceinline__ int anneal_step(Desc *Dp, const Hot &H, Replica<NS, F
                         const UT u1 = (UT)(max(S.e1[i], EoC) - EoC);
                         const UT u2 = (UT)(max(S.e2[i], EoC) - EoC);
                         const UT Sx = strict ? (u1 + u2) : (u1 < u2 ? u1 : u2);
-                        const uint32_t L = Lv[f] & 0xFFFFFu;
-                        const uint64_t low = (uint64_t)Tl * (uint64_t)L;   // 24 x 20 bits
-                        const uint64_t t64 = (uint64_t)Th * (uint64_t)L + (low >> 24);
-                        const uint32_t ok = (uint64_t)Sx <= t64 ? 1u : 0u;
+                        uint32_t ok;
+                        if (THR) {
+                            ok = (uint64_t)Sx <= (uint64_t)Lv[f] ? 1u : 0u;
+                        } else {
+                            const uint32_t L = Lv[f] & 0xFFFFFu;
+                            const uint64_t low = (uint64_t)Tl * (uint64_t)L;   // 24 x 20 bits
+                            const uint64_t t64 = (uint64_t)Th * (uint64_t)L + (low >> 24);
+                            ok = (uint64_t)Sx <= t64 ? 1u : 0u;
+                        }
                         certain |= ((maybe >> f) & ok) << f;
                     }
                 }
@@ -536,21 +544,42 @@ __device__ __forceinline__ int64_t thr_entry(const Hot &H, uint32_t k)
     return sizeof(FT) == 8 ? H.thrmax64[k] : (int64_t)H.thrmax[k];
 }
 
-// All steps of one replica with its state in registers.
+// All steps of one replica with its state in registers.  tab is the wave's
+// 4096 words of LDS: the -ln table (copied from lnt_g) while the temperature
+// changes; from step ntab on, where it stays at its last value, the int32 build
+// replaces each LNT[k] by the threshold (T * LNT[k]) >> 24 of that temperature.
 template <int NS, int PV, int AM, class FT>
-__device__ __forceinline__ void run_replica(Desc *Dp, int r, int lane, const MDA_LDS int32_t *lnt)
+__device__ __forceinline__ void run_replica(Desc *Dp, int r, int lane, MDA_LDS int32_t *tab,
+                                            const MDA_GLOBAL int32_t *lnt_g)
 {
+    constexpr bool wide = sizeof(FT) == 8;
+#pragma unroll 8
+    for (int k = lane; k < 4096; k += 64) tab[k] = lnt_g[k];
     Replica<NS, FT> S;
     init_replica<NS, PV>(Dp, S, r, lane);
     group_minima<NS, AM>(S);
     const Hot H = load_hot(Dp);
     // the next step's threshold is loaded one step ahead
     int64_t thr = thr_entry<FT>(H, 0);
-    for (uint32_t t = 1; t <= H.steps; ++t) {
+    const uint32_t cool = wide ? H.steps : ((H.ntab - 1u < H.steps) ? H.ntab - 1u : H.steps);
+    uint32_t t = 1;
+    for (; t <= cool; ++t) {
         // entry of step t + 1: min(t + 1, ntab) - 1 = min(t, ntab - 1), ntab >= 1
         const int64_t thr_next = thr_entry<FT>(H, (t < H.ntab - 1u) ? t : H.ntab - 1u);
-        anneal_step<NS, PV, AM>(Dp, H, S, r, t, lane, lnt, thr);
+        anneal_step<NS, PV, AM>(Dp, H, S, r, t, lane, (const MDA_LDS int32_t *)tab, thr);
         thr = thr_next;
+    }
+    if (!wide && t <= H.steps) {
+        const uint64_t T = (uint64_t)H.T[H.ntab - 1u];
+#pragma unroll 8
+        for (int k = lane; k < 4096; k += 64) {
+            // T < 2^43 and LNT < 2^20: the product fits 64 bits
+            const uint64_t v = (T * (uint64_t)((uint32_t)tab[k] & 0xFFFFFu)) >> 24;
+            tab[k] = (int32_t)(uint32_t)(v < 0xFFFFFFFFull ? v : 0xFFFFFFFFull);
+        }
+        for (; t <= H.steps; ++t)
+            anneal_step<NS, PV, AM, FT, const MDA_LDS int32_t *, true>(Dp, H, S, r, t, lane,
+                                                                      (const MDA_LDS int32_t *)tab, thr);
     }
     export_replica<NS>(Dp, S, r, lane);
 }
@@ -574,11 +603,11 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(OCC)))
                                                     const int32_t *lnt_)
 {
     using FT = typename std::conditional<F64 != 0, int64_t, int32_t>::type;
-    // the -ln table, read at random by the exact acceptance test, lives in LDS
-    __shared__ int32_t lnt_lds[4096];
-    for (int k = (int)threadIdx.x; k < 4096; k += (int)blockDim.x) lnt_lds[k] = ((const MDA_GLOBAL int32_t *)lnt_)[k];
-    __syncthreads();
-    const MDA_LDS int32_t *lnt = (const MDA_LDS int32_t *)lnt_lds;
+    // dynamic LDS: 4096 words per wave, read at random by the exact
+    // acceptance test (see run_replica)
+    extern __shared__ int32_t wave_tab[];
+    MDA_LDS int32_t *tab = (MDA_LDS int32_t *)(wave_tab + (threadIdx.x >> 6) * 4096);
+    const MDA_GLOBAL int32_t *lnt = (const MDA_GLOBAL int32_t *)lnt_;
     const int lane = __lane_id();
     const int wpb = (int)(blockDim.x >> 6);
     const int wave = uni((int)(blockIdx.x * wpb + (threadIdx.x >> 6)));
@@ -590,7 +619,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(OCC)))
         switch (step_variant(Dp)) {
 #define X(PV, AM)                                        \
     case PV * 2 + AM:                                    \
-        run_replica<NS, PV, AM, FT>(Dp, r, lane, lnt); \
+        run_replica<NS, PV, AM, FT>(Dp, r, lane, tab, lnt); \
         break;
             MDA_STEP_VARIANTS(X)
 #undef X

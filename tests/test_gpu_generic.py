@@ -252,10 +252,10 @@ def test_generic_errors(mda):
             mda.gda_run(g, mda.make_params(args["replicas"], args["steps"], 1, **extra))
         assert e.value.code == mda.MDA_EINVAL, kw
     g3 = mda.GQubo(np.zeros((3, 64, 64), np.int32))
-    with pytest.raises(mda.MdaError) as e:            # 6145 x 3 energies exceed a wave's LDS share
-        mda.gda_run(g3, mda.make_params(2, 10, 1, archive_size=6145))
+    with pytest.raises(mda.MdaError) as e:            # 5462 x 3 energies exceed a wave's LDS share
+        mda.gda_run(g3, mda.make_params(2, 10, 1, archive_size=5462))
     assert e.value.code == mda.MDA_EINVAL
-    run = mda.gda_run(g3, mda.make_params(2, 10, 1, archive_size=6144))   # the largest: one wave per block
+    run = mda.gda_run(g3, mda.make_params(2, 10, 1, archive_size=5461))   # the largest: one wave per block
     run.sync()
     run = mda.gda_run(g, mda.make_params(2, 10, 1))
     with pytest.raises(mda.MdaError):

@@ -61,6 +61,29 @@ def test_modes(mda, n, path, accept, archive, escape, asize):
                archive_size=asize)
 
 
+@pytest.mark.parametrize("n,path,accept,archive,escape", [
+    (5, 1, 0, 0, 0), (9, 2, 1, 0, 0), (17, 2, 0, 1, 1), (24, 1, 1, 1, 0), (33, 2, 0, 0, 1), (50, 2, 1, 0, 0),
+    (64, 1, 0, 0, 0)])
+def test_final_temperature_thresholds(mda, n, path, accept, archive, escape):
+    """A fast schedule (xi = 0.02) that reaches its final temperature after a
+    few hundred steps: most steps take their thresholds from the table of the
+    final temperature in LDS; every replica against the oracle."""
+    inst = synth.make_instance(n, -0.3, seed=300 + n)
+    oq = oracle.Qubo(inst.F1, inst.F2, inst.D, 0)
+    steps, seed = 3000, 40 + n
+    d0, df, _, _ = oracle.default_schedule(oq.maxabs_c, steps)
+    beta = max(1, int(d0 // steps))
+    R = 6 if n < 40 else 3
+    q, run = _run(mda, inst, R, steps, seed, path=path, delta0=d0, deltaf=df, xi=0.02, beta=beta, accept=accept,
+                  archive=archive, escape=escape)
+    assert run.params.steps == steps
+    okw = oracle_kwargs(oq, steps, seed, accept=accept, archive=archive, escape=escape,
+                        schedule=(d0, df, 0.02, beta))
+    res = run_replicas(inst.F1, inst.F2, inst.D, range(R), **okw)
+    for r in range(R):
+        compare_replica(run, res[r], r, label="n=%d path=%d xi=0.02" % (n, path))
+
+
 @pytest.mark.parametrize("n", [4, 7, 9])
 def test_general_kronecker_nonsymmetric(mda, n):
     """Non-symmetric flows and distances with non-zero diagonals (two-product column)."""
