@@ -70,17 +70,15 @@ __device__ __forceinline__ GDesc *gcold(GDesc *p)
     return (GDesc *)(((uint64_t)hi << 32) | lo);
 }
 
-// p dominates q over K objectives (Section 3.3): <= in every one, not equal in all.
+// p dominates q over K objectives (Section 3.3): <= in every one, not equal in
+// all; as for two objectives, exactly when the OR of the q_k - p_k is positive.
 template <int K>
 __device__ __forceinline__ bool gdom(const int64_t *p, const int64_t *q)
 {
-    bool le = true, eq = true;
+    int64_t o = q[0] - p[0];
 #pragma unroll
-    for (int k = 0; k < K; ++k) {
-        le = le && p[k] <= q[k];
-        eq = eq && p[k] == q[k];
-    }
-    return le && !eq;
+    for (int k = 1; k < K; ++k) o |= q[k] - p[k];
+    return o > 0;
 }
 
 template <int K, int S, int AM>
@@ -481,10 +479,11 @@ __device__ __forceinline__ void g_run(GDesc *Dp, int r, int lane, const MDA_LDS 
     g_export<K, S>(Dp, G, r, lane);
 }
 
-// Persistent form: wave w of the grid runs replicas w, w + W, ... of one run.
+// Persistent form: wave w of the grid runs replica w, then whichever replica
+// comes next when it finishes (from the launch's counter, zero at launch).
 // Dynamic LDS: s * K int64 archive energies per wave of the block.
 template <int K, int S>
-__global__ void __launch_bounds__(256) k_generic(const GRunDesc *run, const int32_t *lnt_)
+__global__ void __launch_bounds__(256) k_generic(const GRunDesc *run, const int32_t *lnt_, unsigned int *next)
 {
     __shared__ int32_t lnt_lds[4096];
     __shared__ int32_t thr_lds[4096];
@@ -509,7 +508,7 @@ __global__ void __launch_bounds__(256) k_generic(const GRunDesc *run, const int3
     const int R = Dp->R;
     const bool strict = Dp->accept == 0;
     MDA_LDS int64_t *AL = (MDA_LDS int64_t *)(garch_lds + (size_t)(threadIdx.x >> 6) * Dp->s * K);
-    for (int r = wave; r < R; r += nwaves) {
+    for (int r = wave; r < R; r = nwaves + next_item(next, lane)) {
         if (strict) g_run<K, S, kAmStrict>(Dp, r, lane, lnt, thrt, AL);
         else g_run<K, S, kAmLenient>(Dp, r, lane, lnt, thrt, AL);
     }

@@ -16,8 +16,8 @@
 
 namespace mda {
 #define MDA_GK_DECL(K)                                                                                      \
-    hipError_t launch_generic_k##K(int S, const GRunDesc *run, const int32_t *lnt, int grid, int block,     \
-                                   size_t dyn_lds, hipStream_t stream, int R);                              \
+    hipError_t launch_generic_k##K(int S, const GRunDesc *run, const int32_t *lnt, unsigned int *next,      \
+                                   int grid, int block, size_t dyn_lds, hipStream_t stream, int R);         \
     hipError_t generic_occupancy_k##K(int S, int block, size_t dyn_lds, int *blocks_per_cu);
 #define MDA_GF_DECL(K)                                                                                      \
     hipError_t launch_gfront_k##K(const GRunDesc *run, int r0, int nr, const int64_t *offs, int64_t total,      \
@@ -28,6 +28,7 @@ namespace mda {
 MDA_GK_DECL(1) MDA_GK_DECL(2) MDA_GK_DECL(3) MDA_GK_DECL(4)
 MDA_GF_DECL(1) MDA_GF_DECL(2) MDA_GF_DECL(3) MDA_GF_DECL(4)
 #undef MDA_GF_DECL
+hipError_t launch_zero_counter(unsigned int *p, hipStream_t stream);
 hipError_t launch_gxgather(const int64_t *at, int64_t n, const uint64_t *archX, int s, int nl, uint64_t *out,
                            hipStream_t stream);
 #undef MDA_GK_DECL
@@ -234,6 +235,7 @@ extern "C" int gda_run(const mda_gqubo *gc, const mda_params *pin, mda_grun **ou
     DevPool &pool = r->pool;
     GRunDesc *ddesc = pool.alloc<GRunDesc>(1, stream);
     int32_t *dlnt = pool.alloc<int32_t>(4096, stream);
+    unsigned int *dnext = pool.alloc<unsigned int>(1, stream);
     int64_t *dT = pool.alloc<int64_t>(T.size(), stream);
     int64_t *dthr = pool.alloc<int64_t>(T.size(), stream);
     d.x = pool.alloc<uint64_t>((size_t)R * 64, stream);
@@ -243,7 +245,7 @@ extern "C" int gda_run(const mda_gqubo *gc, const mda_params *pin, mda_grun **ou
     d.archX = pool.alloc<uint64_t>((size_t)R * s * d.nl, stream);
     d.nd = pool.alloc<uint8_t>((size_t)R * s, stream);
     d.trace = pool.alloc<int32_t>((size_t)std::max(1, p.trace_replicas) * (size_t)(p.trace_replicas ? p.steps : 1), stream);
-    if (!ddesc || !dlnt || !dT || !dthr || !d.x || !d.h || !d.st || !d.archE || !d.archX || !d.nd || !d.trace)
+    if (!ddesc || !dlnt || !dnext || !dT || !dthr || !d.x || !d.h || !d.st || !d.archE || !d.archX || !d.nd || !d.trace)
         return fail(MDA_ENOMEM, "device allocation failed for the run (%lld bytes so far)", (long long)pool.total);
     d.T = dT;
     d.thrmax = dthr;
@@ -277,13 +279,14 @@ extern "C" int gda_run(const mda_gqubo *gc, const mda_params *pin, mda_grun **ou
     int grid = cus * per_cu;
     const int need = (R + block / 64 - 1) / (block / 64);
     if (grid > need) grid = need;
+    HIP_TRY(launch_zero_counter(dnext, stream));
     HIP_TRY(hipEventRecord(r->ek0, stream));
     hipError_t le = hipErrorInvalidValue;
     switch (K) {
-    case 1: le = launch_generic_k1(g->S, ddesc, dlnt, grid, block, dyn, stream, R); break;
-    case 2: le = launch_generic_k2(g->S, ddesc, dlnt, grid, block, dyn, stream, R); break;
-    case 3: le = launch_generic_k3(g->S, ddesc, dlnt, grid, block, dyn, stream, R); break;
-    default: le = launch_generic_k4(g->S, ddesc, dlnt, grid, block, dyn, stream, R); break;
+    case 1: le = launch_generic_k1(g->S, ddesc, dlnt, dnext, grid, block, dyn, stream, R); break;
+    case 2: le = launch_generic_k2(g->S, ddesc, dlnt, dnext, grid, block, dyn, stream, R); break;
+    case 3: le = launch_generic_k3(g->S, ddesc, dlnt, dnext, grid, block, dyn, stream, R); break;
+    default: le = launch_generic_k4(g->S, ddesc, dlnt, dnext, grid, block, dyn, stream, R); break;
     }
     if (le != hipSuccess)
         return fail(MDA_EDEVICE, "generic launch (K %d, S %d, grid %d) failed: %s", K, g->S, grid, hipGetErrorString(le));

@@ -10,8 +10,8 @@ namespace mda {
 #define MDA_GCAT2(a, b) a##b
 #define MDA_GCAT(a, b) MDA_GCAT2(a, b)
 
-hipError_t MDA_GCAT(launch_generic_k, MDA_GK)(int S, const GRunDesc *run, const int32_t *lnt, int grid, int block,
-                                             size_t dyn_lds, hipStream_t stream, int R)
+hipError_t MDA_GCAT(launch_generic_k, MDA_GK)(int S, const GRunDesc *run, const int32_t *lnt, unsigned int *next,
+                                             int grid, int block, size_t dyn_lds, hipStream_t stream, int R)
 {
     const int nd_grid = (R * 64 + 255) / 256;
     switch (S) {
@@ -22,7 +22,7 @@ hipError_t MDA_GCAT(launch_generic_k, MDA_GK)(int S, const GRunDesc *run, const 
         const hipError_t ea = hipFuncSetAttribute((const void *)kern,                                        \
                                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)dyn_lds); \
         if (ea != hipSuccess) return ea;                                                                     \
-        hipLaunchKernelGGL(kern, dim3(grid), dim3(block), dyn_lds, stream, run, lnt);                        \
+        hipLaunchKernelGGL(kern, dim3(grid), dim3(block), dyn_lds, stream, run, lnt, next);                  \
         break;                                                                                               \
     }
         GX(8) GX(16) GX(32) GX(64)

@@ -27,7 +27,7 @@ hipError_t launch_group(int ns, int occ, int wr, int wc, const RunDesc *runs, co
                         const int32_t *lnt, int grid, hipStream_t stream);
 hipError_t group_occupancy(int ns, int occ, int wr, int wc, int *blocks_per_cu);
 hipError_t launch_persistent(int ns, int occ, int f64, const RunDesc *runs, const WorkItem *work, int nwork,
-                             const int32_t *lnt, int grid, int block, hipStream_t stream);
+                             const int32_t *lnt, unsigned int *next, int grid, int block, hipStream_t stream);
 hipError_t launch_plain(int ns, const RunDesc *run, int R, uint32_t steps, const int32_t *lnt, int block,
                         hipStream_t stream);
 hipError_t launch_nondominated(const RunDesc *runs, const WorkItem *work, int nwork, hipStream_t stream);
@@ -596,6 +596,7 @@ struct Launch {
     WorkItem *dwork = nullptr;
     int nwork = 0;
     int32_t *dlnt = nullptr;
+    unsigned int *dctr = nullptr;   // work-item counters, one per group
     hipStream_t stream = nullptr;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;   // whole run
     hipEvent_t evk0 = nullptr, evk1 = nullptr; // annealing kernel(s) only
@@ -834,10 +835,14 @@ struct Group {
     int ns, wr, wc, f64, off, cnt;
 };
 
+// Work-item counters a launch holds: one per group (register tile, layout and
+// field width; far fewer combinations exist).
+constexpr int kMaxGroups = 64;
+
 // Work list of a launch: runs grouped by register tile, largest tile first
 // (one persistent launch per tile, each with the occupancy of its own register
-// budget); within a tile, largest instances first so that the round-robin
-// assignment ends with the short items.
+// budget); within a tile, largest instances first so that the items taken
+// last, as waves become free, are the short ones.
 void plan_work(const std::vector<RunDesc> &descs, std::vector<WorkItem> &work, std::vector<Group> &groups)
 {
     const int count = (int)descs.size();
@@ -868,8 +873,12 @@ void plan_work(const std::vector<RunDesc> &descs, std::vector<WorkItem> &work, s
 // dwork and dlnt are the device copies of the descriptors, the work list and
 // the -ln table; cus is the device's compute-unit count.
 int enqueue_anneal(const std::vector<Group> &groups, const RunDesc &first, bool plain, const RunDesc *ddesc,
-                   const WorkItem *dwork, const int32_t *dlnt, int block, int cus, hipStream_t stream)
+                   const WorkItem *dwork, const int32_t *dlnt, unsigned int *dctr, int block, int cus,
+                   hipStream_t stream)
 {
+    if (!plain && groups.size() > kMaxGroups)
+        return fail(MDA_EINVAL, "%zu register tiles in one launch (at most %d)", groups.size(), kMaxGroups);
+    int gi = 0;
     if (plain) {
         HIP_TRY(launch_plain(groups[0].ns, ddesc, first.R, first.steps, dlnt, block, stream));
         return MDA_OK;
@@ -891,8 +900,8 @@ int enqueue_anneal(const std::vector<Group> &groups, const RunDesc &first, bool 
             int grid = cus * per_cu;
             const int need = (g.cnt + wpb - 1) / wpb;
             if (grid > need) grid = need;
-            const hipError_t le =
-                launch_persistent(g.ns, occ, g.f64, ddesc, dwork + g.off, g.cnt, dlnt, grid, block, stream);
+            const hipError_t le = launch_persistent(g.ns, occ, g.f64, ddesc, dwork + g.off, g.cnt, dlnt, dctr + gi,
+                                                    grid, block, stream);
             if (le != hipSuccess)
                 return fail(MDA_EDEVICE, "persistent launch (ns %d, grid %d, block %d, %d blocks/CU) failed: %s", g.ns,
                             grid, block, per_cu, hipGetErrorString(le));
@@ -913,6 +922,7 @@ int enqueue_anneal(const std::vector<Group> &groups, const RunDesc &first, bool 
                 return fail(MDA_EDEVICE, "workgroup launch (ns %d, %d x %d waves, grid %d, %d blocks/CU) failed: %s",
                             g.ns, g.wr, g.wc, grid, per_cu, hipGetErrorString(le));
         }
+        ++gi;
     }
     return MDA_OK;
 }
@@ -958,7 +968,8 @@ extern "C" int da_run_batch(const mda_qubo *const *qs, const mda_params *ps, int
     L->ddesc = L->pool.alloc<RunDesc>(descs.size(), stream);
     L->dwork = L->pool.alloc<WorkItem>(work.size(), stream);
     L->dlnt = L->pool.alloc<int32_t>(4096, stream);
-    if (!L->ddesc || !L->dwork || !L->dlnt) return fail(MDA_ENOMEM, "device allocation failed");
+    L->dctr = L->pool.alloc<unsigned int>(kMaxGroups, stream);
+    if (!L->ddesc || !L->dwork || !L->dlnt || !L->dctr) return fail(MDA_ENOMEM, "device allocation failed");
     int32_t lnt[4096];
     threshold_table(lnt);
     HIP_TRY(hipMemcpyAsync(L->ddesc, descs.data(), descs.size() * sizeof(RunDesc), hipMemcpyHostToDevice, stream));
@@ -977,7 +988,8 @@ extern "C" int da_run_batch(const mda_qubo *const *qs, const mda_params *ps, int
     // flags.  Either enqueued directly or captured into one graph.
     auto enqueue = [&](bool timed) -> int {
         if (timed) HIP_TRY(hipEventRecord(L->evk0, stream));
-        const int rc = enqueue_anneal(groups, descs[0], plain, L->ddesc, L->dwork, L->dlnt, block, cus, stream);
+        const int rc = enqueue_anneal(groups, descs[0], plain, L->ddesc, L->dwork, L->dlnt, L->dctr, block, cus,
+                                      stream);
         if (rc) return rc;
         if (timed) HIP_TRY(hipEventRecord(L->evk1, stream));
         HIP_TRY(launch_nondominated(L->ddesc, L->dwork, L->nwork, stream));
@@ -1092,14 +1104,15 @@ size_t align256(size_t b)
 // Byte offsets of the parts of the scratch area for R work items and ntab
 // table entries; returns the total.
 struct ScratchPlan {
-    size_t desc, work, lnt, T, thr, thr64, total;
+    size_t desc, ctr, work, lnt, T, thr, thr64, total;
 };
 
 ScratchPlan scratch_plan(int64_t R, int64_t ntab)
 {
     ScratchPlan sp;
     sp.desc = 0;
-    sp.work = sp.desc + align256(sizeof(RunDesc));
+    sp.ctr = sp.desc + align256(sizeof(RunDesc));
+    sp.work = sp.ctr + align256(kMaxGroups * sizeof(unsigned int));
     sp.lnt = sp.work + align256((size_t)R * sizeof(WorkItem));
     sp.T = sp.lnt + align256(4096 * sizeof(int32_t));
     sp.thr = sp.T + align256((size_t)ntab * sizeof(int64_t));
@@ -1211,7 +1224,8 @@ extern "C" int da_run_noalloc(const mda_qubo *q, const mda_params *pin, const md
     int dev = 0, cus = 0;
     HIP_TRY(hipGetDevice(&dev));
     HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
-    rc = enqueue_anneal(groups, d, false, ddesc, dwork, dlnt, default_block(p.waves_per_block), cus, stream);
+    rc = enqueue_anneal(groups, d, false, ddesc, dwork, dlnt, reinterpret_cast<unsigned int *>(sb + sp.ctr),
+                        default_block(p.waves_per_block), cus, stream);
     if (rc) return rc;
     HIP_TRY(launch_nondominated(ddesc, dwork, (int)work.size(), stream));
     return MDA_OK;

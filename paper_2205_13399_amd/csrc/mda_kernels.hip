@@ -129,24 +129,40 @@ int ns_for(int n)
 // that tile (mda_wave_ns*.hip), so that the tiles compile in parallel.
 #define MDA_WAVE_DECL(N)                                                                                   \
     hipError_t launch_persistent_ns##N(int occ, const RunDesc *runs, const WorkItem *work, int nwork,      \
-                                       const int32_t *lnt, int grid, int block, hipStream_t stream);       \
+                                       const int32_t *lnt, unsigned int *next, int grid, int block,        \
+                                       hipStream_t stream);                                                \
     hipError_t persistent_occupancy_ns##N(int occ, int block, int *blocks_per_cu);                        \
     hipError_t launch_plain_ns##N(const RunDesc *run, int R, uint32_t steps, const int32_t *lnt, int block, \
                                   hipStream_t stream);                                                     \
     hipError_t launch_persistent64_ns##N(const RunDesc *runs, const WorkItem *work, int nwork,             \
-                                         const int32_t *lnt, int grid, int block, hipStream_t stream);     \
+                                         const int32_t *lnt, unsigned int *next, int grid, int block,      \
+                                         hipStream_t stream);                                              \
     hipError_t persistent64_occupancy_ns##N(int block, int *blocks_per_cu);
 MDA_NS_LIST(MDA_WAVE_DECL)
 #undef MDA_WAVE_DECL
 
-hipError_t launch_persistent(int ns, int occ, int f64, const RunDesc *runs, const WorkItem *work, int nwork,
-                             const int32_t *lnt, int grid, int block, hipStream_t stream)
+__global__ void k_zero_counter(unsigned int *p)
 {
+    if (threadIdx.x == 0) *p = 0u;
+}
+
+hipError_t launch_zero_counter(unsigned int *p, hipStream_t stream)
+{
+    hipLaunchKernelGGL(k_zero_counter, dim3(1), dim3(64), 0, stream, p);
+    return hipGetLastError();
+}
+
+// The persistent launch of one tile, preceded by the zeroing of its work-item
+// counter (a kernel, so that the pair can be captured into a graph).
+hipError_t launch_persistent(int ns, int occ, int f64, const RunDesc *runs, const WorkItem *work, int nwork,
+                             const int32_t *lnt, unsigned int *next, int grid, int block, hipStream_t stream)
+{
+    hipLaunchKernelGGL(k_zero_counter, dim3(1), dim3(64), 0, stream, next);
     switch (ns) {
 #define X(N)                                                                                       \
     case N:                                                                                        \
-        return f64 ? launch_persistent64_ns##N(runs, work, nwork, lnt, grid, block, stream)       \
-                   : launch_persistent_ns##N(occ, runs, work, nwork, lnt, grid, block, stream);
+        return f64 ? launch_persistent64_ns##N(runs, work, nwork, lnt, next, grid, block, stream) \
+                   : launch_persistent_ns##N(occ, runs, work, nwork, lnt, next, grid, block, stream);
         MDA_NS_LIST(X)
 #undef X
     default:

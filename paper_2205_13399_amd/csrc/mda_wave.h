@@ -588,9 +588,12 @@ __device__ __forceinline__ void run_replica(Desc *Dp, int r, int lane, MDA_LDS i
     X(kPvDense, kAmStrict) X(kPvDense, kAmLenient) X(kPvKronSym, kAmStrict) X(kPvKronSym, kAmLenient) \
     X(kPvKronGen, kAmStrict) X(kPvKronGen, kAmLenient)
 
-// Persistent form: wave w of the grid runs work items w, w + W, w + 2W, ...
-// (W waves in the grid; the host orders the items largest first), each for
-// all of its steps with the replica state in registers.  From 40 slots up the
+// Persistent form: wave w of the grid runs work item w, then whichever item
+// comes next in the list when it finishes (W waves in the grid; the host
+// orders the items largest first), each for all of its steps with the replica
+// state in registers.  Replicas of one instance can differ a lot in length (an
+// archive that grows large makes every move scan it), so a fixed assignment of
+// items to waves would leave the launch waiting for its unluckiest wave.  From 40 slots up the
 // kernel holds one wave per SIMD (OCC = 1); the OCC = 2 build keeps part of the
 // cold-path state (initial fields, restarts, archive scans) in scratch so that
 // a second wave per SIMD hides the latency of the first.  The host takes it
@@ -600,7 +603,7 @@ __device__ __forceinline__ void run_replica(Desc *Dp, int r, int lane, MDA_LDS i
 // F64 = 1: the int64-difference build (one wave per SIMD).
 template <int NS, int OCC, int F64>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(OCC))) k_persistent(const RunDesc *runs, const WorkItem *work, int nwork,
-                                                    const int32_t *lnt_)
+                                                    const int32_t *lnt_, unsigned int *next)
 {
     using FT = typename std::conditional<F64 != 0, int64_t, int32_t>::type;
     // dynamic LDS: 4096 words per wave, read at random by the exact
@@ -612,7 +615,10 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(OCC)))
     const int wpb = (int)(blockDim.x >> 6);
     const int wave = uni((int)(blockIdx.x * wpb + (threadIdx.x >> 6)));
     const int nwaves = (int)gridDim.x * wpb;
-    for (int item = wave; item < nwork; item += nwaves) {
+    // work items are taken in list order (largest first): a wave's first is
+    // its own index, every later one comes from the launch's counter (zero at
+    // launch), so that waves whose replicas run long take fewer of them
+    for (int item = wave; item < nwork; item = nwaves + next_item(next, lane)) {
         const WorkItem w = {ro(work)[item].run, ro(work)[item].replica};
         Desc *Dp = ro(runs) + uni(w.run);
         const int r = uni(w.replica);

@@ -20,10 +20,11 @@ inline size_t persistent_lds(int block)
 // int64 differences: one build, the natural register budget (its state is
 // twice that of the int32 build, so a second wave per SIMD would only spill).
 hipError_t MDA_CAT(launch_persistent64_ns, MDA_TILE)(const RunDesc *runs, const WorkItem *work, int nwork,
-                                                    const int32_t *lnt, int grid, int block, hipStream_t stream)
+                                                    const int32_t *lnt, unsigned int *next, int grid, int block,
+                                                    hipStream_t stream)
 {
     hipLaunchKernelGGL((k_persistent<MDA_TILE, 1, 1>), dim3(grid), dim3(block), persistent_lds(block), stream, runs,
-                       work, nwork, lnt);
+                       work, nwork, lnt, next);
     return hipGetLastError();
 }
 
@@ -37,15 +38,16 @@ hipError_t MDA_CAT(persistent64_occupancy_ns, MDA_TILE)(int block, int *blocks_p
 constexpr int kTileOcc2 = MDA_TILE >= 40 ? 2 : 1;
 
 hipError_t MDA_CAT(launch_persistent_ns, MDA_TILE)(int occ, const RunDesc *runs, const WorkItem *work, int nwork,
-                                                  const int32_t *lnt, int grid, int block, hipStream_t stream)
+                                                  const int32_t *lnt, unsigned int *next, int grid, int block,
+                                                  hipStream_t stream)
 {
     const size_t lds = persistent_lds(block);
     if (occ >= 2 && kTileOcc2 == 2) {
         hipLaunchKernelGGL((k_persistent<MDA_TILE, kTileOcc2, 0>), dim3(grid), dim3(block), lds, stream, runs, work,
-                           nwork, lnt);
+                           nwork, lnt, next);
     } else {
         hipLaunchKernelGGL((k_persistent<MDA_TILE, 1, 0>), dim3(grid), dim3(block), lds, stream, runs, work, nwork,
-                           lnt);
+                           lnt, next);
     }
     return hipGetLastError();
 }
