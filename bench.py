@@ -92,18 +92,22 @@ def hbm_roofline_dense(m, moves, kernel_ms, traffic=None):
             "kernel_ms": round(kernel_ms, 3), "algorithmic_bytes_per_launch": int(nbytes)}
 
 
-# sources of the persistent kernel (the per-tile translation units only name a tile)
-KERNEL_SOURCES = ("paper_2205_13399_amd/csrc/mda_wave.h", "paper_2205_13399_amd/csrc/mda_wave_tile.h",
-                  "paper_2205_13399_amd/csrc/mda_device.h", "paper_2205_13399_amd/csrc/mda_desc.h")
+# sources of each measured kernel (the per-tile translation units only name a tile)
+KERNEL_SOURCES = {
+    "k_persistent": ("paper_2205_13399_amd/csrc/mda_wave.h", "paper_2205_13399_amd/csrc/mda_wave_tile.h",
+                     "paper_2205_13399_amd/csrc/mda_device.h", "paper_2205_13399_amd/csrc/mda_desc.h"),
+    "k_generic": ("paper_2205_13399_amd/csrc/mda_generic.h", "paper_2205_13399_amd/csrc/mda_generic_tile.h",
+                  "paper_2205_13399_amd/csrc/mda_device.h"),
+}
 
 
 def _log(msg):
     print("[bench] " + msg, file=sys.stderr, flush=True)
 
 
-def kernel_source_hash() -> str:
+def kernel_source_hash(kernel: str = "k_persistent") -> str:
     h = hashlib.sha256()
-    for rel in KERNEL_SOURCES:
+    for rel in KERNEL_SOURCES[kernel]:
         with open(os.path.join(ROOT, rel), "rb") as f:
             h.update(f.read())
     return h.hexdigest()[:16]
@@ -121,7 +125,7 @@ def measured_traffic(workload: str, kernel: str = "k_persistent"):
             if ":" in line and line.startswith("- "):
                 k, v = line[2:].split(":", 1)
                 fields[k.strip()] = v.strip()
-    if fields.get("kernel_source_sha256_16") != kernel_source_hash():
+    if fields.get("kernel_source_sha256_16") != kernel_source_hash(kernel):
         return None
     try:
         return float(fields["hbm_bytes_per_launch"])
@@ -529,7 +533,8 @@ def generic_measure(mda, opm, name, steps_timed, warmup, cpu_replicas=2):
     achieved = ops / (kernel_ms * 1e-3) / 1e12
     nbytes = go["breakdown"]["hbm_bytes_per_move_bit_per_objective"] * K * m * st["moves"]
     roof = {"bound": "alu", "achieved": round(achieved, 3), "peak": round(ALU_PEAK_TOPS, 2), "unit": "TOP/s",
-            "frac": round(achieved / ALU_PEAK_TOPS, 4), "traffic": None, "kernel": "k_generic<%d,%d>" % (K, _slots(m, K)),
+            "frac": round(achieved / ALU_PEAK_TOPS, 4), "traffic": measured_traffic(name, "k_generic"),
+            "kernel": "k_generic<%d,%d>" % (K, _slots(m, K)),
             "kernel_ms": round(kernel_ms, 3), "ops_per_launch": int(ops), "opmodel_version": opm["version"],
             "hbm": {"algorithmic_bytes_per_launch": int(nbytes),
                     "achieved_GBs": round(nbytes / (kernel_ms * 1e-3) / 1e9, 2), "peak_GBs": HBM_PEAK_GBS,

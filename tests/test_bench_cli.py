@@ -16,6 +16,7 @@ def test_more_than_one_gpu_is_refused_with_a_message():
 def test_kernel_source_hash_names_existing_files():
     sys.path.insert(0, ROOT)
     import bench
-    for rel in bench.KERNEL_SOURCES:
-        assert os.path.exists(os.path.join(ROOT, rel)), rel
-    assert len(bench.kernel_source_hash()) == 16
+    for kernel, files in bench.KERNEL_SOURCES.items():
+        for rel in files:
+            assert os.path.exists(os.path.join(ROOT, rel)), rel
+        assert len(bench.kernel_source_hash(kernel)) == 16
