@@ -117,6 +117,21 @@ typedef struct {
 int qubo_build_bqap(int32_t n, const int32_t *F1, const int32_t *F2, const int32_t *D,
                     const mda_build_opts *opts, void *stream, mda_qubo **out);
 
+/*
+ * SB-DA (Alg. SB-DA, Sec. 3.2) on the same kernels: the QUBO of the
+ * scalarised cost gamma R + (1 - gamma) S with gamma = g10 / 10, scaled by 10
+ * to stay integer -- C is linear in the flows, so this is the cost QUBO of the
+ * flows g10 F1 + (10 - g10) F2 -- with its own penalty (opts->penalty; the
+ * paper's is MDA_PEN_VL) and a second objective identically zero, under which
+ * the strict rule is the single-objective DA's (Eq. paccepts).  Arguments as
+ * qubo_build_bqap; F1, F2 are the flows as given (normalise them first with
+ * qubo_build_bqap + qubo_flows for the normalised variant).
+ * Errors: as qubo_build_bqap; MDA_EINVAL for g10 outside [0, 10];
+ * MDA_EOVERFLOW when a scalarised flow exceeds int32.
+ */
+int qubo_build_scalarised(int32_t n, const int32_t *F1, const int32_t *F2, const int32_t *D, int32_t g10,
+                          const mda_build_opts *opts, void *stream, mda_qubo **out);
+
 /* The flows q was built from, after normalisation: host, row-major n*n int32
  * each (either may be NULL).  Errors: MDA_EINVAL (NULL q). */
 int qubo_flows(const mda_qubo *q, int32_t *F1, int32_t *F2);
@@ -236,6 +251,15 @@ int da_params_get(const mda_run *r, mda_params *out);
 /* Run statistics summed over replicas: moves, archive entries compared, random
  * blocks drawn, total archive entries (synchronises). */
 int da_stats(mda_run *r, int64_t *moves, int64_t *scanned, int64_t *rng_blocks, int64_t *archived);
+
+/* Each replica's best solution, the state Algorithm 1 returns: the archive
+ * entry of least E_1 (the first slot among equal ones) of replicas [0, R),
+ * found on the device.  e1 and slot receive R entries each (INT64_MAX and -1
+ * for an empty archive); synchronises.  With a second objective identically
+ * zero (SB-DA) the archive keeps the lowest-energy states the replica
+ * visited, so this is its least-energy state.  Errors: MDA_EINVAL (NULL
+ * argument), MDA_ENOMEM, MDA_EDEVICE. */
+int da_best(mda_run *r, int64_t *e1, int32_t *slot);
 
 void da_run_free(mda_run *r);
 

@@ -31,6 +31,7 @@ hipError_t launch_persistent(int ns, int occ, int f64, const RunDesc *runs, cons
 hipError_t launch_plain(int ns, const RunDesc *run, int R, uint32_t steps, const int32_t *lnt, int block,
                         hipStream_t stream);
 hipError_t launch_nondominated(const RunDesc *runs, const WorkItem *work, int nwork, hipStream_t stream);
+hipError_t launch_best(const RunDesc *run, int R, int64_t *e1, int32_t *slot, hipStream_t stream);
 size_t front_filter_scratch();
 hipError_t launch_front_filter(const FrontEntry *ent, int64_t count, void *scratch, FrontEntry *out,
                                unsigned long long *nout, hipStream_t stream);
@@ -580,6 +581,27 @@ extern "C" int qubo_info(const mda_qubo *q, mda_qubo_info *info)
     return MDA_OK;
 }
 
+extern "C" int qubo_build_scalarised(int32_t n, const int32_t *F1, const int32_t *F2, const int32_t *D, int32_t g10,
+                                     const mda_build_opts *opts, void *stream, mda_qubo **out)
+{
+    if (!out) return fail(MDA_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (g10 < 0 || g10 > 10) return fail(MDA_EINVAL, "g10 = %d outside [0, 10]", g10);
+    if (n < 2 || n > 100) return fail(MDA_EINVAL, "n = %d outside [2, 100]", n);
+    if (!F1 || !F2 || !D) return fail(MDA_EINVAL, "NULL input matrix");
+    // C is linear in the flows: gamma R + (1 - gamma) S, times 10, is the cost
+    // QUBO of g10 F1 + (10 - g10) F2 (Alg. SB-DA aggregation)
+    const size_t nn = (size_t)n * n;
+    std::vector<int32_t> F(nn), Z(nn, 0);
+    for (size_t k = 0; k < nn; ++k) {
+        const int64_t v = (int64_t)g10 * F1[k] + (int64_t)(10 - g10) * F2[k];
+        if (v > INT32_MAX || v < INT32_MIN)
+            return fail(MDA_EOVERFLOW, "scalarised flow %lld at (%zu, %zu) beyond int32", (long long)v, k / n, k % n);
+        F[k] = (int32_t)v;
+    }
+    return qubo_build_bqap(n, F.data(), Z.data(), D, opts, stream, out);
+}
+
 extern "C" void qubo_free(mda_qubo *q)
 {
     if (q) qubo_release(q);
@@ -602,11 +624,20 @@ struct Launch {
     hipEvent_t evk0 = nullptr, evk1 = nullptr; // annealing kernel(s) only
     hipGraph_t graph = nullptr;                // captured launch sequence, if any
     hipGraphExec_t graph_exec = nullptr;
+    // streams on which further register-tile groups run beside the first
+    // (default priority), with the fork and join events
+    std::vector<hipStream_t> side;
+    hipEvent_t fork = nullptr;
+    std::vector<hipEvent_t> join;
     ~Launch()
     {
         // wait for this launch only (its last event), not for later work on the stream
         if (ev1) (void)hipEventSynchronize(ev1);
         else if (stream || ev0) (void)hipStreamSynchronize(stream);
+        for (hipStream_t st : side) (void)hipStreamSynchronize(st);
+        for (hipStream_t st : side) (void)hipStreamDestroy(st);
+        for (hipEvent_t e : join) (void)hipEventDestroy(e);
+        if (fork) (void)hipEventDestroy(fork);
         if (graph_exec) (void)hipGraphExecDestroy(graph_exec);
         if (graph) (void)hipGraphDestroy(graph);
         if (ev0) (void)hipEventDestroy(ev0);
@@ -874,7 +905,8 @@ void plan_work(const std::vector<RunDesc> &descs, std::vector<WorkItem> &work, s
 // the -ln table; cus is the device's compute-unit count.
 int enqueue_anneal(const std::vector<Group> &groups, const RunDesc &first, bool plain, const RunDesc *ddesc,
                    const WorkItem *dwork, const int32_t *dlnt, unsigned int *dctr, int block, int cus,
-                   hipStream_t stream)
+                   hipStream_t stream, const std::vector<hipStream_t> *side = nullptr, hipEvent_t fork = nullptr,
+                   const std::vector<hipEvent_t> *join = nullptr)
 {
     if (!plain && groups.size() > kMaxGroups)
         return fail(MDA_EINVAL, "%zu register tiles in one launch (at most %d)", groups.size(), kMaxGroups);
@@ -883,7 +915,18 @@ int enqueue_anneal(const std::vector<Group> &groups, const RunDesc &first, bool 
         HIP_TRY(launch_plain(groups[0].ns, ddesc, first.R, first.steps, dlnt, block, stream));
         return MDA_OK;
     }
+    // Several groups: group k goes to stream k mod (1 + side streams), so
+    // that one group's tail overlaps the next group's work; the side streams
+    // start after everything enqueued on stream so far and stream continues
+    // after all of them (in a captured graph: parallel branches).
+    const bool fan = side && !side->empty() && fork && join && join->size() == side->size() && groups.size() > 1;
+    const int nstreams = fan ? 1 + (int)side->size() : 1;
+    if (fan) {
+        HIP_TRY(hipEventRecord(fork, stream));
+        for (hipStream_t st : *side) HIP_TRY(hipStreamWaitEvent(st, fork, 0));
+    }
     for (const Group &g : groups) {
+        const hipStream_t gs = (gi % nstreams == 0) ? stream : (*side)[gi % nstreams - 1];
         int per_cu = 0;
         if (g.wr * g.wc == 1) {
             // one wave per SIMD when that holds every replica of the launch
@@ -901,7 +944,7 @@ int enqueue_anneal(const std::vector<Group> &groups, const RunDesc &first, bool 
             const int need = (g.cnt + wpb - 1) / wpb;
             if (grid > need) grid = need;
             const hipError_t le = launch_persistent(g.ns, occ, g.f64, ddesc, dwork + g.off, g.cnt, dlnt, dctr + gi,
-                                                    grid, block, stream);
+                                                    grid, block, gs);
             if (le != hipSuccess)
                 return fail(MDA_EDEVICE, "persistent launch (ns %d, grid %d, block %d, %d blocks/CU) failed: %s", g.ns,
                             grid, block, per_cu, hipGetErrorString(le));
@@ -917,12 +960,18 @@ int enqueue_anneal(const std::vector<Group> &groups, const RunDesc &first, bool 
             }
             int grid = cus * per_cu;
             if (grid > g.cnt) grid = g.cnt;
-            const hipError_t le = launch_group(g.ns, occ, g.wr, g.wc, ddesc, dwork + g.off, g.cnt, dlnt, grid, stream);
+            const hipError_t le = launch_group(g.ns, occ, g.wr, g.wc, ddesc, dwork + g.off, g.cnt, dlnt, grid, gs);
             if (le != hipSuccess)
                 return fail(MDA_EDEVICE, "workgroup launch (ns %d, %d x %d waves, grid %d, %d blocks/CU) failed: %s",
                             g.ns, g.wr, g.wc, grid, per_cu, hipGetErrorString(le));
         }
         ++gi;
+    }
+    if (fan) {
+        for (size_t k = 0; k < side->size(); ++k) {
+            HIP_TRY(hipEventRecord((*join)[k], (*side)[k]));
+            HIP_TRY(hipStreamWaitEvent(stream, (*join)[k], 0));
+        }
     }
     return MDA_OK;
 }
@@ -970,6 +1019,19 @@ extern "C" int da_run_batch(const mda_qubo *const *qs, const mda_params *ps, int
     L->dlnt = L->pool.alloc<int32_t>(4096, stream);
     L->dctr = L->pool.alloc<unsigned int>(kMaxGroups, stream);
     if (!L->ddesc || !L->dwork || !L->dlnt || !L->dctr) return fail(MDA_ENOMEM, "device allocation failed");
+    if (!plain && groups.size() > 1) {
+        // up to three more streams (four hardware queues per process)
+        const size_t nside = std::min<size_t>(3, groups.size() - 1);
+        HIP_TRY(hipEventCreateWithFlags(&L->fork, hipEventDisableTiming));
+        for (size_t k = 0; k < nside; ++k) {
+            hipStream_t st = nullptr;
+            HIP_TRY(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+            L->side.push_back(st);
+            hipEvent_t e = nullptr;
+            HIP_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+            L->join.push_back(e);
+        }
+    }
     int32_t lnt[4096];
     threshold_table(lnt);
     HIP_TRY(hipMemcpyAsync(L->ddesc, descs.data(), descs.size() * sizeof(RunDesc), hipMemcpyHostToDevice, stream));
@@ -989,7 +1051,7 @@ extern "C" int da_run_batch(const mda_qubo *const *qs, const mda_params *ps, int
     auto enqueue = [&](bool timed) -> int {
         if (timed) HIP_TRY(hipEventRecord(L->evk0, stream));
         const int rc = enqueue_anneal(groups, descs[0], plain, L->ddesc, L->dwork, L->dlnt, L->dctr, block, cus,
-                                      stream);
+                                      stream, &L->side, L->fork, &L->join);
         if (rc) return rc;
         if (timed) HIP_TRY(hipEventRecord(L->evk1, stream));
         HIP_TRY(launch_nondominated(L->ddesc, L->dwork, L->nwork, stream));
@@ -1635,4 +1697,21 @@ extern "C" int mda_autotune(const mda_qubo *q, const mda_params *pin, int64_t pr
     std::lock_guard<std::mutex> g(g_tune_mu);
     g_tune_cache[key] = *out;
     return MDA_OK;
+}
+
+extern "C" int da_best(mda_run *r, int64_t *e1, int32_t *slot)
+{
+    if (!r || !e1 || !slot) return fail(MDA_EINVAL, "NULL argument");
+    const RunDesc &d = r->h;
+    hipStream_t s = r->launch->stream;
+    TmpPool tmp;
+    RunDesc *dd = tmp.pool.alloc<RunDesc>(1, s);
+    int64_t *de = tmp.pool.alloc<int64_t>((size_t)d.R, s);
+    int32_t *ds = tmp.pool.alloc<int32_t>((size_t)d.R, s);
+    if (!dd || !de || !ds) return fail(MDA_ENOMEM, "device allocation failed for %d replicas", d.R);
+    HIP_TRY(hipMemcpyAsync(dd, &d, sizeof d, hipMemcpyHostToDevice, s));
+    HIP_TRY(launch_best(dd, d.R, de, ds, s));
+    int rc = copy_d2h(e1, de, (size_t)d.R * sizeof(int64_t), s);
+    if (rc) return rc;
+    return copy_d2h(slot, ds, (size_t)d.R * sizeof(int32_t), s);
 }

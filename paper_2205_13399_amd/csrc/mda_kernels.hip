@@ -200,6 +200,48 @@ hipError_t launch_plain(int ns, const RunDesc *run, int R, uint32_t steps, const
 
 
 
+// Best archive entry of each of R replicas: least E_1, lowest slot on ties
+// (one wave per replica).
+__global__ void __launch_bounds__(256) k_best(const RunDesc *run, int64_t *e1_out, int32_t *slot_out)
+{
+    const int lane = __lane_id();
+    const int r = uni((int)((blockIdx.x * blockDim.x + threadIdx.x) >> 6));
+    Desc &D = *ro(run);
+    if (r >= D.R) return;
+    const int s = D.s;
+    int asz = uni((int)rw(D.st)[(size_t)r * kStWords + kStArch]);
+    asz = asz < 0 ? 0 : (asz > s ? s : asz);
+    const MDA_GLOBAL int64_t *AE = rw(D.archE) + (size_t)r * s * 2;
+    int64_t be = INT64_MAX;
+    int bs = INT_MAX;
+    for (int e = lane; e < asz; e += 64) {
+        const int64_t v = AE[2 * (size_t)e];
+        if (v < be) {
+            be = v;
+            bs = e;
+        }
+    }
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+        const int64_t ov = __shfl_xor(be, off);
+        const int os = __shfl_xor(bs, off);
+        if (ov < be || (ov == be && os < bs)) {
+            be = ov;
+            bs = os;
+        }
+    }
+    if (lane == 0) {
+        e1_out[r] = be;
+        slot_out[r] = bs == INT_MAX ? -1 : bs;
+    }
+}
+
+hipError_t launch_best(const RunDesc *run, int R, int64_t *e1, int32_t *slot, hipStream_t stream)
+{
+    hipLaunchKernelGGL(k_best, dim3((R + 3) / 4), dim3(256), 0, stream, run, e1, slot);
+    return hipGetLastError();
+}
+
 hipError_t launch_nondominated(const RunDesc *runs, const WorkItem *work, int nwork, hipStream_t stream)
 {
     const int block = 256;

@@ -131,6 +131,10 @@ def lib():
     vp, i32, i64 = C.c_void_p, C.c_int32, C.c_int64
     L.qubo_build_bqap.argtypes = [i32, vp, vp, vp, C.POINTER(BuildOpts), vp, C.POINTER(vp)]
     L.qubo_build_bqap.restype = C.c_int
+    L.qubo_build_scalarised.argtypes = [i32, vp, vp, vp, i32, C.POINTER(BuildOpts), vp, C.POINTER(vp)]
+    L.qubo_build_scalarised.restype = C.c_int
+    L.da_best.argtypes = [vp, vp, vp]
+    L.da_best.restype = C.c_int
     L.qubo_flows.argtypes = [vp, vp, vp]
     L.qubo_flows.restype = C.c_int
     L.qubo_info.argtypes = [vp, C.POINTER(QuboInfo)]
@@ -209,7 +213,7 @@ def lib():
     return L
 
 
-EXPORTED = ["qubo_build_bqap", "qubo_flows", "qubo_info", "qubo_free", "mda_params_default", "da_run", "da_run_batch",
+EXPORTED = ["qubo_build_bqap", "qubo_build_scalarised", "da_best", "qubo_flows", "qubo_info", "qubo_free", "mda_params_default", "da_run", "da_run_batch",
             "da_sync", "da_elapsed_ms", "da_kernel_ms", "archive_get", "da_state_get", "da_params_get", "da_stats", "da_run_free",
             "mda_set_allocator", "mda_last_error", "mda_threshold_table", "mda_temperature_table",
             "mda_autotune", "mda_footprint", "da_run_layout", "da_run_noalloc", "mda_server_create", "mda_server_submit", "mda_server_wait", "mda_server_stats",
@@ -296,11 +300,13 @@ def temperature_table(delta0: float, deltaf: float, xi: float, steps: int) -> np
 # ---------------------------------------------------------------- handles
 
 class Qubo:
-    """qubo_build_bqap: the penalised QUBOs Y, Z of one bi-objective QAP instance."""
+    """qubo_build_bqap: the penalised QUBOs Y, Z of one bi-objective QAP instance;
+    with scalarise = g10 (0..10), qubo_build_scalarised: the single-objective
+    QUBO of SB-DA's weight gamma = g10 / 10."""
 
     def __init__(self, F1, F2, D, penalty: int = PEN_2MAX, path: int = PATH_AUTO,
                  dense_budget: int = 0, stream: Optional[int] = None, normalise: int = NORM_NONE,
-                 fields: int = FIELDS_AUTO):
+                 fields: int = FIELDS_AUTO, scalarise: Optional[int] = None):
         F1 = np.ascontiguousarray(F1, np.int32)
         F2 = np.ascontiguousarray(F2, np.int32)
         D = np.ascontiguousarray(D, np.int32)
@@ -310,8 +316,12 @@ class Qubo:
         self._h = C.c_void_p()
         opts = BuildOpts(int(penalty), int(path), int(dense_budget), int(normalise), int(fields))
         s = current_stream_handle() if stream is None else stream
-        _check(lib().qubo_build_bqap(n, _ptr(F1), _ptr(F2), _ptr(D), C.byref(opts),
-                                     C.c_void_p(s) if s else None, C.byref(self._h)))
+        if scalarise is None:
+            _check(lib().qubo_build_bqap(n, _ptr(F1), _ptr(F2), _ptr(D), C.byref(opts),
+                                         C.c_void_p(s) if s else None, C.byref(self._h)))
+        else:
+            _check(lib().qubo_build_scalarised(n, _ptr(F1), _ptr(F2), _ptr(D), int(scalarise), C.byref(opts),
+                                               C.c_void_p(s) if s else None, C.byref(self._h)))
         self.n = n
         self.m = n * n
 
@@ -451,6 +461,15 @@ class Run:
         if trace:
             res["trace"] = tr
         return res
+
+    def best(self):
+        """da_best: per replica the archive entry of least E1 (first slot on
+        ties) as (e1, slot) arrays; slot -1 for an empty archive."""
+        R = int(self.params.replicas)
+        e1 = np.zeros(R, np.int64)
+        slot = np.zeros(R, np.int32)
+        _check(lib().da_best(self._h, _ptr(e1), _ptr(slot)))
+        return e1, slot
 
     def stats(self) -> dict:
         a, b, c, d = C.c_int64(), C.c_int64(), C.c_int64(), C.c_int64()

@@ -2,12 +2,12 @@
 
 For each weight gamma = g / 10, g = 0..10, the aggregated cost QUBO
 C = gamma R + (1 - gamma) S (scaled by 10 to stay integer: the cost QUBO of
-the flows 10 gamma F1 + (10 - 10 gamma) F2, since C is linear in the flows)
-gets its own penalty (Eq. vermap / wvermaa) and is solved by the DA
-(Algorithm 1).  The DA is the multi-objective annealer with a second
+the flows 10 gamma F1 + (10 - 10 gamma) F2, since C is linear in the flows;
+built by the library's qubo_build_scalarised) gets its own penalty (Eq.
+vermap / wvermaa) and is solved by the DA (Algorithm 1).  The DA is the multi-objective annealer with a second
 objective identically zero: the strict rule then reduces to Eq. paccepts and
 the archive holds the lowest-energy states, so each replica's best solution
-is its archive entry of least E1.  Every weight runs in one batched launch;
+is its archive entry of least E1 (found on the device by da_best).  Every weight runs in one batched launch;
 replica r of every weight together form SB-DA run r, whose result is the
 non-dominated subset of its 11 solutions in the true objectives (f1, f2).
 
@@ -28,13 +28,6 @@ from . import mda, quality
 WEIGHTS = tuple(range(11))   # 10 gamma
 
 
-def scalarised_flows(F1: np.ndarray, F2: np.ndarray, g10: int) -> np.ndarray:
-    F = g10 * np.asarray(F1, np.int64) + (10 - g10) * np.asarray(F2, np.int64)
-    if np.abs(F).max(initial=0) >= 2 ** 31:
-        raise ValueError("scalarised flows exceed int32")
-    return F.astype(np.int32)
-
-
 def qap_cost(F: np.ndarray, D: np.ndarray, perm: np.ndarray) -> int:
     """Eq. nqap: sum_ij F[i][j] D[perm i][perm j]."""
     p = np.asarray(perm, np.int64)
@@ -52,10 +45,8 @@ class SbdaResult:
 
 
 def _aggregated_qubos(F1, F2, D, weights, penalty, path, stream):
-    n = D.shape[0]
-    zero = np.zeros((n, n), np.int32)
-    return [mda.Qubo(scalarised_flows(F1, F2, g), zero, D, penalty=penalty, path=path, stream=stream)
-            for g in weights]
+    """qubo_build_scalarised for every weight."""
+    return [mda.Qubo(F1, F2, D, penalty=penalty, path=path, stream=stream, scalarise=g) for g in weights]
 
 
 def normalised_qubos(F1, F2, D, normalise: int, weights: Sequence[int] = WEIGHTS, penalty: int = mda.PEN_VL,
@@ -70,8 +61,8 @@ def normalised_qubos(F1, F2, D, normalise: int, weights: Sequence[int] = WEIGHTS
             A, B = q.flows()
             q.close()
             return _aggregated_qubos(A, B, D, weights, penalty, path, stream), L
-        except (mda.MdaError, ValueError) as e:
-            if normalise > 0 or (isinstance(e, mda.MdaError) and e.code != mda.MDA_EOVERFLOW):
+        except mda.MdaError as e:
+            if normalise > 0 or e.code != mda.MDA_EOVERFLOW:
                 raise
     raise mda.MdaError(mda.MDA_EOVERFLOW, "no normalisation 2^L, 1 <= L <= 23, fits every aggregated QUBO")
 
@@ -93,13 +84,14 @@ def sbda(F1, F2, D, replicas: int, steps: int, seed: int, weights: Sequence[int]
     best = np.zeros((len(weights), replicas, 2), np.int64)
     cand = [[] for _ in range(replicas)]
     for w, run in enumerate(runs):
+        e1, slot = run.best()                     # da_best: least E1, first slot on ties
+        best[w, :, 0] = e1
+        best[w, :, 1] = slot
         for r in range(replicas):
-            a = run.archive(r, raw=True)
-            if len(a) == 0:
-                best[w, r] = (np.iinfo(np.int64).max, -1)
+            if slot[r] < 0:
                 continue
-            k = int(np.argmin(a.e1))              # first slot of least energy
-            best[w, r] = (a.e1[k], k)
+            a = run.archive(r, raw=True)
+            k = int(slot[r])
             if a.feasible[k]:
                 perm = a.perm[k]
                 cand[r].append((qap_cost(F1, D, perm), qap_cost(F2, D, perm), perm.copy()))

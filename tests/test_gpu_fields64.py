@@ -132,7 +132,7 @@ def test_sbda_at_paper_size(mda):
     assert any(r.qubo.info().fields == 64 for r in res.runs)
     zero = np.zeros_like(inst.F1)
     for w, g in enumerate(res.weights):
-        Fg = sbda.scalarised_flows(inst.F1, inst.F2, g)
+        Fg = (g * inst.F1.astype(np.int64) + (10 - g) * inst.F2.astype(np.int64)).astype(np.int32)
         oq = oracle.Qubo(Fg, zero, inst.D, 1)
         out = run_replicas(Fg, zero, inst.D, range(R), penalty=1, workers=3,
                            **oracle_kwargs(oq, steps, seed + g, trace=False))

@@ -30,7 +30,7 @@ def test_sbda_against_oracle(mods):
     res = sbda.sbda(inst.F1, inst.F2, inst.D, R, steps, seed)
     zero = np.zeros_like(inst.F1)
     for w, g in enumerate(res.weights):
-        Fg = sbda.scalarised_flows(inst.F1, inst.F2, g)
+        Fg = (g * inst.F1.astype(np.int64) + (10 - g) * inst.F2.astype(np.int64)).astype(np.int32)
         oq = oracle.Qubo(Fg, zero, inst.D, 1)
         assert oq.alpha[1] == 0
         out = run_replicas(Fg, zero, inst.D, range(R), penalty=1, workers=4,
@@ -38,7 +38,9 @@ def test_sbda_against_oracle(mods):
         for r in range(R):
             compare_replica(res.runs[w], out[r], r, trace=False, label="SB-DA weight %d" % g)
             assert np.all(out[r]["arch_e2"] == 0)
+            # da_best: the least energy and its first slot in the oracle's archive
             assert res.best[w, r, 0] == out[r]["arch_e1"].min()
+            assert res.best[w, r, 1] == int(np.argmin(out[r]["arch_e1"]))
     for r in range(R):
         assert len(res.points[r]) >= 1
         for (f1, f2), perm in zip(res.points[r], res.perms[r]):
@@ -80,3 +82,31 @@ def test_sbda_normalised_against_oracle(mods):
         for (f1, f2), perm in zip(res.points[r], res.perms[r]):
             assert f1 == oracle.qap_cost(inst.F1, inst.D, perm)
             assert f2 == oracle.qap_cost(inst.F2, inst.D, perm)
+
+
+def test_scalarised_build_errors_and_best_of_empty(mods):
+    mda, _ = mods
+    inst = synth.make_instance(6, 0.0, seed=6)
+    for g in (-1, 11):
+        with pytest.raises(mda.MdaError) as e:
+            mda.Qubo(inst.F1, inst.F2, inst.D, scalarise=g)
+        assert e.value.code == mda.MDA_EINVAL
+    big = np.full((6, 6), 2 ** 28, np.int32)
+    with pytest.raises(mda.MdaError) as e:        # 10 * 2^28 > 2^31 - 1
+        mda.Qubo(big, big, inst.D, scalarise=5)
+    assert e.value.code == mda.MDA_EOVERFLOW
+    # weight 10 is objective 1 alone: the same QUBO as the plain build with a zero second objective
+    zero = np.zeros_like(inst.F1)
+    a = mda.Qubo(inst.F1 * 10, zero, inst.D, penalty=mda.PEN_VL)
+    b = mda.Qubo(inst.F1, inst.F2, inst.D, penalty=mda.PEN_VL, scalarise=10)
+    ia, ib = a.info(), b.info()
+    assert (ia.alpha1, ia.alpha2, ia.maxabs_c) == (ib.alpha1, ib.alpha2, ib.maxabs_c)
+    # one step from a random start may leave an archive empty: slot -1
+    run = mda.da_run(b, mda.make_params(8, 1, 3))
+    e1, slot = run.best()
+    for r in range(8):
+        a_r = run.archive(r, raw=True, bits=False)
+        if len(a_r) == 0:
+            assert slot[r] == -1 and e1[r] == np.iinfo(np.int64).max
+        else:
+            assert e1[r] == a_r.e1.min() and slot[r] == int(np.argmin(a_r.e1))
