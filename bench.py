@@ -771,9 +771,9 @@ def main():
         # launch shape from the autotuner (probe runs, outside the timed region)
         tuning = mda.autotune(qs[0], params[0], probe_steps=2000)
         params = [mda.tuned(p, tuning) for p in params]
-        _log("autotuner: %d waves per replica, %d waves per block (%s)"
-             % (tuning["waves_per_replica"], tuning["waves_per_block"],
-                ", ".join("%d/%d: %.1f ms" % c for c in tuning["candidates"])))
+        _log("autotuner: %d waves per replica, %d waves per block, occupancy build %d (%s)"
+             % (tuning["waves_per_replica"], tuning["waves_per_block"], tuning["occupancy"],
+                ", ".join("%d/%d/%d: %.1f ms" % c for c in tuning["candidates"])))
     torch.cuda.synchronize()
 
     bit_trials_step = len(insts) * R * m * steps
@@ -803,7 +803,8 @@ def main():
                    "path": w["path"], "launch": "persistent, all instances in one launch",
                    "bit_trials_per_step": bit_trials_step,
                    "launch_shape": ({"waves_per_replica": tuning["waves_per_replica"],
-                                     "waves_per_block": tuning["waves_per_block"], "autotuned": True}
+                                     "waves_per_block": tuning["waves_per_block"],
+                                     "occupancy_build": tuning["occupancy"], "autotuned": True}
                                     if tuning else {"waves_per_block": args.waves_per_block})},
         "roofline": roofline,
         "run_stats": {"moves_per_replica": moves / (len(insts) * R),

@@ -167,6 +167,11 @@ typedef struct {
                                  geometric schedule of delta0, deltaf and xi (Table param) as input data.
                                  Copied before da_run returns.  delta0 still sets the default beta.
                                  NULL: the geometric schedule */
+    int32_t occupancy;        /* one-wave form, int32 differences: 0 = automatic (the build holding two waves
+                                 per SIMD when a launch has more replicas than one wave per SIMD holds at
+                                 once); 1 or 2: that build (2 exists from 40 register slots, i.e. n > 32;
+                                 smaller tiles take 1).  In a batch the first block's value applies.
+                                 Results do not depend on it */
 } mda_params;
 
 /* Fills p with the defaults of Table (param) and the benchmark settings. */
@@ -295,9 +300,10 @@ typedef struct {
     double best_ms;
     int64_t probe_steps;
     int32_t probe_replicas;
-    int32_t reserved;
+    int32_t occupancy;           /* chosen: set in mda_params (0 = automatic, for workgroup layouts) */
     int32_t cand_wpb[16], cand_wpr[16];
     double probe_ms[16];         /* persistent-kernel time of each candidate */
+    int32_t cand_occ[16];
 } mda_tuning;
 
 int mda_autotune(const mda_qubo *q, const mda_params *p, int64_t probe_steps, int32_t probe_replicas,

@@ -715,6 +715,7 @@ static int resolve_run(const mda_qubo *q, const mda_params *pin, mda_params &p, 
     if (p.escape != MDA_ESC_OFFSET && p.escape != MDA_ESC_ARCHIVE) return fail(MDA_EINVAL, "escape = %d", p.escape);
     if (p.archive_size < 0) return fail(MDA_EINVAL, "archive_size = %d", p.archive_size);
     if (p.trace_replicas < 0 || p.trace_replicas > p.replicas) return fail(MDA_EINVAL, "trace_replicas = %d", p.trace_replicas);
+    if (p.occupancy < 0 || p.occupancy > 2) return fail(MDA_EINVAL, "occupancy = %d outside [0, 2]", p.occupancy);
     if (p.delta0 <= 0.0) {
         p.delta0 = 1e9 * (double)q->maxabs / 8388608.0;
         p.deltaf = 1e4 * (double)q->maxabs / 8388608.0;
@@ -905,8 +906,8 @@ void plan_work(const std::vector<RunDesc> &descs, std::vector<WorkItem> &work, s
 // the -ln table; cus is the device's compute-unit count.
 int enqueue_anneal(const std::vector<Group> &groups, const RunDesc &first, bool plain, const RunDesc *ddesc,
                    const WorkItem *dwork, const int32_t *dlnt, unsigned int *dctr, int block, int cus,
-                   hipStream_t stream, const std::vector<hipStream_t> *side = nullptr, hipEvent_t fork = nullptr,
-                   const std::vector<hipEvent_t> *join = nullptr)
+                   hipStream_t stream, int occ_req = 0, const std::vector<hipStream_t> *side = nullptr,
+                   hipEvent_t fork = nullptr, const std::vector<hipEvent_t> *join = nullptr)
 {
     if (!plain && groups.size() > kMaxGroups)
         return fail(MDA_EINVAL, "%zu register tiles in one launch (at most %d)", groups.size(), kMaxGroups);
@@ -934,8 +935,10 @@ int enqueue_anneal(const std::vector<Group> &groups, const RunDesc &first, bool 
             const int wpb = block / 64;
             HIP_TRY(persistent_occupancy(g.ns, 1, g.f64, block, &per_cu));
             if (per_cu < 1) per_cu = 1;
-            // (the int64 build has one register budget only)
-            const int occ = !g.f64 && (int64_t)g.cnt > (int64_t)cus * per_cu * wpb ? 2 : 1;
+            // (the int64 build has one register budget only); occ_req 1 or 2
+            // overrides the rule
+            int occ = !g.f64 && (int64_t)g.cnt > (int64_t)cus * per_cu * wpb ? 2 : 1;
+            if (occ_req == 1 || occ_req == 2) occ = g.f64 ? 1 : occ_req;
             if (occ == 2) {
                 HIP_TRY(persistent_occupancy(g.ns, 2, 0, block, &per_cu));
                 if (per_cu < 1) per_cu = 1;
@@ -1051,7 +1054,7 @@ extern "C" int da_run_batch(const mda_qubo *const *qs, const mda_params *ps, int
     auto enqueue = [&](bool timed) -> int {
         if (timed) HIP_TRY(hipEventRecord(L->evk0, stream));
         const int rc = enqueue_anneal(groups, descs[0], plain, L->ddesc, L->dwork, L->dlnt, L->dctr, block, cus,
-                                      stream, &L->side, L->fork, &L->join);
+                                      stream, ps[0].occupancy, &L->side, L->fork, &L->join);
         if (rc) return rc;
         if (timed) HIP_TRY(hipEventRecord(L->evk1, stream));
         HIP_TRY(launch_nondominated(L->ddesc, L->dwork, L->nwork, stream));
@@ -1287,7 +1290,7 @@ extern "C" int da_run_noalloc(const mda_qubo *q, const mda_params *pin, const md
     HIP_TRY(hipGetDevice(&dev));
     HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
     rc = enqueue_anneal(groups, d, false, ddesc, dwork, dlnt, reinterpret_cast<unsigned int *>(sb + sp.ctr),
-                        default_block(p.waves_per_block), cus, stream);
+                        default_block(p.waves_per_block), cus, stream, p.occupancy);
     if (rc) return rc;
     HIP_TRY(launch_nondominated(ddesc, dwork, (int)work.size(), stream));
     return MDA_OK;
@@ -1644,11 +1647,19 @@ extern "C" int mda_autotune(const mda_qubo *q, const mda_params *pin, int64_t pr
         }
     }
     std::memset(out, 0, sizeof *out);
-    // candidates: one wave per replica (n <= 64) with 1, 2, 4 waves per block;
-    // workgroups of 2 and 4 waves where a layout exists
-    std::vector<std::pair<int, int>> cand;   // (waves per replica, waves per block)
+    // candidates: one wave per replica (n <= 64) with 1, 2, 4 waves per block,
+    // each with the one- and (from 40 slots, int32 differences) the
+    // two-waves-per-SIMD build; workgroups of 2 and 4 waves where a layout
+    // exists (their build by the host rule)
+    struct Cand {
+        int wpr, wpb, occ;
+    };
+    std::vector<Cand> cand;
     if (n <= kMaxWaveN)
-        for (int wpb : {1, 2, 4}) cand.push_back({1, wpb});
+        for (int wpb : {1, 2, 4}) {
+            cand.push_back({1, wpb, 1});
+            if (!q->f64 && ns_for(n) >= 40) cand.push_back({1, wpb, 2});
+        }
     const int wc = (n + 63) / 64;
     for (int g : {2, 4}) {
         if (q->f64) break;   // int64 differences run one wave per replica
@@ -1656,7 +1667,7 @@ extern "C" int mda_autotune(const mda_qubo *q, const mda_params *pin, int64_t pr
         if (wr * wc != g) continue;
         const int gns = (((n + wr - 1) / wr + 7) / 8) * 8;
         if (gns > 64 || g > group_waves_limit(gns)) continue;
-        cand.push_back({g, 0});
+        cand.push_back({g, 0, 0});
     }
     if (cand.size() > 16) cand.resize(16);
     mda_params p = *pin;
@@ -1668,8 +1679,9 @@ extern "C" int mda_autotune(const mda_qubo *q, const mda_params *pin, int64_t pr
     // a first launch loads the code objects; it is not timed
     for (int pass = 0; pass < 2; ++pass) {
         for (size_t c = 0; c < cand.size(); ++c) {
-            p.waves_per_replica = cand[c].first;
-            p.waves_per_block = cand[c].second;
+            p.waves_per_replica = cand[c].wpr;
+            p.waves_per_block = cand[c].wpb;
+            p.occupancy = cand[c].occ;
             mda_run *r = nullptr;
             int rc = da_run(q, &p, &r);
             if (rc) return rc;
@@ -1678,8 +1690,9 @@ extern "C" int mda_autotune(const mda_qubo *q, const mda_params *pin, int64_t pr
             da_run_free(r);
             if (rc) return rc;
             if (pass == 1) {
-                out->cand_wpr[c] = cand[c].first;
-                out->cand_wpb[c] = cand[c].second;
+                out->cand_wpr[c] = cand[c].wpr;
+                out->cand_wpb[c] = cand[c].wpb;
+                out->cand_occ[c] = cand[c].occ;
                 out->probe_ms[c] = ms;
             }
             if (pass == 0) break;   // one warm-up launch is enough
@@ -1691,6 +1704,7 @@ extern "C" int mda_autotune(const mda_qubo *q, const mda_params *pin, int64_t pr
         if (out->probe_ms[c] < out->probe_ms[best]) best = c;
     out->waves_per_replica = out->cand_wpr[best];
     out->waves_per_block = out->cand_wpb[best];
+    out->occupancy = out->cand_occ[best];
     out->best_ms = out->probe_ms[best];
     out->probe_steps = probe_steps;
     out->probe_replicas = R;

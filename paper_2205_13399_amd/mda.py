@@ -56,7 +56,7 @@ class Params(C.Structure):
                 ("escape", C.c_int32), ("variant", C.c_int32), ("seed", C.c_uint64),
                 ("trace_replicas", C.c_int32), ("waves_per_block", C.c_int32),
                 ("stream", C.c_void_p), ("graph", C.c_int32), ("waves_per_replica", C.c_int32),
-                ("temp_table", C.c_void_p)]
+                ("temp_table", C.c_void_p), ("occupancy", C.c_int32)]
 
 
 class ArchiveOut(C.Structure):
@@ -74,8 +74,8 @@ class State(C.Structure):
 class Tuning(C.Structure):
     _fields_ = [("waves_per_block", C.c_int32), ("waves_per_replica", C.c_int32), ("candidates", C.c_int32),
                 ("cached", C.c_int32), ("best_ms", C.c_double), ("probe_steps", C.c_int64),
-                ("probe_replicas", C.c_int32), ("reserved", C.c_int32), ("cand_wpb", C.c_int32 * 16),
-                ("cand_wpr", C.c_int32 * 16), ("probe_ms", C.c_double * 16)]
+                ("probe_replicas", C.c_int32), ("occupancy", C.c_int32), ("cand_wpb", C.c_int32 * 16),
+                ("cand_wpr", C.c_int32 * 16), ("probe_ms", C.c_double * 16), ("cand_occ", C.c_int32 * 16)]
 
 
 class RunLayout(C.Structure):
@@ -358,7 +358,7 @@ def make_params(replicas: int, steps: int, seed: int, *, archive_size: int = 0,
                 accept: int = STRICT, archive: int = EXPLORE, escape: int = ESC_OFFSET,
                 variant: int = VARIANT_AUTO, trace_replicas: int = 0, waves_per_block: int = 0,
                 stream: Optional[int] = None, graph: bool = False, waves_per_replica: int = 0,
-                temp_table: Optional[np.ndarray] = None) -> Params:
+                temp_table: Optional[np.ndarray] = None, occupancy: int = 0) -> Params:
     """A parameter block (mda_params).  temp_table: steps int64 entries of T_t
     (fixed point, 8 fractional bits) in place of the geometric schedule; the
     array is kept alive with the returned block and copied by the library when
@@ -381,6 +381,7 @@ def make_params(replicas: int, steps: int, seed: int, *, archive_size: int = 0,
     p.waves_per_block = int(waves_per_block)
     p.graph = 1 if graph else 0
     p.waves_per_replica = int(waves_per_replica)
+    p.occupancy = int(occupancy)
     s = current_stream_handle() if stream is None else stream
     p.stream = C.c_void_p(s) if s else None
     if temp_table is not None:
@@ -711,8 +712,9 @@ def autotune(q: Qubo, params: Params, probe_steps: int = 2000, probe_replicas: i
     _check(lib().mda_autotune(q.handle, C.byref(params), int(probe_steps), int(probe_replicas), C.byref(t)))
     k = int(t.candidates)
     return {"waves_per_block": int(t.waves_per_block), "waves_per_replica": int(t.waves_per_replica),
-            "cached": bool(t.cached), "best_ms": float(t.best_ms),
-            "candidates": [(int(t.cand_wpr[i]), int(t.cand_wpb[i]), float(t.probe_ms[i])) for i in range(k)]}
+            "occupancy": int(t.occupancy), "cached": bool(t.cached), "best_ms": float(t.best_ms),
+            "candidates": [(int(t.cand_wpr[i]), int(t.cand_wpb[i]), int(t.cand_occ[i]), float(t.probe_ms[i]))
+                           for i in range(k)]}
 
 
 def tuned(params: Params, tuning: dict) -> Params:
@@ -720,4 +722,5 @@ def tuned(params: Params, tuning: dict) -> Params:
     p = Params.from_buffer_copy(params)
     p.waves_per_block = tuning["waves_per_block"]
     p.waves_per_replica = tuning["waves_per_replica"]
+    p.occupancy = tuning["occupancy"]
     return p

@@ -23,10 +23,11 @@ def test_autotune_picks_fastest_and_keeps_results(mda):
     q = mda.Qubo(inst.F1, inst.F2, inst.D, path=2)
     p = mda.make_params(256, 3000, 7)
     t = mda.autotune(q, p, probe_steps=500)
-    shapes = {(w, b) for w, b, _ in t["candidates"]}
-    assert {(1, 1), (1, 2), (1, 4), (2, 0), (4, 0)} <= shapes
-    assert t["best_ms"] == min(ms for _, _, ms in t["candidates"])
-    assert (t["waves_per_replica"], t["waves_per_block"]) in shapes
+    shapes = {(w, b, o) for w, b, o, _ in t["candidates"]}
+    # n = 30: 32 slots, one build per SIMD only
+    assert {(1, 1, 1), (1, 2, 1), (1, 4, 1), (2, 0, 0), (4, 0, 0)} <= shapes
+    assert t["best_ms"] == min(ms for _, _, _, ms in t["candidates"])
+    assert (t["waves_per_replica"], t["waves_per_block"], t["occupancy"]) in shapes
     again = mda.autotune(q, p, probe_steps=500)
     assert again["cached"] and again["waves_per_replica"] == t["waves_per_replica"]
     a = mda.da_run(q, p)
@@ -44,3 +45,23 @@ def test_autotune_beyond_one_wave(mda):
     q = mda.Qubo(inst.F1, inst.F2, inst.D, path=2)
     t = mda.autotune(q, mda.make_params(64, 400, 3), probe_steps=300)
     assert t["waves_per_replica"] == 4 and [c[0] for c in t["candidates"]] == [4]
+
+
+def test_autotune_times_both_occupancy_builds(mda):
+    """n = 40 (40 slots): the one- and two-waves-per-SIMD builds are both
+    candidates; every forced build gives the same results."""
+    inst = synth.make_instance(40, 0.0, seed=41)
+    q = mda.Qubo(inst.F1, inst.F2, inst.D, path=2)
+    p = mda.make_params(2048, 600, 5)
+    t = mda.autotune(q, p, probe_steps=300)
+    occs = {o for w, _, o, _ in t["candidates"] if w == 1}
+    assert occs == {1, 2}
+    runs = [mda.da_run(q, mda.make_params(2048, 600, 5, occupancy=o)) for o in (0, 1, 2)]
+    for r in (0, 1000, 2047):
+        s0 = runs[0].state(r)
+        for other in runs[1:]:
+            s1 = other.state(r)
+            assert (s0["E1"], s0["E2"], s0["moves"]) == (s1["E1"], s1["E2"], s1["moves"])
+    with pytest.raises(mda.MdaError) as e:
+        mda.da_run(q, mda.make_params(4, 10, 1, occupancy=3))
+    assert e.value.code == mda.MDA_EINVAL
