@@ -559,8 +559,9 @@ struct GFrontEntry {
 
 // One wave per replica r0 + k: its flagged (non-dominated within its archive)
 // entries appended at offs[k] in slot order (offs has nr + 1 entries: the host
-// prefix of the flag counts), and its entry of least energy sum (lowest slot
-// on ties) as a reference point, or an entry of INT64_MAX energies if none.
+// prefix of the flag counts), and K + 1 of them as reference points: the entry
+// of least energy sum and, for each objective, the entry of least energy in it
+// (lowest slot on ties), or entries of INT64_MAX energies if there is none.
 template <int K>
 __global__ void __launch_bounds__(256) k_ggather(const GRunDesc *run, int r0, int nr, const int64_t *offs,
                                                  GFrontEntry *out, GFrontEntry *ref)
@@ -577,8 +578,14 @@ __global__ void __launch_bounds__(256) k_ggather(const GRunDesc *run, int r0, in
     const int64_t base = offs[k], lim = offs[k + 1];
     const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
     int64_t run_n = 0;
-    int64_t bsum = INT64_MAX;
-    int bslot = INT_MAX;
+    // key c = 0: energy sum; c = 1..K: objective c - 1
+    int64_t bv[K + 1];
+    int bslot[K + 1];
+#pragma unroll
+    for (int c = 0; c <= K; ++c) {
+        bv[c] = INT64_MAX;
+        bslot[c] = INT_MAX;
+    }
     for (int b = 0; b < asz; b += 64) {
         const int e = b + lane;
         const bool flag = e < asz && nd[e] != 0;
@@ -593,38 +600,48 @@ __global__ void __launch_bounds__(256) k_ggather(const GRunDesc *run, int r0, in
             for (int q = 0; q < K; ++q) {
                 g.e[q] = AE[(size_t)e * K + q];
                 sum += g.e[q];
+                if (g.e[q] < bv[q + 1]) {
+                    bv[q + 1] = g.e[q];
+                    bslot[q + 1] = e;
+                }
             }
             g.rep = r;
             g.slot = e;
             if (pos < lim) out[pos] = g;
-            if (sum < bsum) {
-                bsum = sum;
-                bslot = e;
+            if (sum < bv[0]) {
+                bv[0] = sum;
+                bslot[0] = e;
             }
         }
         run_n += __popcll(M);
     }
-    // least (sum, slot) over the wave
+    // least (value, slot) of each key over the wave
 #pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) {
-        const int64_t os = __shfl_xor(bsum, off);
-        const int oslot = __shfl_xor(bslot, off);
-        if (os < bsum || (os == bsum && oslot < bslot)) {
-            bsum = os;
-            bslot = oslot;
+    for (int c = 0; c <= K; ++c) {
+#pragma unroll
+        for (int off = 32; off >= 1; off >>= 1) {
+            const int64_t ov = __shfl_xor(bv[c], off);
+            const int os = __shfl_xor(bslot[c], off);
+            if (ov < bv[c] || (ov == bv[c] && os < bslot[c])) {
+                bv[c] = ov;
+                bslot[c] = os;
+            }
         }
     }
-    if (lane == 0) {
+    if (lane <= K) {
+        int sl = bslot[0];
+#pragma unroll
+        for (int c = 1; c <= K; ++c) sl = (lane == c) ? bslot[c] : sl;
         GFrontEntry g;
 #pragma unroll
         for (int q = 0; q < kMaxK; ++q) g.e[q] = INT64_MAX;
-        if (bslot != INT_MAX) {
+        if (sl != INT_MAX) {
 #pragma unroll
-            for (int q = 0; q < K; ++q) g.e[q] = AE[(size_t)bslot * K + q];
+            for (int q = 0; q < K; ++q) g.e[q] = AE[(size_t)sl * K + q];
         }
-        g.rep = bslot != INT_MAX ? r : -1;
-        g.slot = bslot != INT_MAX ? bslot : -1;
-        ref[k] = g;
+        g.rep = sl != INT_MAX ? r : -1;
+        g.slot = sl != INT_MAX ? sl : -1;
+        ref[(size_t)k * (K + 1) + lane] = g;
     }
 }
 

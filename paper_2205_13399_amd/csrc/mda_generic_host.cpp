@@ -365,8 +365,9 @@ bool lex_less(const GEntryH &a, const GEntryH &b, int K)
 
 // Non-dominated entries of the archives of replicas [r0, r0 + nr) (Section
 // 3.3), equal energy vectors reduced to the lowest (replica, slot), sorted by
-// (E, replica, slot).  The device gathers the flagged entries, drops those a
-// replica's least-sum entry dominates and keeps the survivors that no other
+// (E, replica, slot).  The device gathers the flagged entries, drops those
+// that one of each replica's K + 1 reference entries (least energy sum, least
+// energy per objective) dominates, and keeps the survivors that no other
 // survivor dominates; the host sorts what is left.
 int merged_front(mda_grun *r, int r0, int nr, const std::vector<int64_t> &st, std::vector<GEntryH> &out)
 {
@@ -381,7 +382,7 @@ int merged_front(mda_grun *r, int r0, int nr, const std::vector<int64_t> &st, st
     TmpPool tmp;
     int64_t *doffs = tmp.pool.alloc<int64_t>(offs.size(), s);
     GFrontEntry *cand = tmp.pool.alloc<GFrontEntry>((size_t)total, s);
-    GFrontEntry *ref = tmp.pool.alloc<GFrontEntry>((size_t)nr, s);
+    GFrontEntry *ref = tmp.pool.alloc<GFrontEntry>((size_t)nr * (K + 1), s);
     GFrontEntry *keep = tmp.pool.alloc<GFrontEntry>((size_t)total, s);
     GFrontEntry *front = tmp.pool.alloc<GFrontEntry>((size_t)total, s);
     unsigned long long *cnt = tmp.pool.alloc<unsigned long long>(2, s);

@@ -58,7 +58,7 @@ hipError_t MDA_GCAT(launch_gfront_k, MDA_GK)(const GRunDesc *run, int r0, int nr
 {
     hipLaunchKernelGGL((k_ggather<MDA_GK>), dim3((nr + 3) / 4), dim3(256), 0, stream, run, r0, nr, offs, cand, ref);
     hipLaunchKernelGGL((k_gfilter<MDA_GK>), dim3((unsigned)((total + 255) / 256)), dim3(256), 0, stream, cand, total,
-                       ref, nr, keep, nkeep);
+                       ref, nr * (MDA_GK + 1), keep, nkeep);
     return hipGetLastError();
 }
 
