@@ -262,7 +262,7 @@ def serving_measure(mda, w, factors=(0.5, 0.9, 1.2)):
 
 def serve_config(w, insts):
     return {"workload": "bqap-serve-n10-100", "requests": len(insts), "n": [w["n_lo"], w["n_hi"]],
-            "replicas": w["replicas"], "anneal_steps": w["steps"], "path": "automatic (dense up to 2 GB)",
+            "replicas": w["replicas"], "anneal_steps": w["steps"], "path": "automatic (Kronecker)",
             "arrivals": "all at once (saturated), then Poisson at the stated multiples of the saturated rate",
             "server": "admission by device footprint, up to 4 launches in flight"}
 

@@ -50,7 +50,8 @@ enum { MDA_PEN_2MAX = 0,   /* alpha_k = 2 * max |C_k| (the benchmark setting) */
        MDA_PEN_VL = 1 };   /* Eq. (vermap) on the symmetric form, alpha = ceil(w/2), Eq. (wvermaa) */
 
 /* How the local fields are updated after a flip. */
-enum { MDA_PATH_AUTO = 0,  /* dense when 8*m*m <= dense_budget, else Kronecker */
+enum { MDA_PATH_AUTO = 0,  /* Kronecker; dense when the rows fit a positive dense_budget, or when the
+                              Kronecker operands exceed the 24-bit multiplier range */
        MDA_PATH_DENSE = 1, /* stream int32 rows of the symmetric P_1, P_2 from HBM */
        MDA_PATH_KRON = 2 };/* regenerate the column from F_k, D and alpha_k */
 
@@ -68,7 +69,8 @@ typedef struct mda_run mda_run;    /* one run: device replica state and archives
 typedef struct {
     int32_t penalty;         /* MDA_PEN_* */
     int32_t path;            /* MDA_PATH_* */
-    int64_t dense_budget;    /* bytes for MDA_PATH_AUTO; <= 0 means 2 GiB */
+    int64_t dense_budget;    /* bytes of dense rows MDA_PATH_AUTO may take; <= 0: none (the Kronecker
+                                update is the faster one at every size) */
     int32_t normalise_log2;  /* objective normalisation (Sec. Parameter Settings, which
                                 sets the largest coefficient of each C_k to 2^23):
                                 0 = none; L in [1, 30] = each F_k is scaled by
@@ -104,7 +106,7 @@ typedef struct {
  *   n            2 <= n <= 100 (m = n*n <= 10000)
  *   F1, F2, D    host, row-major n*n int32: F_k[i*n+j] flow from facility i to j
  *                in objective k, D[u*n+v] distance from location u to v
- *   opts         NULL for defaults (MDA_PEN_2MAX, MDA_PATH_AUTO, 2 GiB)
+ *   opts         NULL for defaults (MDA_PEN_2MAX, MDA_PATH_AUTO, no dense budget)
  *   stream       hipStream_t for the uploads (NULL = default stream)
  *   out          receives the handle
  * Errors: MDA_EINVAL (n outside [2, 100], a NULL array, an unknown option),

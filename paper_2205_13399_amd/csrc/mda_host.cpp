@@ -236,7 +236,9 @@ static int64_t objective_maxabs(const int32_t *F, const int32_t *Dm, int n)
 static int build_bqap(int32_t n, const int32_t *F1, const int32_t *F2, const int32_t *D, const mda_build_opts &o,
                       int L, const int64_t *mxk, hipStream_t stream, mda_qubo **out)
 {
-    const int64_t budget = o.dense_budget > 0 ? o.dense_budget : (int64_t)2 << 30;
+    // automatic path: dense rows only within an explicit budget (the Kronecker
+    // update is the faster one at every size)
+    const int64_t budget = o.dense_budget > 0 ? o.dense_budget : 0;
 
     std::unique_ptr<mda_qubo> q(new mda_qubo);
     const int m = n * n;
@@ -1596,7 +1598,7 @@ extern "C" int64_t mda_footprint(int32_t n, const mda_params *p, const mda_build
     if (p->trace_replicas > 0) b += (int64_t)p->trace_replicas * steps * 4;
     // QUBO: dense rows when the build will pick them, the per-lane operands
     const mda_build_opts o = bo ? *bo : mda_build_opts{MDA_PEN_2MAX, MDA_PATH_AUTO, 0};
-    const int64_t budget = o.dense_budget > 0 ? o.dense_budget : (int64_t)2 << 30;
+    const int64_t budget = o.dense_budget > 0 ? o.dense_budget : 0;
     const int64_t pld = n <= kMaxWaveN ? kLD : n, ldk = n <= kMaxWaveN ? kLD : 2 * kLD;
     const int64_t dense = 8 * m * n * pld;
     const bool use_dense = o.path == MDA_PATH_DENSE || (o.path == MDA_PATH_AUTO && dense <= budget);
