@@ -56,8 +56,8 @@ struct RunDesc {
     //   P_k[(i,u)][(i',u')] = KA_k[i'][i] * DA[u'][u] (+ KB_k[i'][i] * DB[u'][u])
     //                         + 2 alpha_k [(i == i') != (u == u')]
     const int32_t *KA1, *KA2, *KB1, *KB2, *DA, *DB;
-    // dense operands: symmetric P_k, m rows of n * kLD int32, entry (j, v) of
-    // row a at j * kLD + v
+    // dense operands: symmetric P_k, m rows of n * pld int32, entry (j, v) of
+    // row a at a * n * pld + j * pld + v (pld = n: no padding)
     const int32_t *P1, *P2;
     const int32_t *diag1, *diag2;   // d_k[(i,u)] = P_k[a][a] at i * kLD + u
     // outputs and archives

@@ -459,11 +459,12 @@ static int build_bqap(int32_t n, const int32_t *F1, const int32_t *F2, const int
     if (q->f64 && n > kMaxWaveN)
         return fail(MDA_EOVERFLOW, "%s; int64 fields run one wave per replica (n <= %d), n = %d",
                     why32[0] ? why32 : "int64 fields requested", kMaxWaveN, n);
-    // Operand layouts: up to 64 facilities every row is padded to 64 entries
-    // (one wave per replica reads them unmasked); beyond, rows of 128 entries
-    // and the dense rows unpadded (the workgroup form masks its reads).
+    // Operand layouts: up to 64 facilities every Kronecker row is padded to 64
+    // entries (one wave per replica reads them unmasked), beyond to 128; the
+    // dense rows are never padded (both forms mask their reads), so a move
+    // streams 2 n^2 entries, the algorithmic amount.
     q->ldk = n <= kMaxWaveN ? kLD : 2 * kLD;
-    q->pld = n <= kMaxWaveN ? kLD : n;
+    q->pld = n;
     const bool dense_fits = 8 * (int64_t)m * n * q->pld <= budget;
     if (o.path == MDA_PATH_KRON) {
         if (!kron_ok) return fail(MDA_EOVERFLOW, "Kronecker operands exceed the 24-bit multiplier range");
@@ -1599,7 +1600,7 @@ extern "C" int64_t mda_footprint(int32_t n, const mda_params *p, const mda_build
     // QUBO: dense rows when the build will pick them, the per-lane operands
     const mda_build_opts o = bo ? *bo : mda_build_opts{MDA_PEN_2MAX, MDA_PATH_AUTO, 0};
     const int64_t budget = o.dense_budget > 0 ? o.dense_budget : 0;
-    const int64_t pld = n <= kMaxWaveN ? kLD : n, ldk = n <= kMaxWaveN ? kLD : 2 * kLD;
+    const int64_t pld = n, ldk = n <= kMaxWaveN ? kLD : 2 * kLD;
     const int64_t dense = 8 * m * n * pld;
     const bool use_dense = o.path == MDA_PATH_DENSE || (o.path == MDA_PATH_AUTO && dense <= budget);
     b += (use_dense ? dense + 3 * m * 4 : 0) + 6 * (int64_t)n * ldk * 4 + 2 * std::max<int64_t>(n, kMaxWaveN) * ldk * 4;

@@ -51,8 +51,11 @@ __device__ __forceinline__ void flip(Desc *Dp, int n_, Replica<NS, FT> &S, int j
         const int j = js * n + jl;
         const UT c1 = (lane == jl) ? (UT)(-2 * d1) - (UT)(FT)ro(D.diag1)[js * kLD + jl] : (UT)0;
         const UT c2 = (lane == jl) ? (UT)(-2 * d2) - (UT)(FT)ro(D.diag2)[js * kLD + jl] : (UT)0;
-        const MDA_CONST int32_t *r1 = ro(D.P1) + (size_t)j * (size_t)(n * kLD);
-        const MDA_CONST int32_t *r2 = ro(D.P2) + (size_t)j * (size_t)(n * kLD);
+        // rows of n x n entries: lanes beyond n read a clamped (in-bounds)
+        // index and take 0
+        const MDA_CONST int32_t *r1 = ro(D.P1) + (size_t)j * (size_t)(n * n);
+        const MDA_CONST int32_t *r2 = ro(D.P2) + (size_t)j * (size_t)(n * n);
+        const int ul = live ? lane : 0;
 #pragma unroll
         for (int g = 0; g < NS; g += 8) {
             // at most 16 row loads in flight (keeps the register budget)
@@ -61,8 +64,10 @@ __device__ __forceinline__ void flip(Desc *Dp, int n_, Replica<NS, FT> &S, int j
 #pragma unroll
             for (int f = 0; f < 8; ++f) {
                 const int i = g + f;
-                t1[f] = (i < n) ? (uint32_t)r1[i * kLD + lane] : 0u;   // padded rows: 0 beyond n
-                t2[f] = (i < n) ? (uint32_t)r2[i * kLD + lane] : 0u;
+                t1[f] = (i < n) ? (uint32_t)r1[i * n + ul] : 0u;
+                t2[f] = (i < n) ? (uint32_t)r2[i * n + ul] : 0u;
+                t1[f] = live ? t1[f] : 0u;
+                t2[f] = live ? t2[f] : 0u;
             }
 #pragma unroll
             for (int f = 0; f < 8; ++f) {
@@ -142,16 +147,19 @@ __device__ __forceinline__ void fields_from_scratch(Desc *Dp, Replica<NS, FT> &S
         const int bu = __ffsll((long long)bb) - 1;
         const int bi = uni(__ffsll((long long)rl64(todo, bu)) - 1);
         if (PV == kPvDense) {
-            const MDA_CONST int32_t *r1 = ro(D.P1) + (size_t)(bi * n + bu) * (size_t)(n * kLD);
-            const MDA_CONST int32_t *r2 = ro(D.P2) + (size_t)(bi * n + bu) * (size_t)(n * kLD);
+            const MDA_CONST int32_t *r1 = ro(D.P1) + (size_t)(bi * n + bu) * (size_t)(n * n);
+            const MDA_CONST int32_t *r2 = ro(D.P2) + (size_t)(bi * n + bu) * (size_t)(n * n);
+            const int ul = live ? lane : 0;
 #pragma unroll
             for (int g = 0; g < NS; g += 8) {
                 asm volatile("" : "+v"(r1), "+v"(r2));
 #pragma unroll
                 for (int f = 0; f < 8; ++f) {
                     const int i = g + f;
-                    S.e1[i] = (FT)((UT)S.e1[i] + ((i < n) ? (UT)(FT)r1[i * kLD + lane] : (UT)0));
-                    S.e2[i] = (FT)((UT)S.e2[i] + ((i < n) ? (UT)(FT)r2[i * kLD + lane] : (UT)0));
+                    const UT v1 = (i < n) ? (UT)(FT)r1[i * n + ul] : (UT)0;
+                    const UT v2 = (i < n) ? (UT)(FT)r2[i * n + ul] : (UT)0;
+                    S.e1[i] = (FT)((UT)S.e1[i] + (live ? v1 : (UT)0));
+                    S.e2[i] = (FT)((UT)S.e2[i] + (live ? v2 : (UT)0));
                 }
             }
         } else {

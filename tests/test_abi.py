@@ -87,14 +87,19 @@ def test_torch_allocator_installed_once(mda):
 
 def test_footprint_counts_archives_and_operands(mda):
     """mda_footprint: replicas x archive slots x (energies + stored solution)
-    dominate; the dense rows are counted only when the build would pick them."""
+    dominate; the dense rows (2 m^2 int32) are counted only when the build
+    would pick them."""
     p = mda.make_params(4096, 100000, 1)
     kron = mda.footprint(50, p, path=mda.PATH_KRON)
     m = 2500
     assert kron >= 4096 * m * (16 + 50 * 8)          # archives of every replica
     assert kron < 4096 * m * (16 + 50 * 8) * 1.2
     dense = mda.footprint(50, p, path=mda.PATH_DENSE)
-    assert dense - kron >= 8 * m * 50 * 64            # two padded objectives
+    assert dense - kron >= 8 * m * m                  # two objectives' rows of m entries (no padding)
+    assert dense - kron < 8 * m * m * 1.1
+    # the automatic path takes dense rows only within an explicit budget
+    assert mda.footprint(50, p) == kron
+    assert mda.footprint(50, p, dense_budget=8 * m * m) == dense
     # beyond 64 facilities a solution is stored as 2 x 2 wave blocks of 64 words
     p100 = mda.make_params(256, 50000, 1)
     assert mda.footprint(100, p100, path=mda.PATH_KRON) >= 256 * 10000 * (16 + 256 * 8)
