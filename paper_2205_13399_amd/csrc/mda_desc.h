@@ -19,6 +19,12 @@ enum : int32_t {
     kStArch = 6, kStDetailed = 7, kStNd = 8, kStWords = 16
 };
 
+// Step variant of a run: update path (0 dense rows, 1 Kronecker with one
+// product per objective, 2 with two) times 2 plus the acceptance rule (0
+// strict, 1 lenient).  The one-wave persistent kernels are built per variant
+// and a launch holds the items of one variant only.
+constexpr int kStepVariants = 6;
+
 // One non-dominated archive entry gathered for the host merge.
 struct FrontEntry {
     int64_t e1, e2;
@@ -84,6 +90,11 @@ struct RunDesc {
     int32_t xrw;               // words per replica in x (64, or wr * wc * 64)
     int32_t pad2;
 };
+
+inline __host__ __device__ int run_step_variant(int32_t path, int32_t kform, int32_t accept)
+{
+    return (path == kPathDense ? 0 : (kform == kKronGen ? 2 : 1)) * 2 + (accept != 0 ? 1 : 0);
+}
 
 struct WorkItem {
     int32_t run;      // index into the RunDesc array

@@ -289,7 +289,7 @@ __device__ __forceinline__ int path_variant(Desc *Dp)
 // Update path and acceptance rule of a run, as one switch value.
 __device__ __forceinline__ int step_variant(Desc *Dp)
 {
-    return path_variant(Dp) * 2 + (Dp->accept != 0 ? kAmLenient : kAmStrict);
+    return run_step_variant(Dp->path, Dp->kform, Dp->accept);
 }
 
 }  // namespace mda

@@ -26,7 +26,7 @@ int group_waves_limit(int ns);
 hipError_t launch_group(int ns, int occ, int wr, int wc, const RunDesc *runs, const WorkItem *work, int nwork,
                         const int32_t *lnt, int grid, hipStream_t stream);
 hipError_t group_occupancy(int ns, int occ, int wr, int wc, int *blocks_per_cu);
-hipError_t launch_persistent(int ns, int occ, int f64, const RunDesc *runs, const WorkItem *work, int nwork,
+hipError_t launch_persistent(int ns, int occ, int f64, int sv, const RunDesc *runs, const WorkItem *work, int nwork,
                              const int32_t *lnt, unsigned int *next, int grid, int block, hipStream_t stream);
 hipError_t launch_plain(int ns, const RunDesc *run, int R, uint32_t steps, const int32_t *lnt, int block,
                         hipStream_t stream);
@@ -39,7 +39,7 @@ hipError_t launch_front_gather(const int64_t *archE, const uint8_t *nd, const in
                                const int64_t *offs, FrontEntry *out, hipStream_t stream);
 hipError_t launch_build_dense(int n, int ld, const int32_t *F, const int32_t *Dm, int32_t two_alpha, int32_t *P,
                               hipStream_t stream);
-hipError_t persistent_occupancy(int ns, int occ, int f64, int block, int *blocks_per_cu);
+hipError_t persistent_occupancy(int ns, int occ, int f64, int sv, int block, int *blocks_per_cu);
 }  // namespace mda
 
 using namespace mda;
@@ -864,15 +864,21 @@ static int default_block(int wpb)
 
 namespace {
 
-// One persistent launch: the work items [off, off + cnt) of one register tile
-// and replica layout.
+// One persistent launch: the work items [off, off + cnt) of one register tile,
+// replica layout and field width, and (one wave per replica) step variant sv;
+// the workgroup kernels take every variant (sv = -1).
 struct Group {
-    int ns, wr, wc, f64, off, cnt;
+    int ns, wr, wc, f64, sv, off, cnt;
 };
 
-// Work-item counters a launch holds: one per group (register tile, layout and
-// field width; far fewer combinations exist).
-constexpr int kMaxGroups = 64;
+// Work-item counters a launch holds: one per group (register tile, layout,
+// field width and step variant; far fewer combinations occur).
+constexpr int kMaxGroups = 128;
+
+int group_variant(const RunDesc &d)
+{
+    return d.wr * d.wc == 1 ? run_step_variant(d.path, d.kform, d.accept) : -1;
+}
 
 // Work list of a launch: runs grouped by register tile, largest tile first
 // (one persistent launch per tile, each with the occupancy of its own register
@@ -889,15 +895,17 @@ void plan_work(const std::vector<RunDesc> &descs, std::vector<WorkItem> &work, s
         if (x.wc != y.wc) return x.wc > y.wc;
         if (x.f64 != y.f64) return x.f64 > y.f64;
         if (x.gns != y.gns) return x.gns > y.gns;
+        if (group_variant(x) != group_variant(y)) return group_variant(x) < group_variant(y);
         return (int64_t)x.m * x.steps > (int64_t)y.m * y.steps;
     });
     work.clear();
     groups.clear();
     for (int i : order) {
         const RunDesc &d = descs[i];
+        const int sv = group_variant(d);
         if (groups.empty() || groups.back().ns != d.gns || groups.back().wr != d.wr || groups.back().wc != d.wc ||
-            groups.back().f64 != d.f64)
-            groups.push_back(Group{d.gns, d.wr, d.wc, d.f64, (int)work.size(), 0});
+            groups.back().f64 != d.f64 || groups.back().sv != sv)
+            groups.push_back(Group{d.gns, d.wr, d.wc, d.f64, sv, (int)work.size(), 0});
         for (int rr = 0; rr < d.R; ++rr) work.push_back(WorkItem{i, rr});
         groups.back().cnt += d.R;
     }
@@ -936,21 +944,21 @@ int enqueue_anneal(const std::vector<Group> &groups, const RunDesc &first, bool 
             // one wave per SIMD when that holds every replica of the launch
             // at once, the two-wave build when more are waiting
             const int wpb = block / 64;
-            HIP_TRY(persistent_occupancy(g.ns, 1, g.f64, block, &per_cu));
+            HIP_TRY(persistent_occupancy(g.ns, 1, g.f64, g.sv, block, &per_cu));
             if (per_cu < 1) per_cu = 1;
             // (the int64 build has one register budget only); occ_req 1 or 2
             // overrides the rule
             int occ = !g.f64 && (int64_t)g.cnt > (int64_t)cus * per_cu * wpb ? 2 : 1;
             if (occ_req == 1 || occ_req == 2) occ = g.f64 ? 1 : occ_req;
             if (occ == 2) {
-                HIP_TRY(persistent_occupancy(g.ns, 2, 0, block, &per_cu));
+                HIP_TRY(persistent_occupancy(g.ns, 2, 0, g.sv, block, &per_cu));
                 if (per_cu < 1) per_cu = 1;
             }
             int grid = cus * per_cu;
             const int need = (g.cnt + wpb - 1) / wpb;
             if (grid > need) grid = need;
-            const hipError_t le = launch_persistent(g.ns, occ, g.f64, ddesc, dwork + g.off, g.cnt, dlnt, dctr + gi,
-                                                    grid, block, gs);
+            const hipError_t le = launch_persistent(g.ns, occ, g.f64, g.sv, ddesc, dwork + g.off, g.cnt, dlnt,
+                                                    dctr + gi, grid, block, gs);
             if (le != hipSuccess)
                 return fail(MDA_EDEVICE, "persistent launch (ns %d, grid %d, block %d, %d blocks/CU) failed: %s", g.ns,
                             grid, block, per_cu, hipGetErrorString(le));

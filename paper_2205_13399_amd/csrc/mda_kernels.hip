@@ -128,16 +128,16 @@ int ns_for(int n)
 // Per-tile launchers, each defined in the translation unit that instantiates
 // that tile (mda_wave_ns*.hip), so that the tiles compile in parallel.
 #define MDA_WAVE_DECL(N)                                                                                   \
-    hipError_t launch_persistent_ns##N(int occ, const RunDesc *runs, const WorkItem *work, int nwork,      \
-                                       const int32_t *lnt, unsigned int *next, int grid, int block,        \
-                                       hipStream_t stream);                                                \
-    hipError_t persistent_occupancy_ns##N(int occ, int block, int *blocks_per_cu);                        \
+    hipError_t launch_persistent_ns##N(int occ, int sv, const RunDesc *runs, const WorkItem *work,         \
+                                       int nwork, const int32_t *lnt, unsigned int *next, int grid,        \
+                                       int block, hipStream_t stream);                                     \
+    hipError_t persistent_occupancy_ns##N(int occ, int sv, int block, int *blocks_per_cu);                \
     hipError_t launch_plain_ns##N(const RunDesc *run, int R, uint32_t steps, const int32_t *lnt, int block, \
                                   hipStream_t stream);                                                     \
-    hipError_t launch_persistent64_ns##N(const RunDesc *runs, const WorkItem *work, int nwork,             \
+    hipError_t launch_persistent64_ns##N(int sv, const RunDesc *runs, const WorkItem *work, int nwork,     \
                                          const int32_t *lnt, unsigned int *next, int grid, int block,      \
                                          hipStream_t stream);                                              \
-    hipError_t persistent64_occupancy_ns##N(int block, int *blocks_per_cu);
+    hipError_t persistent64_occupancy_ns##N(int sv, int block, int *blocks_per_cu);
 MDA_NS_LIST(MDA_WAVE_DECL)
 #undef MDA_WAVE_DECL
 
@@ -152,17 +152,19 @@ hipError_t launch_zero_counter(unsigned int *p, hipStream_t stream)
     return hipGetLastError();
 }
 
-// The persistent launch of one tile, preceded by the zeroing of its work-item
-// counter (a kernel, so that the pair can be captured into a graph).
-hipError_t launch_persistent(int ns, int occ, int f64, const RunDesc *runs, const WorkItem *work, int nwork,
+// The persistent launch of one tile and step variant sv, preceded by the
+// zeroing of its work-item counter (a kernel, so that the pair can be captured
+// into a graph).
+hipError_t launch_persistent(int ns, int occ, int f64, int sv, const RunDesc *runs, const WorkItem *work, int nwork,
                              const int32_t *lnt, unsigned int *next, int grid, int block, hipStream_t stream)
 {
+    if (sv < 0 || sv >= kStepVariants) return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_zero_counter, dim3(1), dim3(64), 0, stream, next);
     switch (ns) {
 #define X(N)                                                                                       \
     case N:                                                                                        \
-        return f64 ? launch_persistent64_ns##N(runs, work, nwork, lnt, next, grid, block, stream) \
-                   : launch_persistent_ns##N(occ, runs, work, nwork, lnt, next, grid, block, stream);
+        return f64 ? launch_persistent64_ns##N(sv, runs, work, nwork, lnt, next, grid, block, stream) \
+                   : launch_persistent_ns##N(occ, sv, runs, work, nwork, lnt, next, grid, block, stream);
         MDA_NS_LIST(X)
 #undef X
     default:
@@ -170,13 +172,13 @@ hipError_t launch_persistent(int ns, int occ, int f64, const RunDesc *runs, cons
     }
 }
 
-hipError_t persistent_occupancy(int ns, int occ, int f64, int block, int *blocks_per_cu)
+hipError_t persistent_occupancy(int ns, int occ, int f64, int sv, int block, int *blocks_per_cu)
 {
     switch (ns) {
 #define X(N)                                                                     \
     case N:                                                                      \
-        return f64 ? persistent64_occupancy_ns##N(block, blocks_per_cu)          \
-                   : persistent_occupancy_ns##N(occ, block, blocks_per_cu);
+        return f64 ? persistent64_occupancy_ns##N(sv, block, blocks_per_cu)      \
+                   : persistent_occupancy_ns##N(occ, sv, block, blocks_per_cu);
         MDA_NS_LIST(X)
 #undef X
     default:

@@ -601,15 +601,19 @@ __device__ __forceinline__ void run_replica(Desc *Dp, int r, int lane, MDA_LDS i
 // orders the items largest first), each for all of its steps with the replica
 // state in registers.  Replicas of one instance can differ a lot in length (an
 // archive that grows large makes every move scan it), so a fixed assignment of
-// items to waves would leave the launch waiting for its unluckiest wave.  From 40 slots up the
-// kernel holds one wave per SIMD (OCC = 1); the OCC = 2 build keeps part of the
-// cold-path state (initial fields, restarts, archive scans) in scratch so that
-// a second wave per SIMD hides the latency of the first.  The host takes it
-// when a launch has more replicas than one wave per SIMD can hold at once
-// (n = 50 benchmark launch: 2.45 s -> 1.69 s; three waves spill the step's
-// own state and are slower).
+// items to waves would leave the launch waiting for its unluckiest wave.
+// Every item of a launch has step variant SV (update path and acceptance
+// rule; the host groups the work list by it), so the kernel holds one variant
+// of the step: a build with all six behind a switch needs twice the scratch of
+// the two-wave budget and is 4.5 % slower on the n = 50 benchmark launch.
+// From 40 slots up the kernel holds one wave per SIMD (OCC = 1); the OCC = 2
+// build keeps part of the cold-path state (initial fields, restarts, archive
+// scans) in scratch so that a second wave per SIMD hides the latency of the
+// first.  The host takes it when a launch has more replicas than one wave per
+// SIMD can hold at once (n = 50 benchmark launch: 2.45 s -> 1.69 s; three
+// waves spill the step's own state and are slower).
 // F64 = 1: the int64-difference build (one wave per SIMD).
-template <int NS, int OCC, int F64>
+template <int NS, int OCC, int F64, int SV>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(OCC))) k_persistent(const RunDesc *runs, const WorkItem *work, int nwork,
                                                     const int32_t *lnt_, unsigned int *next)
 {
@@ -630,15 +634,8 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(OCC)))
         const WorkItem w = {ro(work)[item].run, ro(work)[item].replica};
         Desc *Dp = ro(runs) + uni(w.run);
         const int r = uni(w.replica);
-        switch (step_variant(Dp)) {
-#define X(PV, AM)                                        \
-    case PV * 2 + AM:                                    \
-        run_replica<NS, PV, AM, FT>(Dp, r, lane, tab, lnt); \
-        break;
-            MDA_STEP_VARIANTS(X)
-#undef X
-        default: break;
-        }
+        // (an item of another variant is never planned into this launch)
+        if (step_variant(Dp) == SV) run_replica<NS, SV / 2, SV % 2, FT>(Dp, r, lane, tab, lnt);
     }
 }
 

@@ -16,50 +16,65 @@ inline size_t persistent_lds(int block)
     return (size_t)(block / 64) * 4096 * sizeof(int32_t);
 }
 
+// Kernel of step variant sv (the six values of MDA_STEP_VARIANTS), or
+// nullptr for a value out of range.
+template <int OCC, int F64>
+static const void *persistent_kernel(int sv)
+{
+    switch (sv) {
+#define X(PV, AM) \
+    case PV * 2 + AM: return reinterpret_cast<const void *>(&k_persistent<MDA_TILE, OCC, F64, PV * 2 + AM>);
+        MDA_STEP_VARIANTS(X)
+#undef X
+    default: return nullptr;
+    }
+}
+
+static hipError_t launch_kernel(const void *k, const RunDesc *runs, const WorkItem *work, int nwork,
+                                const int32_t *lnt, unsigned int *next, int grid, int block, hipStream_t stream)
+{
+    if (!k) return hipErrorInvalidValue;
+    void *args[] = {(void *)&runs, (void *)&work, (void *)&nwork, (void *)&lnt, (void *)&next};
+    return hipLaunchKernel(k, dim3(grid), dim3(block), args, persistent_lds(block), stream);
+}
+
 #ifdef MDA_F64
 // int64 differences: one build, the natural register budget (its state is
 // twice that of the int32 build, so a second wave per SIMD would only spill).
-hipError_t MDA_CAT(launch_persistent64_ns, MDA_TILE)(const RunDesc *runs, const WorkItem *work, int nwork,
+hipError_t MDA_CAT(launch_persistent64_ns, MDA_TILE)(int sv, const RunDesc *runs, const WorkItem *work, int nwork,
                                                     const int32_t *lnt, unsigned int *next, int grid, int block,
                                                     hipStream_t stream)
 {
-    hipLaunchKernelGGL((k_persistent<MDA_TILE, 1, 1>), dim3(grid), dim3(block), persistent_lds(block), stream, runs,
-                       work, nwork, lnt, next);
-    return hipGetLastError();
+    return launch_kernel(persistent_kernel<1, 1>(sv), runs, work, nwork, lnt, next, grid, block, stream);
 }
 
-hipError_t MDA_CAT(persistent64_occupancy_ns, MDA_TILE)(int block, int *blocks_per_cu)
+hipError_t MDA_CAT(persistent64_occupancy_ns, MDA_TILE)(int sv, int block, int *blocks_per_cu)
 {
-    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_persistent<MDA_TILE, 1, 1>, block,
-                                                        persistent_lds(block));
+    const void *k = persistent_kernel<1, 1>(sv);
+    if (!k) return hipErrorInvalidValue;
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k, block, persistent_lds(block));
 }
 #else
 // From 40 slots up a second build holds two waves per SIMD (see k_persistent).
 constexpr int kTileOcc2 = MDA_TILE >= 40 ? 2 : 1;
 
-hipError_t MDA_CAT(launch_persistent_ns, MDA_TILE)(int occ, const RunDesc *runs, const WorkItem *work, int nwork,
-                                                  const int32_t *lnt, unsigned int *next, int grid, int block,
-                                                  hipStream_t stream)
+static const void *persistent_kernel_occ(int occ, int sv)
 {
-    const size_t lds = persistent_lds(block);
-    if (occ >= 2 && kTileOcc2 == 2) {
-        hipLaunchKernelGGL((k_persistent<MDA_TILE, kTileOcc2, 0>), dim3(grid), dim3(block), lds, stream, runs, work,
-                           nwork, lnt, next);
-    } else {
-        hipLaunchKernelGGL((k_persistent<MDA_TILE, 1, 0>), dim3(grid), dim3(block), lds, stream, runs, work, nwork,
-                           lnt, next);
-    }
-    return hipGetLastError();
+    return (occ >= 2 && kTileOcc2 == 2) ? persistent_kernel<kTileOcc2, 0>(sv) : persistent_kernel<1, 0>(sv);
 }
 
-hipError_t MDA_CAT(persistent_occupancy_ns, MDA_TILE)(int occ, int block, int *blocks_per_cu)
+hipError_t MDA_CAT(launch_persistent_ns, MDA_TILE)(int occ, int sv, const RunDesc *runs, const WorkItem *work,
+                                                  int nwork, const int32_t *lnt, unsigned int *next, int grid,
+                                                  int block, hipStream_t stream)
 {
-    const size_t lds = persistent_lds(block);
-    if (occ >= 2 && kTileOcc2 == 2) {
-        return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_persistent<MDA_TILE, kTileOcc2, 0>, block,
-                                                            lds);
-    }
-    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_persistent<MDA_TILE, 1, 0>, block, lds);
+    return launch_kernel(persistent_kernel_occ(occ, sv), runs, work, nwork, lnt, next, grid, block, stream);
+}
+
+hipError_t MDA_CAT(persistent_occupancy_ns, MDA_TILE)(int occ, int sv, int block, int *blocks_per_cu)
+{
+    const void *k = persistent_kernel_occ(occ, sv);
+    if (!k) return hipErrorInvalidValue;
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k, block, persistent_lds(block));
 }
 
 hipError_t MDA_CAT(launch_plain_ns, MDA_TILE)(const RunDesc *run, int R, uint32_t steps, const int32_t *lnt, int block,
