@@ -105,10 +105,6 @@ __device__ __forceinline__ int kth_lane(uint64_t M, int k, int lane)
     return uni(__ffsll((long long)__ballot(hit)) - 1);
 }
 
-// p dominates q (Section 3.3): p_k <= q_k for every k, not equal in all.  With
-// d_k = q_k - p_k (energies stay far inside int64), the bitwise OR of the d_k
-// is negative when some d_k is, zero when all are, and positive exactly when p
-// dominates q: one sign test, no per-objective compare masks.
 // Index of the next work item from a launch's counter (one atomic per call,
 // made by lane 0 and broadcast to the wave).
 __device__ __forceinline__ int next_item(unsigned int *next, int lane)
@@ -118,6 +114,10 @@ __device__ __forceinline__ int next_item(unsigned int *next, int lane)
     return uni((int)v);
 }
 
+// p dominates q (Section 3.3): p_k <= q_k for every k, not equal in all.  With
+// d_k = q_k - p_k (energies stay far inside int64), the bitwise OR of the d_k
+// is negative when some d_k is, zero when all are, and positive exactly when p
+// dominates q: one sign test, no per-objective compare masks.
 __device__ __forceinline__ bool dominates(int64_t p1, int64_t p2, int64_t q1, int64_t q2)
 {
     return ((q1 - p1) | (q2 - p2)) > 0;

@@ -196,17 +196,23 @@ __device__ __forceinline__ void g_archive(GDesc *Dp, GRep<K, S> &G, int r, uint3
     int slot = -1;
     if (D.archive == 0) {
         // first member that x dominates, 4 blocks of 64 members per round trip
+        // (all reads of a trip issued before any test; lanes past the end
+        // through a bitwise AND, not a branch per block)
         constexpr int kAB = 4;
         for (int b = 0; b < asz; b += 64 * kAB) {
-            uint64_t M[kAB];
+            int64_t a[kAB][K];
 #pragma unroll
             for (int q = 0; q < kAB; ++q) {
                 const int e = b + 64 * q + lane;
                 const int ec = e < asz ? e : asz - 1;
-                int64_t a[K];
 #pragma unroll
-                for (int k = 0; k < K; ++k) a[k] = AL[k * s + ec];
-                M[q] = __ballot(e < asz && gdom<K>(E, a));
+                for (int k = 0; k < K; ++k) a[q][k] = AL[k * s + ec];
+            }
+            uint64_t M[kAB];
+#pragma unroll
+            for (int q = 0; q < kAB; ++q) {
+                const int e = b + 64 * q + lane;
+                M[q] = __ballot((e < asz) & gdom<K>(E, a[q]));
             }
             int q = -1;
 #pragma unroll

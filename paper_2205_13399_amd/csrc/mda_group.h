@@ -270,16 +270,24 @@ __device__ __forceinline__ void g_archive(Desc *Dp, Replica<NS> &S, int r, uint3
     int slot = -1;
     if (D.archive == 0) {
         // first member that x dominates, 8 blocks of 64 members per round trip
-        // (indices clamped into the archive, so every read is in bounds)
+        // (indices clamped into the archive, so every read is in bounds; all
+        // loads of a trip are issued before any test, which takes lanes past
+        // the end through a bitwise AND rather than a branch per block)
         constexpr int kAB = 8;
         for (int b = 0; b < asz; b += 64 * kAB) {
-            uint64_t M[kAB];
+            int64_t a1[kAB], a2[kAB];
 #pragma unroll
             for (int q = 0; q < kAB; ++q) {
                 const int e = b + 64 * q + lane;
                 const int ec = e < asz ? e : asz - 1;
-                const int64_t a1 = AE[2 * ec], a2 = AE[2 * ec + 1];
-                M[q] = __ballot(e < asz && dominates(E1, E2, a1, a2));
+                a1[q] = AE[2 * ec];
+                a2[q] = AE[2 * ec + 1];
+            }
+            uint64_t M[kAB];
+#pragma unroll
+            for (int q = 0; q < kAB; ++q) {
+                const int e = b + 64 * q + lane;
+                M[q] = __ballot((e < asz) & dominates(E1, E2, a1[q], a2[q]));
             }
             int q = -1;
 #pragma unroll

@@ -249,15 +249,25 @@ __device__ __forceinline__ void archive_update(Desc *Dp, int n, Replica<NS, FT> 
         // once (indices clamped into the archive, so every read is in bounds).
         // The archives do not fit the caches, so each round trip waits on
         // memory: 8 blocks per trip beat 4 and 16 on the benchmark launch.
+        // The loads of a round trip are issued before any of their values is
+        // tested, and lanes past the end take their test through a bitwise
+        // AND: a short-circuit test let the compiler move each load under its
+        // own branch, one memory wait per block.
         constexpr int kAB = 8;
         for (int b = 0; b < asz; b += 64 * kAB) {
-            uint64_t M[kAB];
+            int64_t a1[kAB], a2[kAB];
 #pragma unroll
             for (int q = 0; q < kAB; ++q) {
                 const int e = b + 64 * q + lane;
                 const int ec = e < asz ? e : asz - 1;
-                const int64_t a1 = AE[2 * ec], a2 = AE[2 * ec + 1];
-                M[q] = __ballot(e < asz && dominates(E1, E2, a1, a2));
+                a1[q] = AE[2 * ec];
+                a2[q] = AE[2 * ec + 1];
+            }
+            uint64_t M[kAB];
+#pragma unroll
+            for (int q = 0; q < kAB; ++q) {
+                const int e = b + 64 * q + lane;
+                M[q] = __ballot((e < asz) & dominates(E1, E2, a1[q], a2[q]));
             }
             int q = -1;
 #pragma unroll
