@@ -365,6 +365,68 @@ __device__ __forceinline__ void group_minima(Replica<NS, FT> &S)
     }
 }
 
+// Offset and reach of the cheap "can any bit be accepted" test of a step whose
+// largest acceptance threshold is thrmax: a bit can only be accepted when its
+// combined difference is at most the reach.  int32 differences: every real dE
+// is at most 2^31 - 2 (build-time bound), so capping the offset and the reach
+// at 2^31 - 2 keeps all comparisons exact while slots and lanes beyond n, which
+// hold INT_MAX, never qualify.  int64 differences: the offset (at most steps *
+// beta) and the threshold (below 2^39) stay far below the dead values (2^60
+// and up).
+template <class FT>
+__device__ __forceinline__ FT capped_offset(int64_t Eoff)
+{
+    return sizeof(FT) == 8 ? (FT)Eoff : (FT)(Eoff < (int64_t)(INT_MAX - 1) ? Eoff : (int64_t)(INT_MAX - 1));
+}
+
+template <class FT>
+__device__ __forceinline__ FT step_reach(int64_t Eoff, int64_t thrmax)
+{
+    const int64_t Xl = (int64_t)capped_offset<FT>(Eoff) + thrmax;
+    return sizeof(FT) == 8 ? (FT)Xl : (FT)(Xl < (int64_t)(INT_MAX - 1) ? Xl : (int64_t)(INT_MAX - 1));
+}
+
+// Least combined difference over the whole replica (every slot and lane):
+// the cheap test of a step passes exactly when it is within the step's reach.
+template <int NS, class FT>
+__device__ __forceinline__ FT wave_least(const Replica<NS, FT> &S)
+{
+    FT mn = Wide<FT>::kMax;
+#pragma unroll
+    for (int g = 0; g < NS / 8; ++g) mn = min(mn, S.gmin[g]);
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        if (sizeof(FT) == 8) {
+            const uint64_t u = (uint64_t)(int64_t)mn;
+            const int lo = __shfl_xor((int)(uint32_t)u, off), hi = __shfl_xor((int)(uint32_t)(u >> 32), off);
+            mn = min(mn, (FT)(int64_t)(((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo));
+        } else {
+            mn = min(mn, (FT)__shfl_xor((int)mn, off));
+        }
+    }
+    return sizeof(FT) == 8 ? (FT)uni64((int64_t)mn) : (FT)uni((int)mn);
+}
+
+// Steps, from the present one and at most rem, whose cheap test fails while
+// the fields stay as they are: with the offset escape such a step only raises
+// the offset by beta, so step k of the stretch has offset Eoff + k beta and a
+// candidate first appears at the least k with Eoff + k beta + thr >= least
+// (thr the constant largest threshold; least <= 2^31 - 2 for int32 differences,
+// so the caps of step_reach do not change the answer).
+__device__ __forceinline__ uint32_t quiet_steps(int64_t least, int64_t Eoff, int64_t thr, int64_t beta, uint32_t rem)
+{
+    const int64_t need = least - thr - Eoff;
+    if (need <= 0) return 0u;
+    uint64_t k;
+    if (need <= (int64_t)UINT32_MAX && beta <= (int64_t)UINT32_MAX) {
+        const uint32_t nd = (uint32_t)need, b = (uint32_t)beta;
+        k = (uint64_t)(nd / b + (nd % b != 0u ? 1u : 0u));
+    } else {
+        k = (uint64_t)need / (uint64_t)beta + ((uint64_t)need % (uint64_t)beta != 0u ? 1u : 0u);
+    }
+    return k < (uint64_t)rem ? (uint32_t)k : rem;
+}
+
 // One annealing step t of replica r whose largest acceptance threshold
 // (T_t * LNT[0]) >> 24 is thrmax.  Returns the flipped bit or -1.  lnt is the
 // -ln table; with THR (int32 differences at the schedule's final, constant
@@ -375,20 +437,13 @@ __device__ __forceinline__ int anneal_step(Desc *Dp, const Hot &H, Replica<NS, F
                                            LP lnt, int64_t thrmax)
 {
     constexpr bool strict = AM == kAmStrict;
-    constexpr bool wide = sizeof(FT) == 8;
     using UT = typename Wide<FT>::U;
     const int lane = lane_;
     const int n = H.n;
     const uint64_t actmask = (n >= 64) ? ~0ull : ((1ull << n) - 1ull);
     const uint32_t ti = table_index(t, H.ntab);
-    // int32 differences: every real dE is at most 2^31 - 2 (build-time bound),
-    // so capping the offset and the largest threshold at 2^31 - 2 keeps all
-    // comparisons exact while slots and lanes beyond n, which hold INT_MAX,
-    // never qualify.  int64 differences: the offset (at most steps * beta) and
-    // the threshold (below 2^39) stay far below the dead values (2^60 and up).
-    const FT EoC = wide ? (FT)S.Eoff : (FT)(S.Eoff < (int64_t)(INT_MAX - 1) ? S.Eoff : (int64_t)(INT_MAX - 1));
-    const int64_t Xl = (int64_t)EoC + thrmax;
-    const FT X = wide ? (FT)Xl : (FT)(Xl < (int64_t)(INT_MAX - 1) ? Xl : (int64_t)(INT_MAX - 1));
+    const FT EoC = capped_offset<FT>(S.Eoff);
+    const FT X = step_reach<FT>(S.Eoff, thrmax);
 
     // 1. can any bit be accepted?  The minimum is kept per group of 8 slots so
     // that step 2 passes over groups in which no lane comes within reach.
@@ -562,6 +617,16 @@ __device__ __forceinline__ int64_t thr_entry(const Hot &H, uint32_t k)
     return sizeof(FT) == 8 ? H.thrmax64[k] : (int64_t)H.thrmax[k];
 }
 
+// Trace entries (no flip) of the k steps from t of a replica that records its
+// trajectory.
+__device__ __forceinline__ void quiet_trace(Desc *Dp, const Hot &H, int r, uint32_t t, uint32_t k, int lane)
+{
+    if (r < H.trace_R) {
+        MDA_GLOBAL int32_t *tr = rw(cold(Dp)->trace) + (size_t)r * H.steps + (t - 1u);
+        for (uint32_t i = (uint32_t)lane; i < k; i += 64u) tr[i] = -1;
+    }
+}
+
 // All steps of one replica with its state in registers.  tab is the wave's
 // 4096 words of LDS: the -ln table (copied from lnt_g) while the temperature
 // changes; from step ntab on, where it stays at its last value, the int32 build
@@ -577,6 +642,13 @@ __device__ __forceinline__ void run_replica(Desc *Dp, int r, int lane, MDA_LDS i
     init_replica<NS, PV>(Dp, S, r, lane);
     group_minima<NS, AM>(S);
     const Hot H = load_hot(Dp);
+    // With the offset escape a step whose cheap test fails does nothing but
+    // raise the offset by beta.  Such steps are decided against the replica's
+    // least combined difference, which only changes with a move, by the scalar
+    // unit alone: one by one while the temperature changes, a whole stretch at
+    // once (quiet_steps) after that.
+    const bool skip = H.escape == 0;
+    FT least = wave_least(S);
     // the next step's threshold is loaded one step ahead
     int64_t thr = thr_entry<FT>(H, 0);
     const uint32_t cool = wide ? H.steps : ((H.ntab - 1u < H.steps) ? H.ntab - 1u : H.steps);
@@ -584,7 +656,12 @@ __device__ __forceinline__ void run_replica(Desc *Dp, int r, int lane, MDA_LDS i
     for (; t <= cool; ++t) {
         // entry of step t + 1: min(t + 1, ntab) - 1 = min(t, ntab - 1), ntab >= 1
         const int64_t thr_next = thr_entry<FT>(H, (t < H.ntab - 1u) ? t : H.ntab - 1u);
-        anneal_step<NS, PV, AM>(Dp, H, S, r, t, lane, (const MDA_LDS int32_t *)tab, thr);
+        if (skip && least > step_reach<FT>(S.Eoff, thr)) {
+            S.Eoff += H.beta;
+            quiet_trace(Dp, H, r, t, 1u, lane);
+        } else if (anneal_step<NS, PV, AM>(Dp, H, S, r, t, lane, (const MDA_LDS int32_t *)tab, thr) >= 0) {
+            least = wave_least(S);
+        }
         thr = thr_next;
     }
     if (!wide && t <= H.steps) {
@@ -595,9 +672,21 @@ __device__ __forceinline__ void run_replica(Desc *Dp, int r, int lane, MDA_LDS i
             const uint64_t v = (T * (uint64_t)((uint32_t)tab[k] & 0xFFFFFu)) >> 24;
             tab[k] = (int32_t)(uint32_t)(v < 0xFFFFFFFFull ? v : 0xFFFFFFFFull);
         }
-        for (; t <= H.steps; ++t)
-            anneal_step<NS, PV, AM, FT, const MDA_LDS int32_t *, true>(Dp, H, S, r, t, lane,
-                                                                      (const MDA_LDS int32_t *)tab, thr);
+        while (t <= H.steps) {
+            if (skip) {
+                const uint32_t k = quiet_steps((int64_t)least, S.Eoff, thr, H.beta, H.steps - t + 1u);
+                if (k > 0u) {
+                    S.Eoff += (int64_t)k * H.beta;
+                    quiet_trace(Dp, H, r, t, k, lane);
+                    t += k;
+                    continue;
+                }
+            }
+            if (anneal_step<NS, PV, AM, FT, const MDA_LDS int32_t *, true>(Dp, H, S, r, t, lane,
+                                                                         (const MDA_LDS int32_t *)tab, thr) >= 0)
+                least = wave_least(S);
+            ++t;
+        }
     }
     export_replica<NS>(Dp, S, r, lane);
 }
