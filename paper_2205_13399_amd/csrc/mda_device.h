@@ -274,6 +274,47 @@ __device__ __forceinline__ int64_t wave_sum64(int64_t v)
 // (Eq. pacceptml).
 enum : int { kAmStrict = 0, kAmLenient = 1 };
 
+// Offset and reach of the cheap "can any bit be accepted" test of a step whose
+// largest acceptance threshold is thrmax: a bit can only be accepted when its
+// combined difference is at most the reach.  int32 differences: every real dE
+// is at most 2^31 - 2 (build-time bound), so capping the offset and the reach
+// at 2^31 - 2 keeps all comparisons exact while slots and lanes beyond n, which
+// hold INT_MAX, never qualify.  int64 differences: the offset (at most steps *
+// beta) and the threshold (below 2^39) stay far below the dead values (2^60
+// and up).
+template <class FT>
+__device__ __forceinline__ FT capped_offset(int64_t Eoff)
+{
+    return sizeof(FT) == 8 ? (FT)Eoff : (FT)(Eoff < (int64_t)(INT_MAX - 1) ? Eoff : (int64_t)(INT_MAX - 1));
+}
+
+template <class FT>
+__device__ __forceinline__ FT step_reach(int64_t Eoff, int64_t thrmax)
+{
+    const int64_t Xl = (int64_t)capped_offset<FT>(Eoff) + thrmax;
+    return sizeof(FT) == 8 ? (FT)Xl : (FT)(Xl < (int64_t)(INT_MAX - 1) ? Xl : (int64_t)(INT_MAX - 1));
+}
+
+// Steps, from the present one and at most rem, whose cheap test fails while
+// the fields stay as they are: with the offset escape such a step only raises
+// the offset by beta, so step k of the stretch has offset Eoff + k beta and a
+// candidate first appears at the least k with Eoff + k beta + thr >= least
+// (thr the constant largest threshold; least <= 2^31 - 2 for int32 differences,
+// so the caps of step_reach do not change the answer).
+__device__ __forceinline__ uint32_t quiet_steps(int64_t least, int64_t Eoff, int64_t thr, int64_t beta, uint32_t rem)
+{
+    const int64_t need = least - thr - Eoff;
+    if (need <= 0) return 0u;
+    uint64_t k;
+    if (need <= (int64_t)UINT32_MAX && beta <= (int64_t)UINT32_MAX) {
+        const uint32_t nd = (uint32_t)need, b = (uint32_t)beta;
+        k = (uint64_t)(nd / b + (nd % b != 0u ? 1u : 0u));
+    } else {
+        k = (uint64_t)need / (uint64_t)beta + ((uint64_t)need % (uint64_t)beta != 0u ? 1u : 0u);
+    }
+    return k < (uint64_t)rem ? (uint32_t)k : rem;
+}
+
 // Index into the temperature tables for step t (the schedule is constant after
 // its last entry).
 __device__ __forceinline__ uint32_t table_index(uint32_t t, uint32_t ntab)

@@ -462,6 +462,31 @@ __device__ __forceinline__ void g_export(GDesc *Dp, const GRep<K, S> &G, int r, 
     }
 }
 
+// Least of the group minima over the live lanes: a step's cheap test passes
+// exactly when it is within the step's reach.
+template <int K, int S>
+__device__ __forceinline__ int32_t g_least(const GRep<K, S> &G, int nl, int lane)
+{
+    int32_t mn = INT_MAX;
+#pragma unroll
+    for (int g = 0; g < S / 8; ++g) mn = min(mn, G.gmin[g]);
+    mn = lane < nl ? mn : INT_MAX;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) mn = min(mn, __shfl_xor(mn, off));
+    return uni(mn);
+}
+
+// Trace entries (no flip) of the q steps from t of a replica that records its
+// trajectory.
+__device__ __forceinline__ void g_quiet_trace(GDesc *Dp, int trace_R, int r, uint32_t t, uint32_t q, int lane)
+{
+    if (r < trace_R) {
+        GDesc &D = *gcold(Dp);
+        MDA_GLOBAL int32_t *tr = rw(D.trace) + (size_t)r * D.steps + (t - 1u);
+        for (uint32_t i = (uint32_t)lane; i < q; i += 64u) tr[i] = -1;
+    }
+}
+
 // thrt: the block's thresholds at the final temperature, or NULL when some
 // would not fit 32 bits (then every step forms its thresholds from lnt).
 template <int K, int S, int AM>
@@ -473,15 +498,41 @@ __device__ __forceinline__ void g_run(GDesc *Dp, int r, int lane, const MDA_LDS 
     g_minima<K, S, AM>(G);
     const uint32_t steps = Dp->steps, ntab = Dp->ntab;
     const MDA_CONST int64_t *thrmax = ro(Dp->thrmax);
+    // With the offset escape a step whose cheap test fails does nothing but
+    // raise the offset: such steps are decided against the replica's least
+    // combined difference (live lanes), which only changes with a move, by the
+    // scalar unit alone: one by one while the temperature changes, a whole
+    // stretch at once (quiet_steps) at the final temperature.
+    const bool skip = Dp->escape == 0;
+    const int64_t beta = Dp->beta;
+    const int trace_R = Dp->trace_R;
+    int32_t least = g_least<K, S>(G, Dp->nl, lane);
     int64_t thr = thrmax[0];
     const uint32_t cool = (thrt == nullptr || ntab - 1u > steps) ? steps : ntab - 1u;
     uint32_t t = 1;
     for (; t <= cool; ++t) {
         const int64_t thr_next = thrmax[(t < ntab - 1u) ? t : ntab - 1u];
-        g_step<K, S, AM>(Dp, G, r, t, lane, lnt, thr, AL);
+        if (skip && (int64_t)least > (int64_t)step_reach<int32_t>(G.Eoff, thr)) {
+            G.Eoff += beta;
+            g_quiet_trace(Dp, trace_R, r, t, 1u, lane);
+        } else if (g_step<K, S, AM>(Dp, G, r, t, lane, lnt, thr, AL) >= 0) {
+            least = g_least<K, S>(G, Dp->nl, lane);
+        }
         thr = thr_next;
     }
-    for (; t <= steps; ++t) g_step<K, S, AM, true>(Dp, G, r, t, lane, thrt, thr, AL);
+    while (t <= steps) {
+        if (skip) {
+            const uint32_t q = quiet_steps((int64_t)least, G.Eoff, thr, beta, steps - t + 1u);
+            if (q > 0u) {
+                G.Eoff += (int64_t)q * beta;
+                g_quiet_trace(Dp, trace_R, r, t, q, lane);
+                t += q;
+                continue;
+            }
+        }
+        if (g_step<K, S, AM, true>(Dp, G, r, t, lane, thrt, thr, AL) >= 0) least = g_least<K, S>(G, Dp->nl, lane);
+        ++t;
+    }
     g_export<K, S>(Dp, G, r, lane);
 }
 

@@ -354,9 +354,9 @@ __device__ __forceinline__ void g_archive(Desc *Dp, Replica<NS> &S, int r, uint3
     }
 }
 
-// One annealing step of the workgroup form.
+// One annealing step of the workgroup form; true when a bit was flipped.
 template <int NS, int PV, int AM>
-__device__ __forceinline__ void g_step(Desc *Dp, const Hot &H, Replica<NS> &S, int r, uint32_t t, const Geo &g,
+__device__ __forceinline__ bool g_step(Desc *Dp, const Hot &H, Replica<NS> &S, int r, uint32_t t, const Geo &g,
                                        GroupLds &L, uint32_t thrmax)
 {
     constexpr bool strict = AM == kAmStrict;
@@ -524,6 +524,28 @@ __device__ __forceinline__ void g_step(Desc *Dp, const Hot &H, Replica<NS> &S, i
             g_restart<NS, PV>(Dp, S, r, pm, g, L);
         }
     }
+    return moved;
+}
+
+// Least combined difference over the whole replica (every wave, live lanes,
+// all slots), the same in every wave: a step's cheap test passes exactly when
+// it is within the step's reach.
+template <int NS, int AM>
+__device__ __forceinline__ int32_t g_least(const Replica<NS> &S, const Geo &g, GroupLds &L, int n)
+{
+    constexpr bool strict = AM == kAmStrict;
+    int32_t mn = INT_MAX;
+#pragma unroll
+    for (int s = 0; s < NS; ++s) mn = min(mn, strict ? max(S.e1[s], S.e2[s]) : min(S.e1[s], S.e2[s]));
+    mn = g.u < n ? mn : INT_MAX;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) mn = min(mn, __shfl_xor(mn, off));
+    if (g.lane == 0) L.part[g.w][3] = mn;
+    __syncthreads();
+    int32_t least = INT_MAX;
+    for (int w2 = 0; w2 < g.G; ++w2) least = min(least, (int32_t)L.part[w2][3]);
+    __syncthreads();   // part[] is free again
+    return uni(least);
 }
 
 // Final state: fields, solution block, statistics (random blocks summed over
@@ -576,11 +598,34 @@ __device__ __forceinline__ void g_run(Desc *Dp, int r, const Geo &g, GroupLds &L
     Replica<NS> S;
     g_init<NS, PV>(Dp, S, r, g, L);
     const Hot H = load_hot(Dp);
+    // With the offset escape a step whose cheap test fails does nothing but
+    // raise the offset: such steps are decided against the replica's least
+    // combined difference (every wave holds the same value and takes the same
+    // decision), with no barrier, one by one while the temperature changes and
+    // a whole stretch at once (quiet_steps) after that.
+    const bool skip = H.escape == 0;
+    int32_t least = skip ? g_least<NS, AM>(S, g, L, H.n) : 0;
     uint32_t thr = H.thrmax[0];
-    for (uint32_t t = 1; t <= H.steps; ++t) {
-        const uint32_t thr_next = H.thrmax[(t < H.ntab - 1u) ? t : H.ntab - 1u];
-        g_step<NS, PV, AM>(Dp, H, S, r, t, g, L, thr);
-        thr = thr_next;
+    uint32_t t = 1;
+    while (t <= H.steps) {
+        uint32_t quiet = 0;
+        if (skip) {
+            if (t >= H.ntab) quiet = quiet_steps((int64_t)least, S.Eoff, (int64_t)thr, H.beta, H.steps - t + 1u);
+            else quiet = (int64_t)least > (int64_t)step_reach<int32_t>(S.Eoff, (int64_t)thr) ? 1u : 0u;
+        }
+        if (quiet > 0u) {
+            S.Eoff += (int64_t)quiet * H.beta;
+            if (r < H.trace_R && g.w == 0) {
+                MDA_GLOBAL int32_t *tr = rw(cold(Dp)->trace) + (size_t)r * H.steps + (t - 1u);
+                for (uint32_t i = (uint32_t)g.lane; i < quiet; i += 64u) tr[i] = -1;
+            }
+        } else {
+            quiet = 1u;
+            if (g_step<NS, PV, AM>(Dp, H, S, r, t, g, L, thr) && skip) least = g_least<NS, AM>(S, g, L, H.n);
+        }
+        t += quiet;
+        // threshold of step t: table entry min(t, ntab) - 1
+        if (t <= H.steps) thr = H.thrmax[(t < H.ntab ? t : H.ntab) - 1u];
     }
     g_export<NS>(Dp, S, r, g, L);
 }

@@ -365,27 +365,6 @@ __device__ __forceinline__ void group_minima(Replica<NS, FT> &S)
     }
 }
 
-// Offset and reach of the cheap "can any bit be accepted" test of a step whose
-// largest acceptance threshold is thrmax: a bit can only be accepted when its
-// combined difference is at most the reach.  int32 differences: every real dE
-// is at most 2^31 - 2 (build-time bound), so capping the offset and the reach
-// at 2^31 - 2 keeps all comparisons exact while slots and lanes beyond n, which
-// hold INT_MAX, never qualify.  int64 differences: the offset (at most steps *
-// beta) and the threshold (below 2^39) stay far below the dead values (2^60
-// and up).
-template <class FT>
-__device__ __forceinline__ FT capped_offset(int64_t Eoff)
-{
-    return sizeof(FT) == 8 ? (FT)Eoff : (FT)(Eoff < (int64_t)(INT_MAX - 1) ? Eoff : (int64_t)(INT_MAX - 1));
-}
-
-template <class FT>
-__device__ __forceinline__ FT step_reach(int64_t Eoff, int64_t thrmax)
-{
-    const int64_t Xl = (int64_t)capped_offset<FT>(Eoff) + thrmax;
-    return sizeof(FT) == 8 ? (FT)Xl : (FT)(Xl < (int64_t)(INT_MAX - 1) ? Xl : (int64_t)(INT_MAX - 1));
-}
-
 // Least combined difference over the whole replica (every slot and lane):
 // the cheap test of a step passes exactly when it is within the step's reach.
 template <int NS, class FT>
@@ -405,26 +384,6 @@ __device__ __forceinline__ FT wave_least(const Replica<NS, FT> &S)
         }
     }
     return sizeof(FT) == 8 ? (FT)uni64((int64_t)mn) : (FT)uni((int)mn);
-}
-
-// Steps, from the present one and at most rem, whose cheap test fails while
-// the fields stay as they are: with the offset escape such a step only raises
-// the offset by beta, so step k of the stretch has offset Eoff + k beta and a
-// candidate first appears at the least k with Eoff + k beta + thr >= least
-// (thr the constant largest threshold; least <= 2^31 - 2 for int32 differences,
-// so the caps of step_reach do not change the answer).
-__device__ __forceinline__ uint32_t quiet_steps(int64_t least, int64_t Eoff, int64_t thr, int64_t beta, uint32_t rem)
-{
-    const int64_t need = least - thr - Eoff;
-    if (need <= 0) return 0u;
-    uint64_t k;
-    if (need <= (int64_t)UINT32_MAX && beta <= (int64_t)UINT32_MAX) {
-        const uint32_t nd = (uint32_t)need, b = (uint32_t)beta;
-        k = (uint64_t)(nd / b + (nd % b != 0u ? 1u : 0u));
-    } else {
-        k = (uint64_t)need / (uint64_t)beta + ((uint64_t)need % (uint64_t)beta != 0u ? 1u : 0u);
-    }
-    return k < (uint64_t)rem ? (uint32_t)k : rem;
 }
 
 // One annealing step t of replica r whose largest acceptance threshold
