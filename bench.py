@@ -433,7 +433,7 @@ def leg_quality(mda, name, qs_2max, runs_2max):
 BATCH = dict(count=256, n_lo=10, n_hi=60, replicas=64, steps=100_000, config=3, plain_sample=4)
 
 
-def leg_batch(mda, opm, steps_timed, warmup):
+def leg_batch(mda, opm, steps_timed, warmup, plain=True):
     """Configuration of many uneven instances: 256 bQAP instances, n uniform on
     {10..60}, 64 replicas x 1e5 steps each, Kronecker updates, one batched
     launch captured as a HIP graph; the plain form of a sample of instances
@@ -454,7 +454,7 @@ def leg_batch(mda, opm, steps_timed, warmup):
     moved_bits = sum(s["moves"] * i.m for s, i in zip(res["stats"], insts))
     ops_roof = alu_roofline(opm, bt, 1, moved_bits, rngb, res["kernel_ms"], kernel="graph of k_persistent launches")
     ns = [i.n for i in insts]
-    sample = sorted({int(np.argmin(ns)), int(np.argmax(ns)), 1, len(insts) // 2})[:w["plain_sample"]]
+    sample = sorted({int(np.argmin(ns)), int(np.argmax(ns)), 1, len(insts) // 2})[:w["plain_sample"]] if plain else []
     pl_bt, pl_s, same = 0, 0.0, True
     for k in sample:
         dt, ok = plain_compare(mda, qs[k], insts[k], w["replicas"], w["steps"], res["runs"][k], res["fronts"][k],
@@ -470,10 +470,10 @@ def leg_batch(mda, opm, steps_timed, warmup):
                       "bit_trials_per_step": bt},
            "roofline": ops_roof,
            "moves": moves,
-           "plain": {"value": pl_bt / pl_s, "unit": "bit-trials/s",
-                     "sample": "instances %s (n = %s), one plain run each" % (sample, [ns[k] for k in sample]),
-                     "identical_results": bool(same)},
-           "vs_plain": round(value / (pl_bt / pl_s), 3)}
+           "plain": ({"value": pl_bt / pl_s, "unit": "bit-trials/s",
+                      "sample": "instances %s (n = %s), one plain run each" % (sample, [ns[k] for k in sample]),
+                      "identical_results": bool(same)} if sample else None),
+           "vs_plain": round(value / (pl_bt / pl_s), 3) if sample else None}
     for r in res["runs"]:
         r.close()
     return out
@@ -705,7 +705,8 @@ def main():
     ap.add_argument("--steps", type=int, default=2, help="timed bench steps")
     ap.add_argument("--warmup", type=int, default=1, help="untimed bench steps")
     ap.add_argument("--workload", default="bqap-n50-x3-kron",
-                    choices=sorted(WORKLOADS) + sorted(GENERIC) + ["bqap-serve-n10-100", "sbda-vs-mda-n20"])
+                    choices=sorted(WORKLOADS) + sorted(GENERIC) + ["bqap-batch-n10-60-x256", "bqap-serve-n10-100",
+                                                                   "sbda-vs-mda-n20"])
     ap.add_argument("--anneal-steps", type=int, default=0, help="override the workload's annealing steps")
     ap.add_argument("--replicas", type=int, default=0, help="override the workload's replicas")
     ap.add_argument("--plain", type=int, default=1, help="plain-form comparison runs (0 = none)")
@@ -742,6 +743,19 @@ def main():
         torch.cuda.set_device(0)
         mda.use_torch_allocator()
         generic_bench(args, mda)
+        return
+    if args.workload == "bqap-batch-n10-60-x256":
+        # the uneven batch alone (its leg of the default line), e.g. for a
+        # kernel trace of the graph's launches
+        torch.cuda.set_device(0)
+        mda.use_torch_allocator()
+        leg = leg_batch(mda, load_opmodel(), args.steps, args.warmup, plain=args.plain > 0)
+        line = {"metric": "bit-trials/s", "value": leg["value"], "unit": "bit-trials/s", "n_gpus": 1,
+                "steps": args.steps, "warmup": args.warmup, "ms_per_step": leg["ms_per_step"],
+                "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "int32",
+                "data": "synthetic"}
+        line.update({k: v for k, v in leg.items() if k not in line})
+        print(json.dumps(line))
         return
     if args.workload == "sbda-vs-mda-n20":
         torch.cuda.set_device(0)
