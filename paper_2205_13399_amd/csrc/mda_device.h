@@ -172,6 +172,22 @@ __device__ __forceinline__ int wave_sum_small(int v)
     return uni(s);
 }
 
+// Wave-wide sum of a per-lane int (every lane active) by DPP moves: sums of
+// 2, 4, 8 and 16 lanes within each row of 16 (row shifts by 1, 2, 4, 8 with
+// zero fill), then lane 15 of rows 0 and 2 into rows 1 and 3, then lane 31
+// into rows 2 and 3; lane 63 ends with the total.  Fields packed into v add
+// independently as long as no field's total overflows into the next.
+__device__ __forceinline__ int wave_sum_dpp(int v)
+{
+    v += __builtin_amdgcn_update_dpp(0, v, 0x111, 0xF, 0xF, false);   // row_shr:1
+    v += __builtin_amdgcn_update_dpp(0, v, 0x112, 0xF, 0xF, false);   // row_shr:2
+    v += __builtin_amdgcn_update_dpp(0, v, 0x114, 0xF, 0xF, false);   // row_shr:4
+    v += __builtin_amdgcn_update_dpp(0, v, 0x118, 0xF, 0xF, false);   // row_shr:8
+    v += __builtin_amdgcn_update_dpp(0, v, 0x142, 0xA, 0xF, false);   // row_bcast:15
+    v += __builtin_amdgcn_update_dpp(0, v, 0x143, 0xC, 0xF, false);   // row_bcast:31
+    return __builtin_amdgcn_readlane(v, 63);
+}
+
 // Fields read on every step, kept in scalar registers.
 struct Hot {
     int n;

@@ -483,22 +483,57 @@ __device__ __forceinline__ int anneal_step(Desc *Dp, const Hot &H, Replica<NS, F
                 acc |= (uint64_t)certain << g;
             }
         }
-        // 3. uniform choice in ascending bit order a = i*n + u
-        const int cnt = wave_sum_small<7>(__popcll(acc));
+        // 3. uniform choice in ascending bit order a = i*n + u.  The wave's
+        // count of accepted bits per group of eight slots (three groups per
+        // word in 10-bit fields, at most 512 each), then per slot of the
+        // chosen group (four per word in 8-bit fields, at most 64 each), then
+        // the lane: the (slot, lane) of the k-th accepted bit, slot-major.
+        constexpr int NG = NS / 8;
+        int gtot[NG];
+#pragma unroll
+        for (int w = 0; w < NG; w += 3) {
+            int packed = 0;
+#pragma unroll
+            for (int q = 0; q < 3 && w + q < NG; ++q)
+                packed |= __popc((uint32_t)(acc >> (8 * (w + q))) & 0xFFu) << (10 * q);
+            const int sum = wave_sum_dpp(packed);
+#pragma unroll
+            for (int q = 0; q < 3 && w + q < NG; ++q) gtot[w + q] = (sum >> (10 * q)) & 0x3FF;
+        }
+        int cnt = 0;
+#pragma unroll
+        for (int g = 0; g < NG; ++g) cnt += gtot[g];
         if (cnt > 0) {
             const U4 o = philox10(0u, t, (uint32_t)r, kTagSel, H.key0, H.key1);
             int k = (int)scale32((uint32_t)uni((int)o.x), (uint32_t)cnt);
-            // (slot, lane) of the k-th accepted bit, slot-major: binary search for
-            // the slot over prefix counts, then the lane within the slot.
-            int lo = 0, hi = NS;
-            while (hi - lo > 1) {
-                const int mid = (lo + hi) >> 1;
-                const int below = wave_sum_small<7>(__popcll(acc & ((1ull << mid) - 1ull)));
-                if (below <= k) lo = mid;
-                else hi = mid;
+            int gs = 0, before = 0, run = 0;
+#pragma unroll
+            for (int g = 0; g < NG; ++g) {
+                const bool here = run <= k && k < run + gtot[g];
+                gs = here ? g : gs;
+                before = here ? run : before;
+                run += gtot[g];
             }
-            const int js = uni(lo);
-            k -= (js == 0) ? 0 : wave_sum_small<7>(__popcll(acc & ((1ull << js) - 1ull)));
+            gs = uni(gs);
+            k -= before;
+            const uint32_t gb = (uint32_t)(acc >> (8 * gs)) & 0xFFu;
+            const int lo4 = wave_sum_dpp((int)((gb & 1u) | ((gb >> 1) & 1u) << 8 | ((gb >> 2) & 1u) << 16 |
+                                               ((gb >> 3) & 1u) << 24));
+            const int hi4 = wave_sum_dpp((int)(((gb >> 4) & 1u) | ((gb >> 5) & 1u) << 8 | ((gb >> 6) & 1u) << 16 |
+                                               ((gb >> 7) & 1u) << 24));
+            int fs = 0;
+            before = 0;
+            run = 0;
+#pragma unroll
+            for (int f = 0; f < 8; ++f) {
+                const int c = ((f < 4 ? lo4 : hi4) >> (8 * (f & 3))) & 0xFF;
+                const bool here = run <= k && k < run + c;
+                fs = here ? f : fs;
+                before = here ? run : before;
+                run += c;
+            }
+            k -= before;
+            const int js = uni(8 * gs + fs);
             const int jl = kth_lane(__ballot((acc >> js) & 1ull), k, lane);
             FT v1 = 0, v2 = 0;
 #pragma unroll
