@@ -160,18 +160,6 @@ __device__ __forceinline__ int wave_sum(int v)
     return uni(v);
 }
 
-// Wave-wide sum of a per-lane integer 0 <= v < 2^B: one ballot per bit, the
-// counts taken on the scalar unit.  Unlike a tree of cross-lane shuffles the
-// B ballots do not wait on one another.
-template <int B>
-__device__ __forceinline__ int wave_sum_small(int v)
-{
-    int s = 0;
-#pragma unroll
-    for (int b = 0; b < B; ++b) s += __popcll(__ballot((v >> b) & 1)) << b;
-    return uni(s);
-}
-
 // Wave-wide sum of a per-lane int (every lane active) by DPP moves: sums of
 // 2, 4, 8 and 16 lanes within each row of 16 (row shifts by 1, 2, 4, 8 with
 // zero fill), then lane 15 of rows 0 and 2 into rows 1 and 3, then lane 31
@@ -185,6 +173,19 @@ __device__ __forceinline__ int wave_sum_dpp(int v)
     v += __builtin_amdgcn_update_dpp(0, v, 0x118, 0xF, 0xF, false);   // row_shr:8
     v += __builtin_amdgcn_update_dpp(0, v, 0x142, 0xA, 0xF, false);   // row_bcast:15
     v += __builtin_amdgcn_update_dpp(0, v, 0x143, 0xC, 0xF, false);   // row_bcast:31
+    return __builtin_amdgcn_readlane(v, 63);
+}
+
+// Wave-wide minimum of a per-lane int (every lane active), by the same DPP
+// moves as wave_sum_dpp; lanes without a source take INT_MAX.
+__device__ __forceinline__ int wave_min_dpp(int v)
+{
+    v = min(v, __builtin_amdgcn_update_dpp(INT_MAX, v, 0x111, 0xF, 0xF, false));   // row_shr:1
+    v = min(v, __builtin_amdgcn_update_dpp(INT_MAX, v, 0x112, 0xF, 0xF, false));   // row_shr:2
+    v = min(v, __builtin_amdgcn_update_dpp(INT_MAX, v, 0x114, 0xF, 0xF, false));   // row_shr:4
+    v = min(v, __builtin_amdgcn_update_dpp(INT_MAX, v, 0x118, 0xF, 0xF, false));   // row_shr:8
+    v = min(v, __builtin_amdgcn_update_dpp(INT_MAX, v, 0x142, 0xA, 0xF, false));   // row_bcast:15
+    v = min(v, __builtin_amdgcn_update_dpp(INT_MAX, v, 0x143, 0xC, 0xF, false));   // row_bcast:31
     return __builtin_amdgcn_readlane(v, 63);
 }
 

@@ -369,7 +369,7 @@ __device__ __forceinline__ int g_step(GDesc *Dp, GRep<K, S> &G, int r, uint32_t 
         // accepted bit from the exclusive prefix of the per-lane counts (one
         // ballot per bit of a count), then the slot within the lane
         const int c = __popcll(acc);
-        const int cnt = wave_sum_small<7>(c);
+        const int cnt = wave_sum_dpp(c);
         if (cnt > 0) {
             const U4 o = philox10(0u, t, (uint32_t)r, kTagSel, Dh.key0, Dh.key1);
             const int k = (int)scale32((uint32_t)uni((int)o.x), (uint32_t)cnt);
@@ -471,9 +471,7 @@ __device__ __forceinline__ int32_t g_least(const GRep<K, S> &G, int nl, int lane
 #pragma unroll
     for (int g = 0; g < S / 8; ++g) mn = min(mn, G.gmin[g]);
     mn = lane < nl ? mn : INT_MAX;
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) mn = min(mn, __shfl_xor(mn, off));
-    return uni(mn);
+    return wave_min_dpp(mn);
 }
 
 // Trace entries (no flip) of the q steps from t of a replica that records its

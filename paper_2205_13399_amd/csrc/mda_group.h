@@ -445,7 +445,7 @@ __device__ __forceinline__ bool g_step(Desc *Dp, const Hot &H, Replica<NS> &S, i
         __syncthreads();   // B2
         int c = 0;
         for (int w2 = 0; w2 < g.G; ++w2) c += __popcll(L.acc[w2][lane]);
-        const int cnt = wave_sum_small<10>(c);
+        const int cnt = wave_sum_dpp(c);
         if (cnt > 0) {
             const U4 o = philox10(0u, t, (uint32_t)r, kTagSel, H.key0, H.key1);
             int k = (int)scale32((uint32_t)uni((int)o.x), (uint32_t)cnt);
@@ -461,7 +461,7 @@ __device__ __forceinline__ bool g_step(Desc *Dp, const Hot &H, Replica<NS> &S, i
                     const uint64_t rm = rr <= 0 ? 0ull : (rr >= 64 ? ~0ull : ((1ull << rr) - 1ull));
                     b += __popcll(L.acc[w2][lane] & rm);
                 }
-                if (wave_sum_small<10>(b) <= k) lo = mid;
+                if (wave_sum_dpp(b) <= k) lo = mid;
                 else hi = mid;
             }
             const int js = uni(lo);
@@ -472,7 +472,7 @@ __device__ __forceinline__ bool g_step(Desc *Dp, const Hot &H, Replica<NS> &S, i
                     const uint64_t rm = rr <= 0 ? 0ull : (rr >= 64 ? ~0ull : ((1ull << rr) - 1ull));
                     b += __popcll(L.acc[w2][lane] & rm);
                 }
-                k -= wave_sum_small<10>(b);
+                k -= wave_sum_dpp(b);
             }
             // location within row js: column-waves in order, lanes ascending
             const int pj = js / NS, sj = js - pj * NS;
@@ -537,9 +537,7 @@ __device__ __forceinline__ int32_t g_least(const Replica<NS> &S, const Geo &g, G
     int32_t mn = INT_MAX;
 #pragma unroll
     for (int s = 0; s < NS; ++s) mn = min(mn, strict ? max(S.e1[s], S.e2[s]) : min(S.e1[s], S.e2[s]));
-    mn = g.u < n ? mn : INT_MAX;
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) mn = min(mn, __shfl_xor(mn, off));
+    mn = wave_min_dpp(g.u < n ? mn : INT_MAX);
     if (g.lane == 0) L.part[g.w][3] = mn;
     __syncthreads();
     int32_t least = INT_MAX;

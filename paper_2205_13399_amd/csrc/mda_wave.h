@@ -373,17 +373,14 @@ __device__ __forceinline__ FT wave_least(const Replica<NS, FT> &S)
     FT mn = Wide<FT>::kMax;
 #pragma unroll
     for (int g = 0; g < NS / 8; ++g) mn = min(mn, S.gmin[g]);
+    if (sizeof(FT) == 4) return (FT)wave_min_dpp((int)mn);
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) {
-        if (sizeof(FT) == 8) {
-            const uint64_t u = (uint64_t)(int64_t)mn;
-            const int lo = __shfl_xor((int)(uint32_t)u, off), hi = __shfl_xor((int)(uint32_t)(u >> 32), off);
-            mn = min(mn, (FT)(int64_t)(((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo));
-        } else {
-            mn = min(mn, (FT)__shfl_xor((int)mn, off));
-        }
+        const uint64_t u = (uint64_t)(int64_t)mn;
+        const int lo = __shfl_xor((int)(uint32_t)u, off), hi = __shfl_xor((int)(uint32_t)(u >> 32), off);
+        mn = min(mn, (FT)(int64_t)(((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo));
     }
-    return sizeof(FT) == 8 ? (FT)uni64((int64_t)mn) : (FT)uni((int)mn);
+    return (FT)uni64((int64_t)mn);
 }
 
 // One annealing step t of replica r whose largest acceptance threshold
