@@ -350,4 +350,66 @@ __device__ __forceinline__ int step_variant(Desc *Dp)
     return run_step_variant(Dp->path, Dp->kform, Dp->accept);
 }
 
+// The differences d_k = dE_k of bit (slot js, lane jl), js uniform: a switch
+// on js (a tree of scalar branches) reaches one readlane of the slot's
+// register per objective, where a select over every slot would take 2 NS
+// vector instructions.
+template <int NS, class FT>
+__device__ __forceinline__ void pick_diffs(const Replica<NS, FT> &S, int js, int jl, FT &d1, FT &d2)
+{
+    switch (js) {
+#define MDA_PICK(I)                                   \
+    case I:                                           \
+        if (I < NS) {                                 \
+            d1 = rlf(S.e1[I < NS ? I : 0], jl);       \
+            d2 = rlf(S.e2[I < NS ? I : 0], jl);       \
+        }                                             \
+        break;
+        MDA_PICK(0) MDA_PICK(1) MDA_PICK(2) MDA_PICK(3) MDA_PICK(4) MDA_PICK(5) MDA_PICK(6) MDA_PICK(7)
+        MDA_PICK(8) MDA_PICK(9) MDA_PICK(10) MDA_PICK(11) MDA_PICK(12) MDA_PICK(13) MDA_PICK(14) MDA_PICK(15)
+        MDA_PICK(16) MDA_PICK(17) MDA_PICK(18) MDA_PICK(19) MDA_PICK(20) MDA_PICK(21) MDA_PICK(22) MDA_PICK(23)
+        MDA_PICK(24) MDA_PICK(25) MDA_PICK(26) MDA_PICK(27) MDA_PICK(28) MDA_PICK(29) MDA_PICK(30) MDA_PICK(31)
+        MDA_PICK(32) MDA_PICK(33) MDA_PICK(34) MDA_PICK(35) MDA_PICK(36) MDA_PICK(37) MDA_PICK(38) MDA_PICK(39)
+        MDA_PICK(40) MDA_PICK(41) MDA_PICK(42) MDA_PICK(43) MDA_PICK(44) MDA_PICK(45) MDA_PICK(46) MDA_PICK(47)
+        MDA_PICK(48) MDA_PICK(49) MDA_PICK(50) MDA_PICK(51) MDA_PICK(52) MDA_PICK(53) MDA_PICK(54) MDA_PICK(55)
+        MDA_PICK(56) MDA_PICK(57) MDA_PICK(58) MDA_PICK(59) MDA_PICK(60) MDA_PICK(61) MDA_PICK(62) MDA_PICK(63)
+#undef MDA_PICK
+    default: break;
+    }
+}
+
+// Slot js (uniform) of every lane takes one more term of the flip: c_k with
+// the lane's sign for that slot ((c ^ m) + b is c or -c in wrapping
+// arithmetic).  A switch on js (a tree of scalar branches) reaches the slot's
+// registers, where a select in every slot's update would take 2 NS vector
+// instructions.
+template <int NS, class FT>
+__device__ __forceinline__ void add_to_slot(Replica<NS, FT> &S, int js, uint64_t xmx, typename Wide<FT>::U c1,
+                                            typename Wide<FT>::U c2)
+{
+    using UT = typename Wide<FT>::U;
+    switch (js) {
+#define MDA_FIX(I)                                                                 \
+    case I:                                                                        \
+        if (I < NS) {                                                              \
+            constexpr int i = I < NS ? I : 0;                                      \
+            const UT b = (UT)((xmx >> i) & 1ull);                                  \
+            const UT m = (UT)0 - b;                                                \
+            S.e1[i] = (FT)((UT)S.e1[i] + (c1 ^ m) + b);                            \
+            S.e2[i] = (FT)((UT)S.e2[i] + (c2 ^ m) + b);                            \
+        }                                                                          \
+        break;
+        MDA_FIX(0) MDA_FIX(1) MDA_FIX(2) MDA_FIX(3) MDA_FIX(4) MDA_FIX(5) MDA_FIX(6) MDA_FIX(7)
+        MDA_FIX(8) MDA_FIX(9) MDA_FIX(10) MDA_FIX(11) MDA_FIX(12) MDA_FIX(13) MDA_FIX(14) MDA_FIX(15)
+        MDA_FIX(16) MDA_FIX(17) MDA_FIX(18) MDA_FIX(19) MDA_FIX(20) MDA_FIX(21) MDA_FIX(22) MDA_FIX(23)
+        MDA_FIX(24) MDA_FIX(25) MDA_FIX(26) MDA_FIX(27) MDA_FIX(28) MDA_FIX(29) MDA_FIX(30) MDA_FIX(31)
+        MDA_FIX(32) MDA_FIX(33) MDA_FIX(34) MDA_FIX(35) MDA_FIX(36) MDA_FIX(37) MDA_FIX(38) MDA_FIX(39)
+        MDA_FIX(40) MDA_FIX(41) MDA_FIX(42) MDA_FIX(43) MDA_FIX(44) MDA_FIX(45) MDA_FIX(46) MDA_FIX(47)
+        MDA_FIX(48) MDA_FIX(49) MDA_FIX(50) MDA_FIX(51) MDA_FIX(52) MDA_FIX(53) MDA_FIX(54) MDA_FIX(55)
+        MDA_FIX(56) MDA_FIX(57) MDA_FIX(58) MDA_FIX(59) MDA_FIX(60) MDA_FIX(61) MDA_FIX(62) MDA_FIX(63)
+#undef MDA_FIX
+    default: break;
+    }
+}
+
 }  // namespace mda

@@ -213,11 +213,12 @@ __device__ __forceinline__ void g_flip(Desc *Dp, Replica<NS> &S, const Geo &g, i
             const uint32_t t2 = ok ? (uint32_t)ro(D.P2)[row + (size_t)i * D.pld + u] : 0u;
             const uint32_t b = (uint32_t)(xmx >> s) & 1u;
             const uint32_t m = 0u - b;
-            const uint32_t u1 = t1 + ((s == jsl) ? c1 : 0u);
-            const uint32_t u2 = t2 + ((s == jsl) ? c2 : 0u);
-            S.e1[s] = (int32_t)((uint32_t)S.e1[s] + (u1 ^ m) + b);
-            S.e2[s] = (int32_t)((uint32_t)S.e2[s] + (u2 ^ m) + b);
+            S.e1[s] = (int32_t)((uint32_t)S.e1[s] + (t1 ^ m) + b);
+            S.e2[s] = (int32_t)((uint32_t)S.e2[s] + (t2 ^ m) + b);
         }
+        // bit j's own entry, in the wave that holds row js (jsl outside
+        // [0, NS) elsewhere: no slot)
+        add_to_slot<NS, int32_t>(S, uni(jsl), xmx, c1, c2);
     } else {
         const int fi = g.i0 + lane;
         const bool fok = fi < n;
@@ -240,8 +241,8 @@ __device__ __forceinline__ void g_flip(Desc *Dp, Replica<NS> &S, const Geo &g, i
         const uint32_t r2 = atj ? (uint32_t)(-2 * d2) - own2 : (live ? ta2 : 0u);
 #pragma unroll
         for (int s = 0; s < NS; ++s) {
-            uint32_t t1 = (uint32_t)__mul24(rl(fa1, s), dv) + ((s == jsl) ? r1 : q1);
-            uint32_t t2 = (uint32_t)__mul24(rl(fa2, s), dv) + ((s == jsl) ? r2 : q2);
+            uint32_t t1 = (uint32_t)__mul24(rl(fa1, s), dv) + q1;
+            uint32_t t2 = (uint32_t)__mul24(rl(fa2, s), dv) + q2;
             if (PV == kPvKronGen) {
                 t1 += (uint32_t)__mul24(rl(fb1, s), dw);
                 t2 += (uint32_t)__mul24(rl(fb2, s), dw);
@@ -251,6 +252,8 @@ __device__ __forceinline__ void g_flip(Desc *Dp, Replica<NS> &S, const Geo &g, i
             S.e1[s] = (int32_t)((uint32_t)S.e1[s] + (t1 ^ m) + b);
             S.e2[s] = (int32_t)((uint32_t)S.e2[s] + (t2 ^ m) + b);
         }
+        // row js takes r_k in place of q_k (in the wave that holds it)
+        add_to_slot<NS, int32_t>(S, uni(jsl), xmx, r1 - q1, r2 - q2);
     }
     S.xm ^= (atj && rowhere) ? (1ull << (jsl & 63)) : 0ull;
 }
@@ -490,14 +493,9 @@ __device__ __forceinline__ bool g_step(Desc *Dp, const Hot &H, Replica<NS> &S, i
             jl = uni(jl < 0 ? 0 : (jl >= n ? n - 1 : jl));
             const int owner = pj * g.WC + (jl >> 6);
             if (g.w == owner) {
-                int32_t v1 = 0, v2 = 0;
-#pragma unroll
-                for (int s = 0; s < NS; ++s) {
-                    v1 = (s == sj) ? S.e1[s] : v1;
-                    v2 = (s == sj) ? S.e2[s] : v2;
-                }
                 const int jll = jl & 63;
-                const int32_t d1 = rl(v1, jll), d2 = rl(v2, jll);
+                int32_t d1 = 0, d2 = 0;
+                pick_diffs<NS, int32_t>(S, uni(sj), jll, d1, d2);
                 const uint32_t xj = (uint32_t)((rl64(S.xm, jll) >> sj) & 1ull);
                 if (lane == 0) {
                     L.pick[0] = d1;
