@@ -34,8 +34,17 @@ namespace mda {
 // afterwards (add_to_slot).
 // Column entries fit int32 (build-time bound); the differences are updated in
 // the unsigned counterpart UT of their type FT, where the additions wrap.
+// LDS words of one wave of the persistent kernel: the 4096-entry -ln (or
+// threshold) table, then kStageWords of staging for the flipped facility's
+// flow rows (four rows of 64 lanes).
+constexpr int kStageWords = 256;
+constexpr int kWaveLds = 4096 + kStageWords;
+
+typedef int32_t v4i32 __attribute__((ext_vector_type(4)));
+
 template <int NS, int PV, class FT>
-__device__ __forceinline__ void flip(Desc *Dp, int n_, Replica<NS, FT> &S, int js, int jl, FT d1, FT d2, int lane_)
+__device__ __forceinline__ void flip(Desc *Dp, int n_, Replica<NS, FT> &S, int js, int jl, FT d1, FT d2, int lane_,
+                                     MDA_LDS int32_t *stage)
 {
     using UT = typename Wide<FT>::U;
     const int n = opaque(n_);
@@ -95,6 +104,16 @@ __device__ __forceinline__ void flip(Desc *Dp, int n_, Replica<NS, FT> &S, int j
         const int32_t fa2 = ro(D.KA2)[js * kLD + lane];
         const int32_t fb1 = (PV == kPvKronGen) ? ro(D.KB1)[js * kLD + lane] : 0;
         const int32_t fb2 = (PV == kPvKronGen) ? ro(D.KB2)[js * kLD + lane] : 0;
+        // The rows (one entry per lane) go through the wave's staging words
+        // in LDS and come back as uniform 16-byte reads, four slots each, in
+        // place of one readlane per slot and objective.
+        stage[lane] = fa1;
+        stage[64 + lane] = fa2;
+        if (PV == kPvKronGen) {
+            stage[128 + lane] = fb1;
+            stage[192 + lane] = fb2;
+        }
+        const MDA_LDS v4i32 *s4 = (const MDA_LDS v4i32 *)stage;
         const UT ta1 = (UT)(FT)D.two_alpha1, ta2 = (UT)(FT)D.two_alpha2;
         const bool atj = lane == jl;
         const UT q1 = atj ? ta1 : (UT)0, q2 = atj ? ta2 : (UT)0;
@@ -106,18 +125,28 @@ __device__ __forceinline__ void flip(Desc *Dp, int n_, Replica<NS, FT> &S, int j
         const UT r1 = atj ? (UT)(-2 * d1) - own1 : (live ? ta1 : (UT)0);
         const UT r2 = atj ? (UT)(-2 * d2) - own2 : (live ? ta2 : (UT)0);
 #pragma unroll
-        for (int i = 0; i < NS; ++i) {
-            // wrapping arithmetic: each product and the column entry fit int32
-            UT t1 = (UT)(FT)__mul24(rl(fa1, i), dv) + q1;
-            UT t2 = (UT)(FT)__mul24(rl(fa2, i), dv) + q2;
+        for (int g = 0; g < NS; g += 4) {
+            const v4i32 a1 = s4[g / 4], a2 = s4[16 + g / 4];
+            v4i32 b1 = a1, b2 = a2;
             if (PV == kPvKronGen) {
-                t1 += (UT)(FT)__mul24(rl(fb1, i), dw);
-                t2 += (UT)(FT)__mul24(rl(fb2, i), dw);
+                b1 = s4[32 + g / 4];
+                b2 = s4[48 + g / 4];
             }
-            const UT b = (UT)((xmx >> i) & 1ull);
-            const UT m = (UT)0 - b;
-            S.e1[i] = (FT)((UT)S.e1[i] + (t1 ^ m) + b);
-            S.e2[i] = (FT)((UT)S.e2[i] + (t2 ^ m) + b);
+#pragma unroll
+            for (int f = 0; f < 4; ++f) {
+                const int i = g + f;
+                // wrapping arithmetic: each product and the column entry fit int32
+                UT t1 = (UT)(FT)__mul24(a1[f], dv) + q1;
+                UT t2 = (UT)(FT)__mul24(a2[f], dv) + q2;
+                if (PV == kPvKronGen) {
+                    t1 += (UT)(FT)__mul24(b1[f], dw);
+                    t2 += (UT)(FT)__mul24(b2[f], dw);
+                }
+                const UT b = (UT)((xmx >> i) & 1ull);
+                const UT m = (UT)0 - b;
+                S.e1[i] = (FT)((UT)S.e1[i] + (t1 ^ m) + b);
+                S.e2[i] = (FT)((UT)S.e2[i] + (t2 ^ m) + b);
+            }
         }
         // slot js takes r_k in place of q_k
         add_to_slot<NS, FT>(S, js, xmx, r1 - q1, r2 - q2);
@@ -394,7 +423,7 @@ __device__ __forceinline__ FT wave_least(const Replica<NS, FT> &S)
 // saturated at 2^32 - 1 (above every statistic, so the decisions are the same).
 template <int NS, int PV, int AM, class FT, class LP, bool THR = false>
 __device__ __forceinline__ int anneal_step(Desc *Dp, const Hot &H, Replica<NS, FT> &S, int r, uint32_t t, int lane_,
-                                           LP lnt, int64_t thrmax)
+                                           LP lnt, int64_t thrmax, MDA_LDS int32_t *stage)
 {
     constexpr bool strict = AM == kAmStrict;
     using UT = typename Wide<FT>::U;
@@ -539,7 +568,7 @@ __device__ __forceinline__ int anneal_step(Desc *Dp, const Hot &H, Replica<NS, F
             FT d1 = 0, d2 = 0;
             pick_diffs<NS, FT>(S, js, jl, d1, d2);
             // 4. move, 5. archive
-            flip<NS, PV>(Dp, n, S, js, jl, d1, d2, lane);
+            flip<NS, PV>(Dp, n, S, js, jl, d1, d2, lane, stage);
             group_minima<NS, AM>(S);
             S.moves++;
             archive_update<NS, FT>(Dp, n, S, r, t, lane, H.key0, H.key1);
@@ -649,7 +678,7 @@ __device__ __forceinline__ void run_replica(Desc *Dp, int r, int lane, MDA_LDS i
         if (skip && least > step_reach<FT>(S.Eoff, thr)) {
             S.Eoff += H.beta;
             quiet_trace(Dp, H, r, t, 1u, lane);
-        } else if (anneal_step<NS, PV, AM>(Dp, H, S, r, t, lane, (const MDA_LDS int32_t *)tab, thr) >= 0) {
+        } else if (anneal_step<NS, PV, AM>(Dp, H, S, r, t, lane, (const MDA_LDS int32_t *)tab, thr, tab + 4096) >= 0) {
             least = wave_least(S);
         }
         thr = thr_next;
@@ -673,7 +702,8 @@ __device__ __forceinline__ void run_replica(Desc *Dp, int r, int lane, MDA_LDS i
                 }
             }
             if (anneal_step<NS, PV, AM, FT, const MDA_LDS int32_t *, true>(Dp, H, S, r, t, lane,
-                                                                         (const MDA_LDS int32_t *)tab, thr) >= 0)
+                                                                         (const MDA_LDS int32_t *)tab, thr,
+                                                                         tab + 4096) >= 0)
                 least = wave_least(S);
             ++t;
         }
@@ -707,10 +737,10 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(OCC)))
                                                     const int32_t *lnt_, unsigned int *next)
 {
     using FT = typename std::conditional<F64 != 0, int64_t, int32_t>::type;
-    // dynamic LDS: 4096 words per wave, read at random by the exact
-    // acceptance test (see run_replica)
+    // dynamic LDS: kWaveLds words per wave, the table read at random by the
+    // exact acceptance test (see run_replica), then the flip's staging words
     extern __shared__ int32_t wave_tab[];
-    MDA_LDS int32_t *tab = (MDA_LDS int32_t *)(wave_tab + (threadIdx.x >> 6) * 4096);
+    MDA_LDS int32_t *tab = (MDA_LDS int32_t *)(wave_tab + (threadIdx.x >> 6) * kWaveLds);
     const MDA_GLOBAL int32_t *lnt = (const MDA_GLOBAL int32_t *)lnt_;
     const int lane = __lane_id();
     const int wpb = (int)(blockDim.x >> 6);
@@ -798,7 +828,10 @@ __device__ __forceinline__ void plain_step_one(Desc *Dp, int r, uint32_t t, int 
     plain_load<NS>(Dp, S, r, lane);
     group_minima<NS, AM>(S);
     const Hot H = load_hot(Dp);
-    anneal_step<NS, PV, AM>(Dp, H, S, r, t, lane, lnt, H.thrmax[table_index(t, H.ntab)]);
+    // staging words of the flip: 256 per wave of the block (at most four)
+    __shared__ __align__(16) int32_t plain_stage[4 * kStageWords];
+    anneal_step<NS, PV, AM>(Dp, H, S, r, t, lane, lnt, H.thrmax[table_index(t, H.ntab)],
+                            (MDA_LDS int32_t *)(plain_stage + (threadIdx.x >> 6) * kStageWords));
     plain_store<NS>(Dp, S, r, lane);
 }
 

@@ -9,11 +9,12 @@ namespace mda {
 #define MDA_CAT2(a, b) a##b
 #define MDA_CAT(a, b) MDA_CAT2(a, b)
 
-// Dynamic LDS of the persistent kernel: 4096 words per wave, 64 KB for the
-// largest block (four waves).
+// Dynamic LDS of the persistent kernel: kWaveLds words per wave (the 4096-word
+// table and the flip's staging words), 68 KB for the largest block (four
+// waves).
 inline size_t persistent_lds(int block)
 {
-    return (size_t)(block / 64) * 4096 * sizeof(int32_t);
+    return (size_t)(block / 64) * kWaveLds * sizeof(int32_t);
 }
 
 // Kernel of step variant sv (the six values of MDA_STEP_VARIANTS), or
