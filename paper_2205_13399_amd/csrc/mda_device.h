@@ -160,6 +160,9 @@ __device__ __forceinline__ int wave_sum(int v)
     return uni(v);
 }
 
+// Four int32 (a 16-byte LDS read of uniform data, e.g. staged flow rows).
+typedef int32_t v4i32 __attribute__((ext_vector_type(4)));
+
 // Wave-wide sum of a per-lane int (every lane active) by DPP moves: sums of
 // 2, 4, 8 and 16 lanes within each row of 16 (row shifts by 1, 2, 4, 8 with
 // zero fill), then lane 15 of rows 0 and 2 into rows 1 and 3, then lane 31

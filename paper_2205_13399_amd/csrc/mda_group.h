@@ -31,6 +31,9 @@ struct GroupLds {
     uint64_t acc[kMaxGroupWaves][64];
     uint64_t xs[kMaxGroupWaves][64];
     int64_t part[kMaxGroupWaves][4];
+    // per wave: the flipped facility's flow rows over this wave's slots
+    // (four rows of 64), read back by the flip as uniform 16-byte loads
+    int32_t stage[kMaxGroupWaves][256];
     int32_t pick[4];
 };
 
@@ -186,7 +189,7 @@ __device__ __forceinline__ void g_restart(Desc *Dp, Replica<NS> &S, int r, int p
 // and value xj, in every wave's block.
 template <int NS, int PV>
 __device__ __forceinline__ void g_flip(Desc *Dp, Replica<NS> &S, const Geo &g, int js, int jl, int32_t d1,
-                                       int32_t d2, uint32_t xj)
+                                       int32_t d2, uint32_t xj, GroupLds &L)
 {
     Desc &D = *cold(Dp);
     const int n = opaque(D.n);
@@ -228,6 +231,15 @@ __device__ __forceinline__ void g_flip(Desc *Dp, Replica<NS> &S, const Geo &g, i
         const int32_t fa2 = fok ? ro(D.KA2)[js * ldk + fi] : 0;
         const int32_t fb1 = (PV == kPvKronGen && fok) ? ro(D.KB1)[js * ldk + fi] : 0;
         const int32_t fb2 = (PV == kPvKronGen && fok) ? ro(D.KB2)[js * ldk + fi] : 0;
+        // the wave's own staging words (no other wave reads them)
+        int32_t *stage = L.stage[g.w];
+        stage[lane] = fa1;
+        stage[64 + lane] = fa2;
+        if (PV == kPvKronGen) {
+            stage[128 + lane] = fb1;
+            stage[192 + lane] = fb2;
+        }
+        const MDA_LDS v4i32 *s4 = (const MDA_LDS v4i32 *)(MDA_LDS int32_t *)stage;
         const uint32_t ta1 = (uint32_t)D.two_alpha1, ta2 = (uint32_t)D.two_alpha2;
         const uint32_t q1 = atj ? ta1 : 0u, q2 = atj ? ta2 : 0u;
         // own column entry of bit j (only used in the wave holding it)
@@ -240,17 +252,27 @@ __device__ __forceinline__ void g_flip(Desc *Dp, Replica<NS> &S, const Geo &g, i
         const uint32_t r1 = atj ? (uint32_t)(-2 * d1) - own1 : (live ? ta1 : 0u);
         const uint32_t r2 = atj ? (uint32_t)(-2 * d2) - own2 : (live ? ta2 : 0u);
 #pragma unroll
-        for (int s = 0; s < NS; ++s) {
-            uint32_t t1 = (uint32_t)__mul24(rl(fa1, s), dv) + q1;
-            uint32_t t2 = (uint32_t)__mul24(rl(fa2, s), dv) + q2;
+        for (int g4 = 0; g4 < NS; g4 += 4) {
+            const v4i32 a1 = s4[g4 / 4], a2 = s4[16 + g4 / 4];
+            v4i32 b1 = a1, b2 = a2;
             if (PV == kPvKronGen) {
-                t1 += (uint32_t)__mul24(rl(fb1, s), dw);
-                t2 += (uint32_t)__mul24(rl(fb2, s), dw);
+                b1 = s4[32 + g4 / 4];
+                b2 = s4[48 + g4 / 4];
             }
-            const uint32_t b = (uint32_t)(xmx >> s) & 1u;
-            const uint32_t m = 0u - b;
-            S.e1[s] = (int32_t)((uint32_t)S.e1[s] + (t1 ^ m) + b);
-            S.e2[s] = (int32_t)((uint32_t)S.e2[s] + (t2 ^ m) + b);
+#pragma unroll
+            for (int f = 0; f < 4; ++f) {
+                const int s = g4 + f;
+                uint32_t t1 = (uint32_t)__mul24(a1[f], dv) + q1;
+                uint32_t t2 = (uint32_t)__mul24(a2[f], dv) + q2;
+                if (PV == kPvKronGen) {
+                    t1 += (uint32_t)__mul24(b1[f], dw);
+                    t2 += (uint32_t)__mul24(b2[f], dw);
+                }
+                const uint32_t b = (uint32_t)(xmx >> s) & 1u;
+                const uint32_t m = 0u - b;
+                S.e1[s] = (int32_t)((uint32_t)S.e1[s] + (t1 ^ m) + b);
+                S.e2[s] = (int32_t)((uint32_t)S.e2[s] + (t2 ^ m) + b);
+            }
         }
         // row js takes r_k in place of q_k (in the wave that holds it)
         add_to_slot<NS, int32_t>(S, uni(jsl), xmx, r1 - q1, r2 - q2);
@@ -506,7 +528,7 @@ __device__ __forceinline__ bool g_step(Desc *Dp, const Hot &H, Replica<NS> &S, i
             __syncthreads();   // B3
             const int32_t d1 = uni(L.pick[0]), d2 = uni(L.pick[1]);
             const uint32_t xj = (uint32_t)uni(L.pick[2]);
-            g_flip<NS, PV>(Dp, S, g, js, jl, d1, d2, xj);
+            g_flip<NS, PV>(Dp, S, g, js, jl, d1, d2, xj, L);
             S.moves++;
             g_archive<NS>(Dp, S, r, t, g, H.key0, H.key1);
             moved = true;

@@ -40,8 +40,6 @@ namespace mda {
 constexpr int kStageWords = 256;
 constexpr int kWaveLds = 4096 + kStageWords;
 
-typedef int32_t v4i32 __attribute__((ext_vector_type(4)));
-
 template <int NS, int PV, class FT>
 __device__ __forceinline__ void flip(Desc *Dp, int n_, Replica<NS, FT> &S, int js, int jl, FT d1, FT d2, int lane_,
                                      MDA_LDS int32_t *stage)
