@@ -59,6 +59,8 @@ __device__ __forceinline__ void flip(Desc *Dp, int n_, Replica<NS, FT> &S, int j
         const int j = js * n + jl;
         const UT c1 = (lane == jl) ? (UT)(-2 * d1) - (UT)(FT)ro(D.diag1)[js * kLD + jl] : (UT)0;
         const UT c2 = (lane == jl) ? (UT)(-2 * d2) - (UT)(FT)ro(D.diag2)[js * kLD + jl] : (UT)0;
+        // bit j's own entry (added first: the additions commute)
+        add_to_slot<NS, FT>(S, js, xmx, c1, c2);
         // rows of n x n entries: lanes beyond n read a clamped (in-bounds)
         // index and take 0
         const MDA_CONST int32_t *r1 = ro(D.P1) + (size_t)j * (size_t)(n * n);
@@ -88,7 +90,6 @@ __device__ __forceinline__ void flip(Desc *Dp, int n_, Replica<NS, FT> &S, int j
                 S.e2[i] = (FT)((UT)S.e2[i] + (u2 ^ m) + b);
             }
         }
-        add_to_slot<NS, FT>(S, js, xmx, c1, c2);
     } else {
         // P_k[(i,u)][(js,jl)] = KA_k[js][i] DA[jl][u] (+ KB_k[js][i] DB[jl][u])
         //                       + 2 alpha_k [(i == js) != (u == jl)]
@@ -122,6 +123,9 @@ __device__ __forceinline__ void flip(Desc *Dp, int n_, Replica<NS, FT> &S, int j
         }
         const UT r1 = atj ? (UT)(-2 * d1) - own1 : (live ? ta1 : (UT)0);
         const UT r2 = atj ? (UT)(-2 * d2) - own2 : (live ? ta2 : (UT)0);
+        // slot js takes r_k in place of q_k (added first: the additions
+        // commute, and fewer values are live here than after the loop)
+        add_to_slot<NS, FT>(S, js, xmx, r1 - q1, r2 - q2);
 #pragma unroll
         for (int g = 0; g < NS; g += 4) {
             const v4i32 a1 = s4[g / 4], a2 = s4[16 + g / 4];
@@ -146,8 +150,6 @@ __device__ __forceinline__ void flip(Desc *Dp, int n_, Replica<NS, FT> &S, int j
                 S.e2[i] = (FT)((UT)S.e2[i] + (t2 ^ m) + b);
             }
         }
-        // slot js takes r_k in place of q_k
-        add_to_slot<NS, FT>(S, js, xmx, r1 - q1, r2 - q2);
     }
     S.xm ^= (lane == jl) ? (1ull << js) : 0ull;
 }
