@@ -28,7 +28,7 @@ hipError_t launch_group(int ns, int occ, int wr, int wc, const RunDesc *runs, co
 hipError_t group_occupancy(int ns, int occ, int wr, int wc, int *blocks_per_cu);
 hipError_t launch_persistent(int ns, int occ, int f64, int sv, const RunDesc *runs, const WorkItem *work, int nwork,
                              const int32_t *lnt, unsigned int *next, int grid, int block, hipStream_t stream);
-hipError_t launch_plain(int ns, const RunDesc *run, int R, uint32_t steps, const int32_t *lnt, int block,
+hipError_t launch_plain(int ns, int sv, const RunDesc *run, int R, uint32_t steps, const int32_t *lnt, int block,
                         hipStream_t stream);
 hipError_t launch_nondominated(const RunDesc *runs, const WorkItem *work, int nwork, hipStream_t stream);
 hipError_t launch_best(const RunDesc *run, int R, int64_t *e1, int32_t *slot, hipStream_t stream);
@@ -924,7 +924,8 @@ int enqueue_anneal(const std::vector<Group> &groups, const RunDesc &first, bool 
         return fail(MDA_EINVAL, "%zu register tiles in one launch (at most %d)", groups.size(), kMaxGroups);
     int gi = 0;
     if (plain) {
-        HIP_TRY(launch_plain(groups[0].ns, ddesc, first.R, first.steps, dlnt, block, stream));
+        HIP_TRY(launch_plain(groups[0].ns, run_step_variant(first.path, first.kform, first.accept), ddesc, first.R,
+                             first.steps, dlnt, block, stream));
         return MDA_OK;
     }
     // Several groups: group k goes to stream k mod (1 + side streams), so

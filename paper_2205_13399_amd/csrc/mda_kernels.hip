@@ -132,8 +132,8 @@ int ns_for(int n)
                                        int nwork, const int32_t *lnt, unsigned int *next, int grid,        \
                                        int block, hipStream_t stream);                                     \
     hipError_t persistent_occupancy_ns##N(int occ, int sv, int block, int *blocks_per_cu);                \
-    hipError_t launch_plain_ns##N(const RunDesc *run, int R, uint32_t steps, const int32_t *lnt, int block, \
-                                  hipStream_t stream);                                                     \
+    hipError_t launch_plain_ns##N(int sv, const RunDesc *run, int R, uint32_t steps, const int32_t *lnt,    \
+                                  int block, hipStream_t stream);                                          \
     hipError_t launch_persistent64_ns##N(int sv, const RunDesc *runs, const WorkItem *work, int nwork,     \
                                          const int32_t *lnt, unsigned int *next, int grid, int block,      \
                                          hipStream_t stream);                                              \
@@ -186,13 +186,13 @@ hipError_t persistent_occupancy(int ns, int occ, int f64, int sv, int block, int
     }
 }
 
-hipError_t launch_plain(int ns, const RunDesc *run, int R, uint32_t steps, const int32_t *lnt, int block,
+hipError_t launch_plain(int ns, int sv, const RunDesc *run, int R, uint32_t steps, const int32_t *lnt, int block,
                         hipStream_t stream)
 {
     switch (ns) {
 #define X(N) \
     case N:  \
-        return launch_plain_ns##N(run, R, steps, lnt, block, stream);
+        return launch_plain_ns##N(sv, run, R, steps, lnt, block, stream);
         MDA_NS_LIST(X)
 #undef X
     default:

@@ -835,23 +835,17 @@ __device__ __forceinline__ void plain_step_one(Desc *Dp, int r, uint32_t t, int 
     plain_store<NS>(Dp, S, r, lane);
 }
 
-template <int NS>
+// One annealing step of every replica of the run, built per step variant SV
+// (the run's own; the host launches the matching build).
+template <int NS, int SV>
 __global__ void __launch_bounds__(256) k_plain_step(const RunDesc *run, uint32_t t, const int32_t *lnt_)
 {
     const int lane = __lane_id();
     const int r = uni((int)((blockIdx.x * blockDim.x + threadIdx.x) >> 6));
     Desc *Dp = ro(run);
-    if (r >= Dp->R) return;
+    if (r >= Dp->R || step_variant(Dp) != SV) return;
     const MDA_GLOBAL int32_t *lnt = (const MDA_GLOBAL int32_t *)lnt_;
-    switch (step_variant(Dp)) {
-#define X(PV, AM)                                           \
-    case PV * 2 + AM:                                       \
-        plain_step_one<NS, PV, AM>(Dp, r, t, lane, lnt); \
-        break;
-        MDA_STEP_VARIANTS(X)
-#undef X
-    default: break;
-    }
+    plain_step_one<NS, SV / 2, SV % 2>(Dp, r, t, lane, lnt);
 }
 
 template <int NS>

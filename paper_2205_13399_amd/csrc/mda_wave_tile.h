@@ -78,14 +78,32 @@ hipError_t MDA_CAT(persistent_occupancy_ns, MDA_TILE)(int occ, int sv, int block
     return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k, block, persistent_lds(block));
 }
 
-hipError_t MDA_CAT(launch_plain_ns, MDA_TILE)(const RunDesc *run, int R, uint32_t steps, const int32_t *lnt, int block,
-                                             hipStream_t stream)
+// Plain step kernel of step variant sv, or nullptr for a value out of range.
+static const void *plain_step_kernel(int sv)
 {
+    switch (sv) {
+#define X(PV, AM) \
+    case PV * 2 + AM: return reinterpret_cast<const void *>(&k_plain_step<MDA_TILE, PV * 2 + AM>);
+        MDA_STEP_VARIANTS(X)
+#undef X
+    default: return nullptr;
+    }
+}
+
+hipError_t MDA_CAT(launch_plain_ns, MDA_TILE)(int sv, const RunDesc *run, int R, uint32_t steps, const int32_t *lnt,
+                                             int block, hipStream_t stream)
+{
+    const void *k = plain_step_kernel(sv);
+    if (!k) return hipErrorInvalidValue;
     const int wpb = block / 64;
     const int grid = (R + wpb - 1) / wpb;
     hipLaunchKernelGGL(k_plain_init<MDA_TILE>, dim3(grid), dim3(block), 0, stream, run);
-    for (uint32_t t = 1; t <= steps; ++t)
-        hipLaunchKernelGGL(k_plain_step<MDA_TILE>, dim3(grid), dim3(block), 0, stream, run, t, lnt);
+    for (uint32_t t = 1; t <= steps; ++t) {
+        uint32_t tt = t;
+        void *args[] = {(void *)&run, (void *)&tt, (void *)&lnt};
+        const hipError_t e = hipLaunchKernel(k, dim3(grid), dim3(block), args, 0, stream);
+        if (e != hipSuccess) return e;
+    }
     hipLaunchKernelGGL(k_plain_final<MDA_TILE>, dim3(grid), dim3(block), 0, stream, run);
     return hipGetLastError();
 }
