@@ -171,7 +171,7 @@ typedef struct {
                                  NULL: the geometric schedule */
     int32_t occupancy;        /* one-wave form, int32 differences: 0 = automatic (the build holding two waves
                                  per SIMD when a launch has more replicas than one wave per SIMD holds at
-                                 once); 1 or 2: that build (2 exists from 40 register slots, i.e. n > 32;
+                                 once); 1 or 2: that build (2 exists from 32 register slots, i.e. n > 24;
                                  smaller tiles take 1).  In a batch the first block's value applies.
                                  Results do not depend on it */
 } mda_params;

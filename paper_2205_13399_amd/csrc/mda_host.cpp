@@ -1660,7 +1660,7 @@ extern "C" int mda_autotune(const mda_qubo *q, const mda_params *pin, int64_t pr
     }
     std::memset(out, 0, sizeof *out);
     // candidates: one wave per replica (n <= 64) with 1, 2, 4 waves per block,
-    // each with the one- and (from 40 slots, int32 differences) the
+    // each with the one- and (from 32 slots, int32 differences) the
     // two-waves-per-SIMD build; workgroups of 2 and 4 waves where a layout
     // exists (their build by the host rule)
     struct Cand {
@@ -1670,7 +1670,7 @@ extern "C" int mda_autotune(const mda_qubo *q, const mda_params *pin, int64_t pr
     if (n <= kMaxWaveN)
         for (int wpb : {1, 2, 4}) {
             cand.push_back({1, wpb, 1});
-            if (!q->f64 && ns_for(n) >= 40) cand.push_back({1, wpb, 2});
+            if (!q->f64 && ns_for(n) >= 32) cand.push_back({1, wpb, 2});
         }
     const int wc = (n + 63) / 64;
     for (int g : {2, 4}) {

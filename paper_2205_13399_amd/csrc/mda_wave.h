@@ -725,7 +725,7 @@ __device__ __forceinline__ void run_replica(Desc *Dp, int r, int lane, MDA_LDS i
 // rule; the host groups the work list by it), so the kernel holds one variant
 // of the step: a build with all six behind a switch needs twice the scratch of
 // the two-wave budget and is 4.5 % slower on the n = 50 benchmark launch.
-// From 40 slots up the kernel holds one wave per SIMD (OCC = 1); the OCC = 2
+// From 32 slots up the kernel holds one wave per SIMD (OCC = 1); the OCC = 2
 // build keeps part of the cold-path state (initial fields, restarts, archive
 // scans) in scratch so that a second wave per SIMD hides the latency of the
 // first.  The host takes it when a launch has more replicas than one wave per

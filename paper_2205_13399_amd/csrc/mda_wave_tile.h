@@ -56,8 +56,8 @@ hipError_t MDA_CAT(persistent64_occupancy_ns, MDA_TILE)(int sv, int block, int *
     return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k, block, persistent_lds(block));
 }
 #else
-// From 40 slots up a second build holds two waves per SIMD (see k_persistent).
-constexpr int kTileOcc2 = MDA_TILE >= 40 ? 2 : 1;
+// From 32 slots up a second build holds two waves per SIMD (see k_persistent).
+constexpr int kTileOcc2 = MDA_TILE >= 32 ? 2 : 1;
 
 static const void *persistent_kernel_occ(int occ, int sv)
 {

@@ -24,8 +24,8 @@ def test_autotune_picks_fastest_and_keeps_results(mda):
     p = mda.make_params(256, 3000, 7)
     t = mda.autotune(q, p, probe_steps=500)
     shapes = {(w, b, o) for w, b, o, _ in t["candidates"]}
-    # n = 30: 32 slots, one build per SIMD only
-    assert {(1, 1, 1), (1, 2, 1), (1, 4, 1), (2, 0, 0), (4, 0, 0)} <= shapes
+    # n = 30: 32 slots, the one- and two-waves-per-SIMD builds
+    assert {(1, 1, 1), (1, 1, 2), (1, 2, 1), (1, 2, 2), (1, 4, 1), (1, 4, 2), (2, 0, 0), (4, 0, 0)} <= shapes
     assert t["best_ms"] == min(ms for _, _, _, ms in t["candidates"])
     assert (t["waves_per_replica"], t["waves_per_block"], t["occupancy"]) in shapes
     again = mda.autotune(q, p, probe_steps=500)
