@@ -140,6 +140,26 @@ def test_plain_form_equals_persistent(mda):
         assert np.array_equal(ea.e1, eb.e1) and np.array_equal(ea.xbits, eb.xbits)
 
 
+@pytest.mark.parametrize("path,accept,general", [(1, 0, False), (1, 1, False), (2, 0, False), (2, 1, False),
+                                                   (2, 0, True), (2, 1, True)])
+def test_plain_form_every_step_variant(mda, path, accept, general):
+    """The plain form's step kernel is built per step variant (update path x
+    acceptance rule; the general Kronecker column for non-symmetric factors):
+    each build against the oracle, every replica, trajectory included."""
+    n = 9
+    if general:
+        rng = np.random.default_rng(90 + accept)
+        F1 = rng.integers(0, 60, size=(n, n)).astype(np.int32)
+        F2 = rng.integers(0, 60, size=(n, n)).astype(np.int32)
+        D = rng.integers(0, 90, size=(n, n)).astype(np.int32)
+        inst = synth.Instance(n, F1, F2, D, 0.0, 0)
+    else:
+        inst = synth.make_instance(n, 0.4, seed=90 + accept)
+    q, run, _ = _check_all(mda, inst, 4, 1500, 13 + accept, path=path, accept=accept,
+                           variant=mda.VARIANT_PLAIN)
+    assert q.info().symmetric == (0 if general else 1)
+
+
 def test_launch_shape_invariance(mda):
     inst = synth.make_instance(10, 0.5, seed=6)
     outs = []
