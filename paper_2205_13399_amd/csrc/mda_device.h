@@ -259,10 +259,11 @@ struct Replica {
     int64_t E1, E2, Eoff;
     int64_t moves, scanned, rngb, detailed;
     int32_t asize;
-    // per group of 8 slots, the lane's least combined difference (max of the
-    // two for the strict rule, min for the lenient one); it only changes when
-    // the fields do, so it is recomputed after a move or restart only
-    FT gmin[NS / 8];
+    // per group of 8 slots (the last one holds 4 when NS is 4 mod 8), the
+    // lane's least combined difference (max of the two for the strict rule,
+    // min for the lenient one); it only changes when the fields do, so it is
+    // recomputed after a move or restart only
+    FT gmin[(NS + 7) / 8];
 };
 
 // Update paths (template argument PV): dense rows of P_k, or the Kronecker

@@ -72,7 +72,7 @@ __device__ __forceinline__ void flip(Desc *Dp, int n_, Replica<NS, FT> &S, int j
             asm volatile("" : "+v"(r1), "+v"(r2));
             uint32_t t1[8], t2[8];
 #pragma unroll
-            for (int f = 0; f < 8; ++f) {
+            for (int f = 0; f < 8 && g + f < NS; ++f) {
                 const int i = g + f;
                 t1[f] = (i < n) ? (uint32_t)r1[i * n + ul] : 0u;
                 t2[f] = (i < n) ? (uint32_t)r2[i * n + ul] : 0u;
@@ -80,7 +80,7 @@ __device__ __forceinline__ void flip(Desc *Dp, int n_, Replica<NS, FT> &S, int j
                 t2[f] = live ? t2[f] : 0u;
             }
 #pragma unroll
-            for (int f = 0; f < 8; ++f) {
+            for (int f = 0; f < 8 && g + f < NS; ++f) {
                 const int i = g + f;
                 const UT b = (UT)((xmx >> i) & 1ull);
                 const UT m = (UT)0 - b;
@@ -187,7 +187,7 @@ __device__ __forceinline__ void fields_from_scratch(Desc *Dp, Replica<NS, FT> &S
             for (int g = 0; g < NS; g += 8) {
                 asm volatile("" : "+v"(r1), "+v"(r2));
 #pragma unroll
-                for (int f = 0; f < 8; ++f) {
+                for (int f = 0; f < 8 && g + f < NS; ++f) {
                     const int i = g + f;
                     const UT v1 = (i < n) ? (UT)(FT)r1[i * n + ul] : (UT)0;
                     const UT v2 = (i < n) ? (UT)(FT)r2[i * n + ul] : (UT)0;
@@ -392,7 +392,7 @@ __device__ __forceinline__ void group_minima(Replica<NS, FT> &S)
     for (int g = 0; g < NS; g += 8) {
         FT gm = Wide<FT>::kMax;
 #pragma unroll
-        for (int f = 0; f < 8; ++f)
+        for (int f = 0; f < 8 && g + f < NS; ++f)
             gm = min(gm, AM == kAmStrict ? max(S.e1[g + f], S.e2[g + f]) : min(S.e1[g + f], S.e2[g + f]));
         S.gmin[g >> 3] = gm;
     }
@@ -405,7 +405,7 @@ __device__ __forceinline__ FT wave_least(const Replica<NS, FT> &S)
 {
     FT mn = Wide<FT>::kMax;
 #pragma unroll
-    for (int g = 0; g < NS / 8; ++g) mn = min(mn, S.gmin[g]);
+    for (int g = 0; g < (NS + 7) / 8; ++g) mn = min(mn, S.gmin[g]);
     if (sizeof(FT) == 4) return (FT)wave_min_dpp((int)mn);
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) {
@@ -439,7 +439,7 @@ __device__ __forceinline__ int anneal_step(Desc *Dp, const Hot &H, Replica<NS, F
     const FT *gmin = S.gmin;
     FT mn = Wide<FT>::kMax;
 #pragma unroll
-    for (int g = 0; g < NS / 8; ++g) mn = min(mn, gmin[g]);
+    for (int g = 0; g < (NS + 7) / 8; ++g) mn = min(mn, gmin[g]);
     const uint64_t cand = __ballot(mn <= X) & actmask;
 
     int j = -1;
@@ -463,7 +463,7 @@ __device__ __forceinline__ int anneal_step(Desc *Dp, const Hot &H, Replica<NS, F
                 const uint32_t slots = (ng - g >= 8) ? 0xFFu : ((1u << (ng - g)) - 1u);
                 uint32_t certain = 0, maybe = 0;
 #pragma unroll
-                for (int f = 0; f < 8; ++f) {
+                for (int f = 0; f < 8 && g + f < NS; ++f) {
                     const int i = g + f;
                     // the statistic S is 0 exactly when the combined difference is at
                     // most the offset, and above every threshold when it exceeds X
@@ -491,7 +491,7 @@ __device__ __forceinline__ int anneal_step(Desc *Dp, const Hot &H, Replica<NS, F
                         Lv[f] = (uint32_t)lnt[(w >> (16 * (f & 1))) & 0xFFFu];
                     }
 #pragma unroll
-                    for (int f = 0; f < 8; ++f) {
+                    for (int f = 0; f < 8 && g + f < NS; ++f) {
                         const int i = g + f;
                         // u_k = max(0, dE_k - E_offset) < 2^31 for a real int32 bit, so
                         // the strict sum stays below 2^32
@@ -518,7 +518,7 @@ __device__ __forceinline__ int anneal_step(Desc *Dp, const Hot &H, Replica<NS, F
         // word in 10-bit fields, at most 512 each), then per slot of the
         // chosen group (four per word in 8-bit fields, at most 64 each), then
         // the lane: the (slot, lane) of the k-th accepted bit, slot-major.
-        constexpr int NG = NS / 8;
+        constexpr int NG = (NS + 7) / 8;
         int gtot[NG];
 #pragma unroll
         for (int w = 0; w < NG; w += 3) {
