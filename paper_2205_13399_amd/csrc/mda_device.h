@@ -252,6 +252,11 @@ __device__ __forceinline__ int64_t rlf(int64_t v, int lane)
     return (int64_t)rl64((uint64_t)v, lane);
 }
 
+// Slots in the group of 8 that starts at slot g: 8, or fewer in the last
+// group when NS is not a multiple of 8 (for a multiple of 8 the condition
+// folds away and the loops compile exactly as with the plain bound).
+#define MDA_GROUP_SLOTS(NS, g) (((NS) % 8 == 0) ? 8 : ((NS) - (g) < 8 ? (NS) - (g) : 8))
+
 template <int NS, class FT = int32_t>
 struct Replica {
     FT e1[NS], e2[NS];        // dE_k of bit (slot i, this lane)

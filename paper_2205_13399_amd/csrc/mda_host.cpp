@@ -887,6 +887,18 @@ int group_variant(const RunDesc &d)
 void plan_work(const std::vector<RunDesc> &descs, std::vector<WorkItem> &work, std::vector<Group> &groups)
 {
     const int count = (int)descs.size();
+    // The 52-slot tile pays only on its own: beside runs of 53 to 56
+    // facilities of the same variant it would split their launch in two
+    // (a longer tail), so runs of 49 to 52 facilities then join the 56-slot
+    // launch (the kernels read no tile size from the descriptor).
+    bool has56[2][kStepVariants] = {};
+    for (const RunDesc &d : descs)
+        if (d.wr * d.wc == 1 && d.gns == 56) has56[d.f64 ? 1 : 0][group_variant(d)] = true;
+    std::vector<int> tile(count);
+    for (int i = 0; i < count; ++i) {
+        const RunDesc &d = descs[i];
+        tile[i] = (d.wr * d.wc == 1 && d.gns == 52 && has56[d.f64 ? 1 : 0][group_variant(d)]) ? 56 : d.gns;
+    }
     std::vector<int> order(count);
     for (int i = 0; i < count; ++i) order[i] = i;
     std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
@@ -894,7 +906,7 @@ void plan_work(const std::vector<RunDesc> &descs, std::vector<WorkItem> &work, s
         if (x.wr * x.wc != y.wr * y.wc) return x.wr * x.wc > y.wr * y.wc;
         if (x.wc != y.wc) return x.wc > y.wc;
         if (x.f64 != y.f64) return x.f64 > y.f64;
-        if (x.gns != y.gns) return x.gns > y.gns;
+        if (tile[a] != tile[b]) return tile[a] > tile[b];
         if (group_variant(x) != group_variant(y)) return group_variant(x) < group_variant(y);
         return (int64_t)x.m * x.steps > (int64_t)y.m * y.steps;
     });
@@ -903,9 +915,9 @@ void plan_work(const std::vector<RunDesc> &descs, std::vector<WorkItem> &work, s
     for (int i : order) {
         const RunDesc &d = descs[i];
         const int sv = group_variant(d);
-        if (groups.empty() || groups.back().ns != d.gns || groups.back().wr != d.wr || groups.back().wc != d.wc ||
+        if (groups.empty() || groups.back().ns != tile[i] || groups.back().wr != d.wr || groups.back().wc != d.wc ||
             groups.back().f64 != d.f64 || groups.back().sv != sv)
-            groups.push_back(Group{d.gns, d.wr, d.wc, d.f64, sv, (int)work.size(), 0});
+            groups.push_back(Group{tile[i], d.wr, d.wc, d.f64, sv, (int)work.size(), 0});
         for (int rr = 0; rr < d.R; ++rr) work.push_back(WorkItem{i, rr});
         groups.back().cnt += d.R;
     }

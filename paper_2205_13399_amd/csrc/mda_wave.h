@@ -72,7 +72,7 @@ __device__ __forceinline__ void flip(Desc *Dp, int n_, Replica<NS, FT> &S, int j
             asm volatile("" : "+v"(r1), "+v"(r2));
             uint32_t t1[8], t2[8];
 #pragma unroll
-            for (int f = 0; f < 8 && g + f < NS; ++f) {
+            for (int f = 0; f < MDA_GROUP_SLOTS(NS, g); ++f) {
                 const int i = g + f;
                 t1[f] = (i < n) ? (uint32_t)r1[i * n + ul] : 0u;
                 t2[f] = (i < n) ? (uint32_t)r2[i * n + ul] : 0u;
@@ -80,7 +80,7 @@ __device__ __forceinline__ void flip(Desc *Dp, int n_, Replica<NS, FT> &S, int j
                 t2[f] = live ? t2[f] : 0u;
             }
 #pragma unroll
-            for (int f = 0; f < 8 && g + f < NS; ++f) {
+            for (int f = 0; f < MDA_GROUP_SLOTS(NS, g); ++f) {
                 const int i = g + f;
                 const UT b = (UT)((xmx >> i) & 1ull);
                 const UT m = (UT)0 - b;
@@ -187,7 +187,7 @@ __device__ __forceinline__ void fields_from_scratch(Desc *Dp, Replica<NS, FT> &S
             for (int g = 0; g < NS; g += 8) {
                 asm volatile("" : "+v"(r1), "+v"(r2));
 #pragma unroll
-                for (int f = 0; f < 8 && g + f < NS; ++f) {
+                for (int f = 0; f < MDA_GROUP_SLOTS(NS, g); ++f) {
                     const int i = g + f;
                     const UT v1 = (i < n) ? (UT)(FT)r1[i * n + ul] : (UT)0;
                     const UT v2 = (i < n) ? (UT)(FT)r2[i * n + ul] : (UT)0;
@@ -392,7 +392,7 @@ __device__ __forceinline__ void group_minima(Replica<NS, FT> &S)
     for (int g = 0; g < NS; g += 8) {
         FT gm = Wide<FT>::kMax;
 #pragma unroll
-        for (int f = 0; f < 8 && g + f < NS; ++f)
+        for (int f = 0; f < MDA_GROUP_SLOTS(NS, g); ++f)
             gm = min(gm, AM == kAmStrict ? max(S.e1[g + f], S.e2[g + f]) : min(S.e1[g + f], S.e2[g + f]));
         S.gmin[g >> 3] = gm;
     }
@@ -463,7 +463,7 @@ __device__ __forceinline__ int anneal_step(Desc *Dp, const Hot &H, Replica<NS, F
                 const uint32_t slots = (ng - g >= 8) ? 0xFFu : ((1u << (ng - g)) - 1u);
                 uint32_t certain = 0, maybe = 0;
 #pragma unroll
-                for (int f = 0; f < 8 && g + f < NS; ++f) {
+                for (int f = 0; f < MDA_GROUP_SLOTS(NS, g); ++f) {
                     const int i = g + f;
                     // the statistic S is 0 exactly when the combined difference is at
                     // most the offset, and above every threshold when it exceeds X
@@ -491,7 +491,7 @@ __device__ __forceinline__ int anneal_step(Desc *Dp, const Hot &H, Replica<NS, F
                         Lv[f] = (uint32_t)lnt[(w >> (16 * (f & 1))) & 0xFFFu];
                     }
 #pragma unroll
-                    for (int f = 0; f < 8 && g + f < NS; ++f) {
+                    for (int f = 0; f < MDA_GROUP_SLOTS(NS, g); ++f) {
                         const int i = g + f;
                         // u_k = max(0, dE_k - E_offset) < 2^31 for a real int32 bit, so
                         // the strict sum stays below 2^32

@@ -84,6 +84,25 @@ def test_final_temperature_thresholds(mda, n, path, accept, archive, escape):
         compare_replica(run, res[r], r, label="n=%d path=%d xi=0.02" % (n, path))
 
 
+@pytest.mark.parametrize("n,path,accept,general", [
+    (49, 1, 0, False), (52, 2, 1, False), (51, 2, 0, True), (52, 1, 1, True), (53, 2, 0, False)])
+def test_slot_tile_of_52(mda, n, path, accept, general):
+    """49 to 52 facilities run on 52 register slots, whose last group of 8
+    holds 4 (53 goes to 56): dense and Kronecker columns, both rules, the
+    two-product column on non-symmetric operands; every replica against the
+    oracle, full trajectories."""
+    if general:
+        rng = np.random.default_rng(n)
+        F1, F2 = (rng.integers(0, 40, size=(n, n)).astype(np.int32) for _ in range(2))
+        D = rng.integers(0, 60, size=(n, n)).astype(np.int32)
+        inst = synth.Instance(n, F1, F2, D, 0.0, 0)
+    else:
+        inst = synth.make_instance(n, 0.4, seed=520 + n)
+    q, run, _ = _check_all(mda, inst, 3, 2000, 52 + n, path=path, accept=accept)
+    assert mda.run_layout(q, mda.make_params(3, 2000, 52 + n)).gns == (52 if n <= 52 else 56)
+    assert q.info().symmetric == (0 if general else 1)
+
+
 @pytest.mark.parametrize("n", [4, 7, 9])
 def test_general_kronecker_nonsymmetric(mda, n):
     """Non-symmetric flows and distances with non-zero diagonals (two-product column)."""
@@ -185,6 +204,27 @@ def test_batch_equals_single(mda):
         res = run_replicas(inst.F1, inst.F2, inst.D, range(3 + k), **okw)
         for r in range(3 + k):
             compare_replica(run, res[r], r, label="batch %d" % k)
+
+
+def test_tile_52_joins_56_in_a_batch(mda):
+    """Beside a run of 54 facilities with the same variant, a run of 50 goes
+    on 56 slots instead of 52 (one launch, not two); alone it keeps 52.  All
+    replicas of both, and of the lone run, against the oracle."""
+    insts = [synth.make_instance(n, 0.1, seed=60 + n) for n in (50, 54)]
+    steps = 1500
+    qs = [mda.Qubo(i.F1, i.F2, i.D, path=2) for i in insts]
+    ps = [mda.make_params(3, steps, 2000 + k, trace_replicas=3) for k in range(2)]
+    runs = mda.da_run_batch(qs, ps)
+    alone = mda.da_run(qs[0], ps[0])
+    alone.sync()
+    for k, (inst, run) in enumerate(zip(insts, runs)):
+        run.sync()
+        okw = oracle_kwargs(oracle.Qubo(inst.F1, inst.F2, inst.D), steps, 2000 + k)
+        res = run_replicas(inst.F1, inst.F2, inst.D, range(3), **okw)
+        for r in range(3):
+            compare_replica(run, res[r], r, label="batch n=%d" % inst.n)
+            if k == 0:
+                compare_replica(alone, res[r], r, label="alone n=50")
 
 
 def test_merged_archive(mda):
