@@ -192,8 +192,10 @@ int da_run(const mda_qubo *q, const mda_params *p, mda_run **out);
 /*
  * Runs several independent MDA runs (instances of any size, each with its own
  * parameters and seed) together on ps[0].stream: the replicas of all runs form
- * one work list, grouped by register tile (slots per lane, 8 * ceil(n / 8)),
- * and each group is one persistent launch; with ps[0].graph the launches are
+ * one work list, grouped by register tile (slots per lane: 8 * ceil(n / 8),
+ * or 52 for n of 49 to 52 unless the batch holds runs of 53 to 56 with the
+ * same step variant, which they then join), and each group is one persistent
+ * launch; with ps[0].graph the launches are
  * one HIP graph.  Each result is identical to the corresponding da_run.  outs
  * receives one handle per run.  All runs share the stream, variant and graph
  * setting.
