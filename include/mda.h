@@ -171,7 +171,7 @@ typedef struct {
                                  NULL: the geometric schedule */
     int32_t occupancy;        /* one-wave form, int32 differences: 0 = automatic (the build holding two waves
                                  per SIMD when a launch has more replicas than one wave per SIMD holds at
-                                 once); 1 or 2: that build (2 exists from 32 register slots, i.e. n > 24;
+                                 once); 1 or 2: that build (2 exists from 32 register slots, i.e. n > 28;
                                  smaller tiles take 1).  In a batch the first block's value applies.
                                  Results do not depend on it */
 } mda_params;
@@ -193,8 +193,9 @@ int da_run(const mda_qubo *q, const mda_params *p, mda_run **out);
  * Runs several independent MDA runs (instances of any size, each with its own
  * parameters and seed) together on ps[0].stream: the replicas of all runs form
  * one work list, grouped by register tile (slots per lane: 8 * ceil(n / 8),
- * or 52 for n of 49 to 52 unless the batch holds runs of 53 to 56 with the
- * same step variant, which they then join), and each group is one persistent
+ * or 28 for n of 25 to 28 and 52 for n of 49 to 52 unless the batch holds
+ * runs of 29 to 32, or 53 to 56, with the same step variant, which they then
+ * join), and each group is one persistent
  * launch; with ps[0].graph the launches are
  * one HIP graph.  Each result is identical to the corresponding da_run.  outs
  * receives one handle per run.  All runs share the stream, variant and graph

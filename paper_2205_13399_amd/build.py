@@ -14,8 +14,8 @@ LIB = os.path.join(HERE, "libmda.so")
 BUILD_DIR = os.path.join(HERE, "_build")
 
 SOURCES = (["mda_wave_ns%d.hip" % t for t in (64, 56, 52, 48, 40)] + ["mda_group_ns%d.hip" % t for t in (64, 56, 48, 40)]
-           + ["mda_wave_ns%d.hip" % t for t in (32, 24, 16, 8)] + ["mda_group_ns%d.hip" % t for t in (32, 24, 16, 8)]
-           + ["mda_wave64_ns%d.hip" % t for t in (64, 56, 52, 48, 40, 32, 24, 16, 8)]
+           + ["mda_wave_ns%d.hip" % t for t in (32, 28, 24, 16, 8)] + ["mda_group_ns%d.hip" % t for t in (32, 24, 16, 8)]
+           + ["mda_wave64_ns%d.hip" % t for t in (64, 56, 52, 48, 40, 32, 28, 24, 16, 8)]
            + ["mda_generic_k%d.hip" % k for k in (4, 3, 2, 1)] + ["mda_generic_host.cpp"]
            + ["mda_kernels.hip", "mda_group.hip", "mda_front.hip", "mda_host.cpp", "mda_server.cpp"])
 

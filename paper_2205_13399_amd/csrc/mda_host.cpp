@@ -887,17 +887,19 @@ int group_variant(const RunDesc &d)
 void plan_work(const std::vector<RunDesc> &descs, std::vector<WorkItem> &work, std::vector<Group> &groups)
 {
     const int count = (int)descs.size();
-    // The 52-slot tile pays only on its own: beside runs of 53 to 56
-    // facilities of the same variant it would split their launch in two
-    // (a longer tail), so runs of 49 to 52 facilities then join the 56-slot
-    // launch (the kernels read no tile size from the descriptor).
-    bool has56[2][kStepVariants] = {};
+    // The 28- and 52-slot tiles pay only on their own: beside runs of 29 to
+    // 32 (53 to 56) facilities of the same variant they would split that
+    // launch in two (a longer tail), so runs of 25 to 28 (49 to 52)
+    // facilities then join the 32-slot (56-slot) launch (the kernels read no
+    // tile size from the descriptor).
+    bool full[2][kStepVariants][2] = {};
     for (const RunDesc &d : descs)
-        if (d.wr * d.wc == 1 && d.gns == 56) has56[d.f64 ? 1 : 0][group_variant(d)] = true;
+        if (d.wr * d.wc == 1 && (d.gns == 32 || d.gns == 56)) full[d.f64 ? 1 : 0][group_variant(d)][d.gns == 56] = true;
     std::vector<int> tile(count);
     for (int i = 0; i < count; ++i) {
         const RunDesc &d = descs[i];
-        tile[i] = (d.wr * d.wc == 1 && d.gns == 52 && has56[d.f64 ? 1 : 0][group_variant(d)]) ? 56 : d.gns;
+        const bool half = d.wr * d.wc == 1 && (d.gns == 28 || d.gns == 52);
+        tile[i] = (half && full[d.f64 ? 1 : 0][group_variant(d)][d.gns == 52]) ? d.gns + 4 : d.gns;
     }
     std::vector<int> order(count);
     for (int i = 0; i < count; ++i) order[i] = i;

@@ -116,16 +116,16 @@ __global__ void k_build_dense(int n, int ld, const int32_t *__restrict__ F, cons
 
 // ---------------------------------------------------------------- host launchers
 
-#define MDA_NS_LIST(X) X(8) X(16) X(24) X(32) X(40) X(48) X(52) X(56) X(64)
+#define MDA_NS_LIST(X) X(8) X(16) X(24) X(28) X(32) X(40) X(48) X(52) X(56) X(64)
 
 
 // Register slots of the one-wave kernels for n facilities: the next multiple
-// of 8, except 52 for 49 to 52 facilities (four slots fewer of registers and
-// of per-step work than 56).
+// of 8, except 28 for 25 to 28 and 52 for 49 to 52 facilities (four slots
+// fewer of registers and of per-step work than 32 and 56).
 int ns_for(int n)
 {
     const int ns = ((n + 7) / 8) * 8;
-    if (ns == 56 && n <= 52) return 52;
+    if ((ns == 32 || ns == 56) && n <= ns - 4) return ns - 4;
     return ns < 8 ? 8 : ns;
 }
 

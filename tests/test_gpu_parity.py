@@ -85,12 +85,13 @@ def test_final_temperature_thresholds(mda, n, path, accept, archive, escape):
 
 
 @pytest.mark.parametrize("n,path,accept,general", [
-    (49, 1, 0, False), (52, 2, 1, False), (51, 2, 0, True), (52, 1, 1, True), (53, 2, 0, False)])
-def test_slot_tile_of_52(mda, n, path, accept, general):
-    """49 to 52 facilities run on 52 register slots, whose last group of 8
-    holds 4 (53 goes to 56): dense and Kronecker columns, both rules, the
-    two-product column on non-symmetric operands; every replica against the
-    oracle, full trajectories."""
+    (49, 1, 0, False), (52, 2, 1, False), (51, 2, 0, True), (52, 1, 1, True), (53, 2, 0, False),
+    (25, 2, 0, False), (28, 1, 1, False), (27, 2, 1, True), (29, 2, 0, False)])
+def test_half_group_slot_tiles(mda, n, path, accept, general):
+    """25 to 28 and 49 to 52 facilities run on 28 and 52 register slots,
+    whose last group of 8 holds 4 (29 and 53 go to 32 and 56): dense and
+    Kronecker columns, both rules, the two-product column on non-symmetric
+    operands; every replica against the oracle, full trajectories."""
     if general:
         rng = np.random.default_rng(n)
         F1, F2 = (rng.integers(0, 40, size=(n, n)).astype(np.int32) for _ in range(2))
@@ -99,7 +100,8 @@ def test_slot_tile_of_52(mda, n, path, accept, general):
     else:
         inst = synth.make_instance(n, 0.4, seed=520 + n)
     q, run, _ = _check_all(mda, inst, 3, 2000, 52 + n, path=path, accept=accept)
-    assert mda.run_layout(q, mda.make_params(3, 2000, 52 + n)).gns == (52 if n <= 52 else 56)
+    want = {25: 28, 27: 28, 28: 28, 29: 32, 53: 56}.get(n, 52)
+    assert mda.run_layout(q, mda.make_params(3, 2000, 52 + n)).gns == want
     assert q.info().symmetric == (0 if general else 1)
 
 
@@ -206,11 +208,13 @@ def test_batch_equals_single(mda):
             compare_replica(run, res[r], r, label="batch %d" % k)
 
 
-def test_tile_52_joins_56_in_a_batch(mda):
-    """Beside a run of 54 facilities with the same variant, a run of 50 goes
-    on 56 slots instead of 52 (one launch, not two); alone it keeps 52.  All
-    replicas of both, and of the lone run, against the oracle."""
-    insts = [synth.make_instance(n, 0.1, seed=60 + n) for n in (50, 54)]
+@pytest.mark.parametrize("pair", [(50, 54), (26, 31)])
+def test_half_tile_joins_full_tile_in_a_batch(mda, pair):
+    """Beside a run of 54 (31) facilities with the same variant, a run of 50
+    (26) goes on 56 (32) slots instead of 52 (28): one launch, not two; alone
+    it keeps the smaller tile.  All replicas of both, and of the lone run,
+    against the oracle."""
+    insts = [synth.make_instance(n, 0.1, seed=60 + n) for n in pair]
     steps = 1500
     qs = [mda.Qubo(i.F1, i.F2, i.D, path=2) for i in insts]
     ps = [mda.make_params(3, steps, 2000 + k, trace_replicas=3) for k in range(2)]
@@ -224,7 +228,7 @@ def test_tile_52_joins_56_in_a_batch(mda):
         for r in range(3):
             compare_replica(run, res[r], r, label="batch n=%d" % inst.n)
             if k == 0:
-                compare_replica(alone, res[r], r, label="alone n=50")
+                compare_replica(alone, res[r], r, label="alone n=%d" % inst.n)
 
 
 def test_merged_archive(mda):
